@@ -1,0 +1,129 @@
+"""Pins for oracle.binning (projection, tile rectangles, depth keys, order)."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from oracle import binning, render
+
+
+def _single(mean, scale, quat=(1, 0, 0, 0), omega=(0, 0, 0), vel=(0, 0, 0), acc=(0, 0, 0)):
+    f = lambda x, n: np.asarray(x, np.float32).reshape(n, 1)
+    return scenes.Gaussians(mean=f(mean, 3), vel=f(vel, 3), acc=f(acc, 3), scale=f(scale, 3),
+                            quat=f(quat, 4), omega=f(omega, 3),
+                            opacity_logit=np.zeros(1, np.float32),
+                            rgb=np.full((3, 1), 0.5, np.float32), albedo=np.ones(1, np.float32))
+
+
+def test_axis_aligned_on_optical_axis_closed_form():
+    # On the optical axis the Jacobian's third column vanishes, so
+    # Sigma' = diag(fx^2 sx^2 / z^2, fy^2 sy^2 / z^2) + dilation I exactly.
+    z, sx, sy, sz = 2.0, 0.05, 0.02, 0.3
+    g = _single((0, 0, z), (sx, sy, sz))
+    cfg = scenes.RenderConfig(width=64, height=48)
+    fr = scenes.Frame(fx=60.0, fy=55.0, cx=32.0, cy=24.0)
+    p = binning.project(g, fr, cfg)
+    sx32, sy32 = float(np.float32(sx)), float(np.float32(sy))
+    s00 = 60.0 ** 2 * sx32 ** 2 / z ** 2 + float(np.float32(0.3))
+    s11 = 55.0 ** 2 * sy32 ** 2 / z ** 2 + float(np.float32(0.3))
+    assert p["S00"][0] == pytest.approx(s00, rel=1e-14)
+    assert p["S11"][0] == pytest.approx(s11, rel=1e-14)
+    assert p["S01"][0] == 0.0
+    assert (p["u"][0], p["v"][0]) == (32.0, 24.0)
+    r = math.ceil(3.0 * math.sqrt(max(s00, s11)))
+    assert p["radius"][0] == r
+    # rect by hand: tiles of 16 px
+    assert list(p["rect"][:, 0]) == [max(0, (32 - r) // 16), min(3, (32 + r) // 16),
+                                     max(0, (24 - r) // 16), min(2, (24 + r) // 16)]
+    assert p["key"][0] == np.float32(z).view(np.uint32)
+
+
+def test_rotation_about_z_closed_form():
+    # q0 = identity, omega = (0, 0, w): q(t) = (1, 0, 0, w t / 2), a rotation by
+    # theta = 2 atan(w t / 2) about z.  On the optical axis the 2D covariance is
+    # then (f/z)^2 R2 diag(sx^2, sy^2) R2^T + dilation.
+    w, t, z, sx, sy = 3.0, 0.25, 2.5, 0.06, 0.02
+    g = _single((0, 0, z), (sx, sy, 0.01), omega=(0, 0, w))
+    cfg = scenes.RenderConfig(width=64, height=48, dilation=0.0)
+    fr = scenes.Frame(fx=60.0, fy=60.0, cx=32.0, cy=24.0, time=t)
+    p = binning.project(g, fr, cfg)
+    th = 2.0 * math.atan(w * t / 2.0)
+    c, s = math.cos(th), math.sin(th)
+    sx, sy = float(np.float32(sx)), float(np.float32(sy))
+    k = (60.0 / z) ** 2
+    assert p["S00"][0] == pytest.approx(k * (c * c * sx * sx + s * s * sy * sy), rel=1e-12)
+    assert p["S11"][0] == pytest.approx(k * (s * s * sx * sx + c * c * sy * sy), rel=1e-12)
+    assert p["S01"][0] == pytest.approx(k * c * s * (sx * sx - sy * sy), rel=1e-12)
+
+
+def test_trajectory_closed_form():
+    g = _single((0.1, -0.2, 2.0), (0.01, 0.01, 0.01), vel=(0.5, 0.25, -1.0), acc=(2.0, 0.0, 4.0))
+    cfg = scenes.RenderConfig(width=64, height=48)
+    t = np.float32(0.125)
+    fr = scenes.Frame(time=float(t))
+    p = binning.project(g, fr, cfg)
+    t = float(t)
+    x = float(np.float32(0.1)) + 0.5 * t + 1.0 * t * t
+    z = 2.0 - 1.0 * t + 2.0 * t * t
+    assert p["px"][0] == pytest.approx(x, rel=1e-15)
+    assert p["pz"][0] == pytest.approx(z, rel=1e-15)
+
+
+def test_culling():
+    g = _single((0, 0, 0.1), (0.01, 0.01, 0.01))           # behind the near plane
+    cfg = scenes.RenderConfig(width=64, height=48)
+    assert not binning.project(g, scenes.Frame(), cfg)["valid"][0]
+    g = _single((10.0, 0, 1.0), (0.01, 0.01, 0.01))         # far outside the image
+    assert not binning.project(g, scenes.Frame(), cfg)["valid"][0]
+    g = _single((0, 0, 1.0), (0.01, 0.01, 0.01))
+    assert binning.project(g, scenes.Frame(), cfg)["valid"][0]
+
+
+def test_matches_differentiable_projection():
+    # Two independent formulations (pinned op order vs torch matrices).
+    wl = scenes.cfg3(n=3000, n_frames=3)
+    for fr in wl.frames:
+        p = binning.project(wl.gaussians, fr, wl.cfg)
+        q = render.gaussian_quantities(render.params_to_torch(wl.gaussians), fr, wl.cfg)
+        v = p["valid"]
+        det = p["S00"] * p["S11"] - p["S01"] ** 2
+        np.testing.assert_allclose(p["u"][v], q["u"].numpy()[v], rtol=1e-10)
+        np.testing.assert_allclose(p["v"][v], q["v"].numpy()[v], rtol=1e-10)
+        np.testing.assert_allclose((p["S11"] / det)[v], q["A"].numpy()[v], rtol=1e-8)
+        np.testing.assert_allclose((p["S00"] / det)[v], q["C"].numpy()[v], rtol=1e-8)
+
+
+@pytest.mark.parametrize("maker", [lambda: scenes.cfg1(),
+                                   lambda: scenes.cfg3(n=400, n_frames=3),
+                                   lambda: scenes.tiny_scene(40, 20, 13, seed=3)])
+def test_sorted_pairs_equal_python_sorted(maker):
+    wl = maker()
+    pairs = binning.sorted_pairs(wl.gaussians, wl.frames, wl.cfg)
+    ref = []
+    for f, fr in enumerate(wl.frames):
+        p = binning.project(wl.gaussians, fr, wl.cfg)
+        xl, xh, yl, yh = p["rect"]
+        for k in range(wl.gaussians.n):
+            if not p["valid"][k]:
+                continue
+            for ty in range(yl[k], yh[k] + 1):
+                for tx in range(xl[k], xh[k] + 1):
+                    ref.append((f, ty * wl.cfg.tiles_x + tx, int(p["key"][k]), k))
+    ref.sort()
+    got = list(zip(pairs["frame"].tolist(), pairs["tile"].tolist(), pairs["key"].tolist(),
+                   pairs["index"].tolist()))
+    assert got == ref
+    assert pairs["P"] == len(ref) > 0
+
+
+def test_scene_generation_deterministic():
+    a = scenes.cfg3(seed=7, n=500).gaussians
+    b = scenes.cfg3(seed=7, n=500).gaussians
+    c = scenes.cfg3(seed=8, n=500).gaussians
+    for k in scenes.Gaussians.FIELDS:
+        assert getattr(a, k).tobytes() == getattr(b, k).tobytes()
+        assert getattr(a, k).dtype == np.float32
+    assert a.mean.tobytes() != c.mean.tobytes()

@@ -1,0 +1,66 @@
+"""Pins for oracle.optim and for the paper's constants (tests/golden)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import optim, render
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.txt")
+
+
+def _golden():
+    out = {}
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        parts = line.split()
+        out[parts[0]] = parts[1:-1]
+    return out
+
+
+def test_adam_first_step_closed_form():
+    # After one bias-corrected step, m_hat = g and v_hat = g^2, so the update is
+    # -lr g / (|g| + eps) elementwise.
+    g = _golden()
+    b1, b2, eps = float(g["adam_beta1"][0]), float(g["adam_beta2"][0]), float(g["adam_eps"][0])
+    rng = np.random.default_rng(0)
+    p, gr = rng.normal(size=100), rng.normal(size=100) * 1e-3
+    lr = float(g["reflectivity_lr"][0])
+    p1, m, v = optim.adam_step(p, gr, np.zeros(100), np.zeros(100), 1, lr, b1, b2, eps)
+    np.testing.assert_allclose(p1 - p, -lr * gr / (np.abs(gr) + eps), rtol=1e-12)
+    # second step with the same gradient: still -lr sign(g) up to eps
+    p2, _, _ = optim.adam_step(p1, gr, m, v, 2, lr, b1, b2, eps)
+    np.testing.assert_allclose(p2 - p1, -lr * np.sign(gr), rtol=1e-9)
+
+
+def test_l2_loss_gradient_central_differences():
+    rng = np.random.default_rng(1)
+    pr, pq = rng.normal(size=(3, 5, 4)), rng.normal(size=(4, 5, 4))
+    tr, tq = rng.normal(size=pr.shape), rng.normal(size=pq.shape)
+    loss, dr, dq = optim.l2_loss_grad(pr, pq, tr, tq, quad_weight=5.0)
+    h = 1e-6
+    for arr, grad, which in ((pr, dr, 0), (pq, dq, 1)):
+        for idx in [(0, 0, 0), (2, 4, 3), (1, 2, 1)]:
+            a2 = arr.copy(); a2[idx] += h
+            args = (a2, pq) if which == 0 else (pr, a2)
+            lp = optim.l2_loss_grad(*args, tr, tq, 5.0)[0]
+            a2[idx] -= 2 * h
+            args = (a2, pq) if which == 0 else (pr, a2)
+            lm = optim.l2_loss_grad(*args, tr, tq, 5.0)[0]
+            assert (lp - lm) / (2 * h) == pytest.approx(grad[idx], rel=1e-6)
+
+
+def test_paper_constants():
+    g = _golden()
+    assert [float(eval(x.replace("pi", "*math.pi").lstrip("*") if "pi" in x else x))
+            if x != "pi" else math.pi for x in g["phase_offsets"]] == pytest.approx(scenes.QUAD_PHASES)
+    du = scenes.SPEED_OF_LIGHT / (2 * 30e6)
+    assert du == pytest.approx(float(g["unambiguous_range_m_at_30MHz"][0]), abs=1e-4)
+    assert render.C_LIGHT == scenes.SPEED_OF_LIGHT
+    # the paper's random background range and initial reflectivity
+    assert [float(x) for x in g["random_background_range"]] == [-1.0, 1.0]
+    gt, tr, _ = scenes.cfg5_scenes(n=10)
+    assert np.all(tr.albedo == np.float32(float(g["initial_reflectivity"][0])))
