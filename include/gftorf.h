@@ -1,0 +1,242 @@
+/*
+ * gftorf.h -- C ABI of the MI355X (gfx950) differentiable C-ToF Gaussian rasterizer.
+ *
+ * The library renders, for a batch of time frames of a dynamic scene of 3D
+ * Gaussians, the RGB image (paper §3, Eq. 2), the raw continuous-wave
+ * time-of-flight quad images (§3, Eq. 4) and the mean depth (§3.1, Eq. 5),
+ * and back-propagates upstream image gradients to every Gaussian parameter
+ * (supplement C, Eqs. S1-S3, plus the background term those equations omit).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array pointers are DEVICE pointers unless a comment says "host".
+ *   The caller owns every buffer; the library never allocates device memory
+ *   inside these calls and never synchronises the stream (except
+ *   gftorf_read_status), so fwd / bwd / loss / adam can be captured in a
+ *   HIP graph.
+ * - `stream` is a hipStream_t passed as void* (NULL = the legacy stream).
+ * - Return value: GFTORF_OK (0) or a negative error code.  On error nothing
+ *   has been enqueued, except for GFTORF_EHIP where a launch failed midway.
+ *   gftorf_last_error() returns a thread-local message for the last failure.
+ * - Parameter arrays are float32 structure-of-arrays: [3][n] means three
+ *   contiguous rows of n floats.
+ * - Images are float32 [F][C][H][W], row-major.
+ * - Camera convention: world -> camera p = R x + t (R row-major), OpenCV
+ *   axes (x right, y down, z forward); pixel (i, j) is sampled at
+ *   (i + 0.5, j + 0.5); u = fx X / Z + cx.  The light source is co-located
+ *   with the camera (paper §1 assumptions).
+ */
+#ifndef GFTORF_H
+#define GFTORF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GFTORF_OK 0
+#define GFTORF_EINVAL (-1)     /* bad argument (NULL, size, unsupported option)        */
+#define GFTORF_ENOWS (-2)      /* workspace smaller than gftorf_workspace_size()       */
+#define GFTORF_EHIP (-3)       /* a HIP runtime call failed                             */
+#define GFTORF_EOVERFLOW (-4)  /* read_status: pairs exceeded max_pairs in last fwd     */
+
+#define GFTORF_MAX_FREQ 4      /* modulation frequencies per call                       */
+#define GFTORF_MAX_PHASE 4     /* phase offsets per frequency                           */
+#define GFTORF_MAX_QUAD 16     /* GFTORF_MAX_FREQ * GFTORF_MAX_PHASE                    */
+
+/* Gaussian parameters (paper §3: centre, covariance from scale + rotation,
+ * opacity, colour, reflectivity).  The time dependence replaces the paper's
+ * deformation MLP (§4) by an analytic trajectory:
+ *   x(t) = mean + vel t + acc t^2 / 2,
+ *   q(t) = quat + (t / 2) (0, omega) (x) quat   (first-order constant rate),
+ * and the rotation is M(q) / |q|^2, so quaternions need not be unit length. */
+typedef struct gftorf_gaussians {
+    int64_t n;
+    const float* mean;          /* [3][n] m                                        */
+    const float* vel;           /* [3][n] m/s, or NULL (static)                    */
+    const float* acc;           /* [3][n] m/s^2, or NULL                           */
+    const float* scale;         /* [3][n] linear standard deviations, m            */
+    const float* quat;          /* [4][n] (w, x, y, z)                             */
+    const float* omega;         /* [3][n] rad/s, or NULL                           */
+    const float* opacity_logit; /* [n]   o = sigmoid(logit)                        */
+    const float* rgb;           /* [3][n] colour c_k (Eq. 2)                       */
+    const float* albedo;        /* [n]   reflectivity r_k (Eq. 3/4)                */
+} gftorf_gaussians;
+
+/* Gradient outputs, same layout as gftorf_gaussians.  Each non-NULL array is
+ * OVERWRITTEN (not accumulated).  A NULL entry is skipped. */
+typedef struct gftorf_gaussians_grad {
+    float* mean;
+    float* vel;
+    float* acc;
+    float* scale;
+    float* quat;
+    float* omega;
+    float* opacity_logit;
+    float* rgb;
+    float* albedo;
+} gftorf_gaussians_grad;
+
+/* One rendered frame; an ARRAY of these lives in DEVICE memory, so a graph
+ * replay can change times, poses and backgrounds between launches. */
+typedef struct gftorf_frame {
+    float R[9];                       /* world -> camera rotation, row-major      */
+    float t[3];                       /* world -> camera translation              */
+    float fx, fy, cx, cy;             /* pinhole intrinsics, pixels               */
+    float time;                       /* s, evaluates the Gaussian trajectories   */
+    float bg_rgb[3];                  /* c_bg (Eq. 2)                             */
+    float bg_quad[GFTORF_MAX_QUAD];   /* q_bg [n_freq][n_phase] (Eq. 4)           */
+} gftorf_frame;
+
+/* Per-call constants (host memory).  The paper states neither the rasterizer
+ * constants nor the tile shape; the defaults in the Python binding are
+ * alpha_min = 1/255, alpha_max = 0.99, T_min = 1e-4, extent_sigma = 3,
+ * dilation = 0.3 px^2, near_z = 0.2 m, source_intensity s = 1, bg_T_power 1. */
+typedef struct gftorf_config {
+    int32_t width, height;            /* image size, pixels (all frames)          */
+    int32_t n_freq;                   /* 1..GFTORF_MAX_FREQ                        */
+    int32_t n_phase;                  /* 1..GFTORF_MAX_PHASE                       */
+    double freq_hz[GFTORF_MAX_FREQ];  /* modulation frequencies f (Eq. 3)          */
+    float phase[GFTORF_MAX_PHASE];    /* quad offsets phi_j (paper §2)             */
+    int32_t tile_w, tile_h;           /* 8x8, 16x16 or 32x8                        */
+    float alpha_min;                  /* skip a Gaussian with alpha < alpha_min    */
+    float alpha_max;                  /* alpha = min(alpha_max, o G)               */
+    float T_min;                      /* stop before T (1 - alpha) < T_min         */
+    float extent_sigma;               /* support radius in std-devs; <= 0: all tiles */
+    float dilation;                   /* added to the 2D covariance diagonal, px^2 */
+    float near_z;                     /* cull p_z <= near_z, m                     */
+    float source_intensity;           /* s in s r_k / d_k^2 (Eq. 3/4)              */
+    int32_t bg_T_power;               /* 1: q_bg T_final (literal Eq. 4); 2: T^2   */
+    int64_t max_pairs;                /* capacity of the (tile, Gaussian) lists    */
+} gftorf_config;
+
+/* Forward outputs.  rgb [F][3][H][W], quad [F][n_freq*n_phase][H][W] (quad
+ * channel index = freq * n_phase + phase), depth [F][H][W]: each may be NULL
+ * (not written).  T_final [F][H][W] and n_contrib [F][H][W] are required:
+ * the backward pass reads them. */
+typedef struct gftorf_outputs {
+    float* rgb;
+    float* quad;
+    float* depth;
+    float* T_final;
+    int32_t* n_contrib;
+} gftorf_outputs;
+
+typedef struct gftorf_status {
+    int64_t n_pairs;     /* (tile, Gaussian) pairs of the last forward (may exceed max_pairs) */
+    int64_t max_pairs;   /* capacity the workspace was carved for                             */
+    int32_t overflow;    /* 1 if n_pairs > max_pairs: the last forward is INVALID              */
+    int32_t nonfinite;   /* Gaussians culled because an input was NaN / Inf                   */
+} gftorf_status;
+
+/* Bytes of workspace needed for n Gaussians, n_frames frames and cfg
+ * (including cfg->max_pairs).  Returns 0 if the arguments are invalid. */
+size_t gftorf_workspace_size(int64_t n, int32_t n_frames, const gftorf_config* cfg);
+
+/* Forward rendering of n_frames frames in one batched launch per stage
+ * (paper §3 Eqs. 2, 4, 5; every frame carries its own time, so raw quads
+ * of a dynamic scene can be rendered at the instants they were captured).
+ * Stages: per (frame, Gaussian) projection and binning -> depth sort ->
+ * (tile, Gaussian) pair emission in depth order -> stable sort by
+ * (frame, tile) -> per-tile ranges -> front-to-back compositing.
+ * The workspace `ws` keeps the sorted lists and per-Gaussian records that
+ * gftorf_render_bwd needs: pass the same ws, untouched, to the backward.
+ * If the pair count exceeds cfg->max_pairs the outputs are invalid and
+ * gftorf_read_status reports overflow. */
+int gftorf_render_fwd(const gftorf_gaussians* g, const gftorf_frame* frames, int32_t n_frames,
+                      const gftorf_config* cfg, const gftorf_outputs* out,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of gftorf_render_fwd (supplement C: Eq. S2 for RGB and depth,
+ * Eq. S3 for the quads, plus the background terms -c_bg T_final/(1-alpha_k)
+ * and -p q_bg T_final^p/(1-alpha_k)).  Upstream gradients d_rgb, d_quad,
+ * d_depth have the output layouts; NULL means zero.  `saved` must be the
+ * outputs of the forward that filled `ws`.  d_bg, if not NULL, receives
+ * dL/d(bg_rgb, bg_quad) as [n_frames][3 + n_freq*n_phase] (overwritten).
+ * Gradients are exact for the forward's discrete decisions (tile lists,
+ * order, skips, stops, clamp) held fixed; FP32 atomics make the result
+ * deterministic only up to summation order. */
+int gftorf_render_bwd(const gftorf_gaussians* g, const gftorf_frame* frames, int32_t n_frames,
+                      const gftorf_config* cfg, const gftorf_outputs* saved,
+                      const float* d_rgb, const float* d_quad, const float* d_depth,
+                      const gftorf_gaussians_grad* grad, float* d_bg,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronises `stream`, then copies the status of the last forward that
+ * used `ws` into *out (host).  Returns GFTORF_EOVERFLOW if it overflowed. */
+int gftorf_read_status(const void* ws, gftorf_status* out, void* stream);
+
+/* Introspection of the forward's binning, for tests and tools: copies
+ * (device to device, asynchronously on `stream`) from the workspace of the
+ * last forward with the same (n, n_frames, cfg):
+ *   pair_key / pair_item: the first min(n_pairs, pair_capacity) sorted pairs,
+ *     key = frame * n_tiles + tile (tile = ty * tiles_x + tx), item =
+ *     frame * n + gaussian, ascending (key, depth key, gaussian);
+ *   depth_key / depth_item: the M = n * n_frames items sorted by their depth
+ *     key (float32 bits of the camera-space z; 0xFFFFFFFF for culled items);
+ *   item_count: tiles covered per item (0 = culled), item order;
+ *   item_rect: [M][2] packed tile rectangles (x_lo | x_hi << 16,
+ *     y_lo | y_hi << 16), item order.
+ * Every destination may be NULL. */
+int gftorf_copy_lists(const void* ws, int64_t n, int32_t n_frames, const gftorf_config* cfg,
+                      uint32_t* pair_key, uint32_t* pair_item, int64_t pair_capacity,
+                      uint32_t* depth_key, uint32_t* depth_item, uint32_t* item_count,
+                      uint32_t* item_rect, void* stream);
+
+/* L2 loss (paper Eq. 9, L2 part): for f < n_frames, with target frame
+ * s = frame_index[f] (device int32 [n_frames], or NULL for s = f):
+ *   loss += weight * mean((pred[f] - targets[s])^2)   over all f and elements,
+ *   grad[f] = weight * 2 (pred[f] - targets[s]) / (n_frames * elems_per_frame).
+ * pred, grad: [n_frames][elems_per_frame]; targets: [*][elems_per_frame];
+ * loss: device float, ADDED to (clear it with gftorf_fill_f32). */
+int gftorf_l2_loss_grad(const float* pred, const float* targets, const int32_t* frame_index,
+                        int32_t n_frames, int64_t elems_per_frame, float weight,
+                        float* grad, float* loss, void* stream);
+
+/* One parameter group of gftorf_adam_step. */
+typedef struct gftorf_adam_group {
+    float* param;
+    const float* grad;
+    float* m;      /* first moment, same size, start at 0  */
+    float* v;      /* second moment, same size, start at 0 */
+    int64_t n;
+    float lr;
+} gftorf_adam_group;
+
+/* Adam (paper §4: beta = (0.9, 0.999), eps = 1e-15, per-group learning
+ * rates).  Increments the device step counter *step (int32) and applies the
+ * bias-corrected update with t = the new value.  groups: host array. */
+int gftorf_adam_step(const gftorf_adam_group* groups, int32_t n_groups, int32_t* step,
+                     float beta1, float beta2, float eps, void* stream);
+
+/* Selects a batch of frames of a sequence from the device step counter, for
+ * graph-replayed optimisation loops: with s = *step (read on the device),
+ * frame b of the batch is seq[(n_batch * s + b) mod n_seq], its backgrounds
+ * replaced by bg_table[(s mod n_bg)][b][0 .. 3 + n_quad) when bg_table is not
+ * NULL (the paper's per-iteration random background, §4), and
+ * frame_index[b] receives the sequence index.  All pointers are device. */
+int gftorf_select_frames(gftorf_frame* frames, int32_t n_batch, const gftorf_frame* seq,
+                         int32_t n_seq, const float* bg_table, int32_t n_bg, int32_t n_quad,
+                         const int32_t* step, int32_t* frame_index, void* stream);
+
+/* Fills n floats with `value` (a kernel, not a memset: safe in graphs). */
+int gftorf_fill_f32(float* p, float value, int64_t n, void* stream);
+
+/* Graph capture of everything the calling thread enqueues on `stream`
+ * between begin and end (hipStreamBeginCapture, thread-local mode).
+ * end instantiates the graph and returns an executable handle. */
+int gftorf_graph_begin(void* stream);
+int gftorf_graph_end(void* stream, void** graph_exec);
+int gftorf_graph_launch(void* graph_exec, void* stream);
+int gftorf_graph_destroy(void* graph_exec);
+
+const char* gftorf_strerror(int code);
+const char* gftorf_last_error(void);
+int gftorf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFTORF_H */

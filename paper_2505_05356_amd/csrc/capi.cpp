@@ -1,0 +1,305 @@
+// Host side of the C ABI declared in include/gftorf.h: argument validation,
+// workspace carving and the launch sequences of the forward and backward
+// passes.  Nothing here allocates device memory or synchronises, except
+// gftorf_read_status.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(GFTORF_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool tile_ok(int tw, int th) {
+    return (tw == 8 && th == 8) || (tw == 16 && th == 16) || (tw == 32 && th == 8);
+}
+
+int key_bits_for(int64_t keys) {
+    int b = 1;
+    while ((int64_t(1) << b) < keys) ++b;
+    return b;
+}
+
+int build_params(int64_t n, int32_t F, const gftorf_config* c, gft::Params* P) {
+    if (!c) return fail(GFTORF_EINVAL, "config is NULL");
+    if (n < 0) return fail(GFTORF_EINVAL, "n < 0");
+    if (F < 1) return fail(GFTORF_EINVAL, "n_frames must be >= 1");
+    if (c->width < 1 || c->height < 1 || c->width > 32768 || c->height > 32768)
+        return fail(GFTORF_EINVAL, "width/height out of range [1, 32768]");
+    if (c->n_freq < 1 || c->n_freq > GFTORF_MAX_FREQ) return fail(GFTORF_EINVAL, "n_freq out of range");
+    if (c->n_phase < 1 || c->n_phase > GFTORF_MAX_PHASE) return fail(GFTORF_EINVAL, "n_phase out of range");
+    if (!tile_ok(c->tile_w, c->tile_h)) return fail(GFTORF_EINVAL, "tile shape must be 8x8, 16x16 or 32x8");
+    if (!(c->alpha_max > 0.f && c->alpha_max < 1.f)) return fail(GFTORF_EINVAL, "alpha_max must be in (0, 1)");
+    if (!(c->alpha_min >= 0.f && c->alpha_min < c->alpha_max)) return fail(GFTORF_EINVAL, "alpha_min must be in [0, alpha_max)");
+    if (!(c->T_min >= 0.f && c->T_min < 1.f)) return fail(GFTORF_EINVAL, "T_min must be in [0, 1)");
+    if (!std::isfinite(c->extent_sigma) || !(c->dilation >= 0.f) || !std::isfinite(c->dilation) ||
+        !std::isfinite(c->near_z) || !std::isfinite(c->source_intensity))
+        return fail(GFTORF_EINVAL, "non-finite option");
+    if (c->bg_T_power != 1 && c->bg_T_power != 2) return fail(GFTORF_EINVAL, "bg_T_power must be 1 or 2");
+    if (c->max_pairs < 0 || c->max_pairs > (int64_t)0xF0000000ll)
+        return fail(GFTORF_EINVAL, "max_pairs out of range [0, 0xF0000000]");
+    for (int i = 0; i < c->n_freq; ++i)
+        if (!(c->freq_hz[i] > 0.0) || !std::isfinite(c->freq_hz[i])) return fail(GFTORF_EINVAL, "bad frequency");
+    const int64_t M = n * (int64_t)F;
+    if (M > (int64_t)0xFFFFFFFFll) return fail(GFTORF_EINVAL, "n * n_frames must be < 2^32");
+    gft::Params& p = *P;
+    std::memset(&p, 0, sizeof(p));
+    p.n = n;
+    p.F = F;
+    p.W = c->width;
+    p.H = c->height;
+    p.tw = c->tile_w;
+    p.th = c->tile_h;
+    p.ntx = (c->width + c->tile_w - 1) / c->tile_w;
+    p.nty = (c->height + c->tile_h - 1) / c->tile_h;
+    p.n_tiles = p.ntx * p.nty;
+    if ((int64_t)p.n_tiles * F > (int64_t)0x7FFFFFFF) return fail(GFTORF_EINVAL, "too many tiles");
+    p.nf = c->n_freq;
+    p.nphi = c->n_phase;
+    p.nq = p.nf * p.nphi;
+    for (int i = 0; i < p.nf; ++i) p.freq[i] = c->freq_hz[i];
+    for (int j = 0; j < p.nphi; ++j) {
+        p.cphi[j] = (float)std::cos((double)c->phase[j]);
+        p.sphi[j] = (float)std::sin((double)c->phase[j]);
+    }
+    p.alpha_min = c->alpha_min;
+    p.alpha_max = c->alpha_max;
+    p.T_min = c->T_min;
+    p.extent = c->extent_sigma;
+    p.dilation = c->dilation;
+    p.near_z = c->near_z;
+    p.s_int = c->source_intensity;
+    p.bg_pow = c->bg_T_power;
+    p.cap = (unsigned long long)c->max_pairs;
+    p.key_bits = key_bits_for((int64_t)F * p.n_tiles);
+    return GFTORF_OK;
+}
+
+int sorted_buffer(const gft::Params& P) {
+    const int passes = (P.key_bits + 7) / 8;
+    return passes & 1;
+}
+
+int check_gauss(const gftorf_gaussians* g) {
+    if (!g) return fail(GFTORF_EINVAL, "gaussians is NULL");
+    if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity_logit || !g->rgb || !g->albedo))
+        return fail(GFTORF_EINVAL, "required Gaussian array is NULL (mean, scale, quat, opacity_logit, rgb, albedo)");
+    return GFTORF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gftorf_workspace_size(int64_t n, int32_t n_frames, const gftorf_config* cfg) {
+    gft::Params P;
+    if (build_params(n, n_frames, cfg, &P) != GFTORF_OK) return 0;
+    return gft::carve(nullptr, n, n_frames, P.nf, P.n_tiles, P.cap).bytes;
+}
+
+int gftorf_render_fwd(const gftorf_gaussians* g, const gftorf_frame* frames, int32_t n_frames,
+                      const gftorf_config* cfg, const gftorf_outputs* out, void* ws,
+                      size_t ws_bytes, void* stream) {
+    int rc = check_gauss(g);
+    if (rc) return rc;
+    gft::Params P;
+    if ((rc = build_params(g->n, n_frames, cfg, &P))) return rc;
+    if (!frames) return fail(GFTORF_EINVAL, "frames is NULL");
+    if (!out || !out->T_final || !out->n_contrib) return fail(GFTORF_EINVAL, "outputs: T_final and n_contrib are required");
+    if (!ws) return fail(GFTORF_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GFTORF_EINVAL, "workspace must be 256-byte aligned");
+    const gft::Workspace w = gft::carve(ws, g->n, n_frames, P.nf, P.n_tiles, P.cap);
+    if (ws_bytes < w.bytes) return fail(GFTORF_ENOWS, "workspace too small: need " + std::to_string(w.bytes) + " bytes");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+
+    gft::launch_fill_u32(reinterpret_cast<uint32_t*>(w.status), 0u, sizeof(gft::Status) / 4, s);
+    gft::launch_preprocess(P, *g, frames, w, s);
+    int dbuf = 0;
+    gft::launch_depth_sort(P, w, s, &dbuf);
+    gft::launch_emit(P, w, dbuf, s);
+    const int tbuf = gft::launch_tile_sort(P, w, s);
+    gft::launch_ranges(P, w, tbuf, s);
+    hipError_t e = gft::launch_composite_fwd(P, frames, w, tbuf, *out, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "gftorf_render_fwd");
+    return GFTORF_OK;
+}
+
+int gftorf_render_bwd(const gftorf_gaussians* g, const gftorf_frame* frames, int32_t n_frames,
+                      const gftorf_config* cfg, const gftorf_outputs* saved, const float* d_rgb,
+                      const float* d_quad, const float* d_depth, const gftorf_gaussians_grad* grad,
+                      float* d_bg, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_gauss(g);
+    if (rc) return rc;
+    gft::Params P;
+    if ((rc = build_params(g->n, n_frames, cfg, &P))) return rc;
+    if (!frames) return fail(GFTORF_EINVAL, "frames is NULL");
+    if (!saved || !saved->T_final || !saved->n_contrib) return fail(GFTORF_EINVAL, "saved: T_final and n_contrib are required");
+    if (!grad) return fail(GFTORF_EINVAL, "grad is NULL");
+    if (!ws) return fail(GFTORF_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GFTORF_EINVAL, "workspace must be 256-byte aligned");
+    const gft::Workspace w = gft::carve(ws, g->n, n_frames, P.nf, P.n_tiles, P.cap);
+    if (ws_bytes < w.bytes) return fail(GFTORF_ENOWS, "workspace too small: need " + std::to_string(w.bytes) + " bytes");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+
+    gft::launch_fill_f32(w.grec, 0.f, (int64_t)gft::grad_floats(P.nf) * w.M, s);
+    if (d_bg) gft::launch_fill_f32(d_bg, 0.f, (int64_t)n_frames * (3 + P.nq), s);
+    hipError_t e = gft::launch_composite_bwd(P, frames, w, sorted_buffer(P), *saved, d_rgb, d_quad,
+                                             d_depth, d_bg, s);
+    if (e == hipSuccess) {
+        gft::launch_preprocess_bwd(P, *g, frames, w, *grad, s);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return hip_fail(e, "gftorf_render_bwd");
+    return GFTORF_OK;
+}
+
+int gftorf_read_status(const void* ws, gftorf_status* out, void* stream) {
+    if (!ws || !out) return fail(GFTORF_EINVAL, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    gft::Status st;
+    hipError_t e = hipMemcpyAsync(&st, ws, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gftorf_read_status");
+    out->n_pairs = (int64_t)st.n_pairs;
+    out->max_pairs = (int64_t)st.cap;
+    out->overflow = (int32_t)st.overflow;
+    out->nonfinite = (int32_t)st.nonfinite;
+    if (st.overflow) return fail(GFTORF_EOVERFLOW, "pairs exceeded max_pairs: " + std::to_string(st.n_pairs));
+    return GFTORF_OK;
+}
+
+int gftorf_copy_lists(const void* ws, int64_t n, int32_t n_frames, const gftorf_config* cfg,
+                      uint32_t* pair_key, uint32_t* pair_item, int64_t pair_capacity,
+                      uint32_t* depth_key, uint32_t* depth_item, uint32_t* item_count,
+                      uint32_t* item_rect, void* stream) {
+    gft::Params P;
+    int rc = build_params(n, n_frames, cfg, &P);
+    if (rc) return rc;
+    if (!ws) return fail(GFTORF_EINVAL, "workspace is NULL");
+    const gft::Workspace w = gft::carve(const_cast<void*>(ws), n, n_frames, P.nf, P.n_tiles, P.cap);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    gft::Status st;
+    hipError_t e = hipMemcpyAsync(&st, ws, sizeof(st), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gftorf_copy_lists");
+    unsigned long long np = st.n_pairs < P.cap ? st.n_pairs : P.cap;
+    if (pair_capacity >= 0 && np > (unsigned long long)pair_capacity) np = (unsigned long long)pair_capacity;
+    const int tb = sorted_buffer(P);
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+        if (dst && bytes && e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+    };
+    cp(pair_key, w.tkey[tb], 4 * np);
+    cp(pair_item, w.tval[tb], 4 * np);
+    cp(depth_key, w.dkey[0], 4 * (size_t)w.M);
+    cp(depth_item, w.dval[0], 4 * (size_t)w.M);
+    cp(item_count, w.cnt, 4 * (size_t)w.M);
+    cp(item_rect, w.rect, 8 * (size_t)w.M);
+    if (e != hipSuccess) return hip_fail(e, "gftorf_copy_lists");
+    return GFTORF_OK;
+}
+
+int gftorf_l2_loss_grad(const float* pred, const float* targets, const int32_t* frame_index,
+                        int32_t n_frames, int64_t elems_per_frame, float weight, float* grad,
+                        float* loss, void* stream) {
+    if (!pred || !targets || !grad) return fail(GFTORF_EINVAL, "NULL argument");
+    if (n_frames < 1 || elems_per_frame < 1) return fail(GFTORF_EINVAL, "empty loss");
+    (void)hipGetLastError();
+    gft::launch_l2_loss(pred, targets, frame_index, n_frames, elems_per_frame, weight, grad, loss,
+                        static_cast<hipStream_t>(stream));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_l2_loss_grad");
+}
+
+int gftorf_adam_step(const gftorf_adam_group* groups, int32_t n_groups, int32_t* step, float beta1,
+                     float beta2, float eps, void* stream) {
+    if (!groups || n_groups < 1 || !step) return fail(GFTORF_EINVAL, "bad Adam arguments");
+    for (int i = 0; i < n_groups; ++i)
+        if (groups[i].n < 0 || (groups[i].n > 0 && (!groups[i].param || !groups[i].grad || !groups[i].m || !groups[i].v)))
+            return fail(GFTORF_EINVAL, "bad Adam group " + std::to_string(i));
+    (void)hipGetLastError();
+    gft::launch_adam(groups, n_groups, step, beta1, beta2, eps, static_cast<hipStream_t>(stream));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_adam_step");
+}
+
+int gftorf_select_frames(gftorf_frame* frames, int32_t n_batch, const gftorf_frame* seq,
+                         int32_t n_seq, const float* bg_table, int32_t n_bg, int32_t n_quad,
+                         const int32_t* step, int32_t* frame_index, void* stream) {
+    if (!frames || !seq || !step || n_batch < 1 || n_seq < 1) return fail(GFTORF_EINVAL, "bad frame selection arguments");
+    if (bg_table && (n_bg < 1 || n_quad < 0 || n_quad > GFTORF_MAX_QUAD)) return fail(GFTORF_EINVAL, "bad background table");
+    (void)hipGetLastError();
+    gft::launch_select_frames(frames, n_batch, seq, n_seq, bg_table, n_bg, n_quad, step, frame_index,
+                              static_cast<hipStream_t>(stream));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_select_frames");
+}
+
+int gftorf_fill_f32(float* p, float value, int64_t n, void* stream) {
+    if (!p && n > 0) return fail(GFTORF_EINVAL, "NULL pointer");
+    (void)hipGetLastError();
+    gft::launch_fill_f32(p, value, n, static_cast<hipStream_t>(stream));
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_fill_f32");
+}
+
+int gftorf_graph_begin(void* stream) {
+    hipError_t e = hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal);
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_graph_begin");
+}
+
+int gftorf_graph_end(void* stream, void** graph_exec) {
+    if (!graph_exec) return fail(GFTORF_EINVAL, "graph_exec is NULL");
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(static_cast<hipStream_t>(stream), &graph);
+    if (e != hipSuccess) return hip_fail(e, "gftorf_graph_end (capture)");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "gftorf_graph_end (instantiate)");
+    *graph_exec = exec;
+    return GFTORF_OK;
+}
+
+int gftorf_graph_launch(void* graph_exec, void* stream) {
+    if (!graph_exec) return fail(GFTORF_EINVAL, "graph_exec is NULL");
+    hipError_t e = hipGraphLaunch(static_cast<hipGraphExec_t>(graph_exec), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_graph_launch");
+}
+
+int gftorf_graph_destroy(void* graph_exec) {
+    if (!graph_exec) return GFTORF_OK;
+    hipError_t e = hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec));
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_graph_destroy");
+}
+
+const char* gftorf_strerror(int code) {
+    switch (code) {
+        case GFTORF_OK: return "ok";
+        case GFTORF_EINVAL: return "invalid argument";
+        case GFTORF_ENOWS: return "workspace too small";
+        case GFTORF_EHIP: return "HIP runtime error";
+        case GFTORF_EOVERFLOW: return "pair capacity overflow";
+        default: return "unknown error";
+    }
+}
+
+const char* gftorf_last_error(void) { return g_err.c_str(); }
+
+int gftorf_version(void) { return 1; }
+
+}  // extern "C"

@@ -1,0 +1,149 @@
+// Internal definitions shared by the gfx950 kernels and the host ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gftorf.h"
+
+namespace gft {
+
+constexpr double kSpeedOfLight = 299792458.0;   // m/s
+constexpr float kLog2e = 1.4426950408889634f;
+
+// Radix sort geometry: 256 threads (4 wave64), 16 keys per thread.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
+constexpr int kSortBuckets = 256;                       // <= 8 digit bits per pass
+
+// Pair emission: items (frame, Gaussian) per block of the emit kernel.
+constexpr int kEmitThreads = 256;
+constexpr int kEmitItems = 4;
+constexpr int kEmitChunk = kEmitThreads * kEmitItems;  // 1024
+
+// Per-(frame, Gaussian) record in float4 units.
+//   r0 = {u_hi, v_hi, u_lo, v_lo}   pixel centre as an unevaluated float pair
+//   r1 = {cA, cB, cC, o}           conic pre-scaled by -log2(e) (x 1/2 on A, C)
+//   r2 = {red, green, blue, d}     colour and range to the optical centre
+//   r3.. = {a sin psi_f, a cos psi_f} for each frequency f (two per float4)
+__host__ __device__ constexpr int record_float4s(int nf) { return 3 + (nf + 1) / 2; }
+// Gradient record per (frame, Gaussian), in floats:
+//   du, dv, dcA, dcB, dcC, do, dred, dgreen, dblue, dd, {d(a sin), d(a cos)} x nf
+__host__ __device__ constexpr int grad_floats(int nf) { return ((10 + 2 * nf) + 3) / 4 * 4; }
+
+// Workspace header, at offset 0 of the workspace.
+struct Status {
+    unsigned long long n_pairs;   // total pairs of the last forward
+    unsigned long long cap;       // capacity (max_pairs)
+    unsigned int overflow;
+    unsigned int nonfinite;
+    unsigned int pad[10];
+};
+
+// Everything a kernel needs to know about a call, passed by value.
+struct Params {
+    int64_t n;              // Gaussians
+    int32_t F;              // frames
+    int32_t W, H;
+    int32_t tw, th, ntx, nty, n_tiles;
+    int32_t nf, nphi, nq;
+    double freq[GFTORF_MAX_FREQ];
+    float cphi[GFTORF_MAX_PHASE], sphi[GFTORF_MAX_PHASE];
+    float alpha_min, alpha_max, T_min, extent, dilation, near_z, s_int;
+    int32_t bg_pow;
+    unsigned long long cap;  // pair capacity
+    int32_t key_bits;        // bits of the (frame, tile) key
+};
+
+// Device pointers carved out of the caller's workspace.
+struct Workspace {
+    Status* status;
+    float4* rec;            // [M][record_float4s]
+    uint2* rect;            // [M] packed (x_lo | x_hi << 16, y_lo | y_hi << 16)
+    uint32_t* cnt;          // [M] tiles covered
+    uint32_t* dkey[2];      // [M] depth keys (double buffer)
+    uint32_t* dval[2];      // [M] item ids
+    unsigned long long* chunk_sum;  // [n_chunks + 1] emission chunk sums / offsets
+    uint32_t* tkey[2];      // [cap] (frame, tile) keys
+    uint32_t* tval[2];      // [cap] item ids
+    uint32_t* counts;       // [256][max_sort_tiles] per-tile digit counts
+    uint32_t* totals;       // [256]
+    uint2* ranges;          // [F * n_tiles]
+    float* grec;            // [M][grad_floats]
+    int64_t M;
+    int64_t n_chunks;
+    int64_t max_sort_tiles;
+    size_t bytes;
+};
+
+// Carves `base` (may be NULL to only compute the size).
+inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int n_tiles, uint64_t cap) {
+    Workspace w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = (off + 255) & ~size_t(255);
+        char* p = base ? static_cast<char*>(base) + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const int64_t M = n * F;
+    w.M = M;
+    w.n_chunks = (M + kEmitChunk - 1) / kEmitChunk;
+    int64_t sort_n = M > (int64_t)cap ? M : (int64_t)cap;
+    w.max_sort_tiles = (sort_n + kSortTile - 1) / kSortTile;
+    if (w.max_sort_tiles < 1) w.max_sort_tiles = 1;
+    w.status = reinterpret_cast<Status*>(take(sizeof(Status)));
+    w.rec = reinterpret_cast<float4*>(take(sizeof(float4) * record_float4s(nf) * M));
+    w.rect = reinterpret_cast<uint2*>(take(sizeof(uint2) * M));
+    w.cnt = reinterpret_cast<uint32_t*>(take(4 * M));
+    for (int i = 0; i < 2; ++i) w.dkey[i] = reinterpret_cast<uint32_t*>(take(4 * M));
+    for (int i = 0; i < 2; ++i) w.dval[i] = reinterpret_cast<uint32_t*>(take(4 * M));
+    w.chunk_sum = reinterpret_cast<unsigned long long*>(take(8 * (w.n_chunks + 1)));
+    for (int i = 0; i < 2; ++i) w.tkey[i] = reinterpret_cast<uint32_t*>(take(4 * cap));
+    for (int i = 0; i < 2; ++i) w.tval[i] = reinterpret_cast<uint32_t*>(take(4 * cap));
+    w.counts = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets * w.max_sort_tiles));
+    w.totals = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets));
+    w.ranges = reinterpret_cast<uint2*>(take(sizeof(uint2) * (int64_t)F * n_tiles));
+    w.grec = reinterpret_cast<float*>(take(4 * (size_t)grad_floats(nf) * M));
+    w.bytes = off + 256;
+    return w;
+}
+
+// Block -> work-item remap so that each of the 8 XCDs (which receive blocks
+// round-robin) processes one contiguous range of work items, keeping the
+// records of neighbouring tiles and of one frame in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    constexpr int kX = 8;
+    const int q = nb / kX, r = nb % kX;
+    const int x = b % kX, i = b / kX;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// ---- host-side launchers (defined in the .hip files) -----------------------
+void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_frame* frames,
+                       const Workspace& w, hipStream_t s);
+void launch_depth_sort(const Params& P, const Workspace& w, hipStream_t s, int* result_buf);
+void launch_emit(const Params& P, const Workspace& w, int dbuf, hipStream_t s);
+int launch_tile_sort(const Params& P, const Workspace& w, hipStream_t s);
+void launch_ranges(const Params& P, const Workspace& w, int tbuf, hipStream_t s);
+hipError_t launch_composite_fwd(const Params& P, const gftorf_frame* frames, const Workspace& w,
+                                int tbuf, const gftorf_outputs& out, hipStream_t s);
+hipError_t launch_composite_bwd(const Params& P, const gftorf_frame* frames, const Workspace& w,
+                                int tbuf, const gftorf_outputs& saved, const float* d_rgb,
+                                const float* d_quad, const float* d_depth, float* d_bg,
+                                hipStream_t s);
+void launch_preprocess_bwd(const Params& P, const gftorf_gaussians& g, const gftorf_frame* frames,
+                           const Workspace& w, const gftorf_gaussians_grad& grad, hipStream_t s);
+void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void launch_l2_loss(const float* pred, const float* targets, const int32_t* frame_index,
+                    int32_t n_frames, int64_t elems, float weight, float* grad, float* loss,
+                    hipStream_t s);
+void launch_adam(const gftorf_adam_group* groups, int32_t n_groups, int32_t* step, float b1,
+                 float b2, float eps, hipStream_t s);
+void launch_select_frames(gftorf_frame* frames, int32_t n_batch, const gftorf_frame* seq,
+                          int32_t n_seq, const float* bg_table, int32_t n_bg, int32_t n_quad,
+                          const int32_t* step, int32_t* frame_index, hipStream_t s);
+
+}  // namespace gft

@@ -1,0 +1,366 @@
+// Front-to-back compositing (forward) and back-to-front gradient recursion
+// (backward) of RGB, mean depth and raw C-ToF quads, one workgroup per
+// (frame, tile) work item and one thread per pixel.
+//
+// Forward (paper §3): for each pixel walk the tile's depth-sorted list and
+//   alpha = min(alpha_max, o G(x)),  skip if alpha < alpha_min,
+//   stop before compositing if T (1 - alpha) < T_min,
+//   RGB += c alpha T (Eq. 2), D += d alpha T (Eq. 5),
+//   S_f += a sin(psi_f) alpha T^2, C_f += a cos(psi_f) alpha T^2 (Eq. 4),
+// then Q_{f,j} = cos(phi_j) S_f + sin(phi_j) C_f + q_bg T^p, because
+// sin(psi + phi) = sin(psi) cos(phi) + cos(psi) sin(phi): two accumulators
+// per frequency serve every phase offset.
+//
+// Backward (supplement C): walk the same list back to front from the last
+// composited entry, recover T_k = T_{k+1} / (1 - alpha_k) from the saved
+// T_final, and accumulate dL/dalpha_k with Eq. S2 (RGB, depth) and Eq. S3
+// (quads) plus the background terms; then chain to the per-entry screen-space
+// quantities.  Per-entry gradients are summed over the wave with DPP and
+// added to the per-(frame, Gaussian) gradient record with one atomic per wave.
+//
+// Records of a batch of list entries are staged in LDS by the whole
+// workgroup (one coalesced 64-byte gather per entry), then every lane reads
+// them as LDS broadcasts.  No MFMA: per (pixel, entry) this is ~20 FP32 VALU
+// operations and one v_exp_f32.
+#include "block_scan.h"
+#include "common.h"
+
+namespace gft {
+
+namespace {
+
+// alpha of one (pixel, entry) pair.  One definition shared by the forward and
+// the backward kernels, with contraction pinned, so both take identical skip
+// / stop / clamp decisions.
+__device__ __forceinline__ float splat_alpha(const float4 r0, const float4 r1, float px, float py,
+                                             float amax, float& dx, float& dy, float& G) {
+#pragma clang fp contract(off)
+    dx = (px - r0.x) - r0.z;
+    dy = (py - r0.y) - r0.w;
+    const float q = __builtin_fmaf(r1.x * dx, dx, __builtin_fmaf(r1.y * dx, dy, (r1.z * dy) * dy));
+    G = __builtin_amdgcn_exp2f(q);
+    return fminf(r1.w * G, amax);
+}
+
+// Sum over the 64 lanes of a wave: DPP within rows of 16, then 4 readlanes.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf,
+                                                              0xf, true));
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_f32<0xb1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f32<0x4e>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f32<0x114>(v);   // row_shr:4
+    v += dpp_f32<0x118>(v);   // row_shr:8 -> lane 15 of each row holds the row sum
+    const int b = __builtin_bit_cast(int, v);
+    return (__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 15)) +
+            __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 31))) +
+           (__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 47)) +
+            __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 63)));
+}
+
+template <int TW, int TH, int NF>
+__global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftorf_frame* __restrict__ frames,
+                                                           const uint2* __restrict__ ranges,
+                                                           const uint32_t* __restrict__ tval,
+                                                           const float4* __restrict__ rec,
+                                                           gftorf_outputs out) {
+    constexpr int BS = TW * TH;
+    constexpr int RS4 = record_float4s(NF);
+    __shared__ float4 srec[RS4][BS];
+
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const int f = w / P.n_tiles;
+    const int tile = w - f * P.n_tiles;
+    const int ty = tile / P.ntx, tx = tile - ty * P.ntx;
+    const int tid = threadIdx.x;
+    const int x = tx * TW + (tid % TW), y = ty * TH + (tid / TW);
+    const bool inside = x < P.W && y < P.H;
+    const float fpx = (float)x + 0.5f, fpy = (float)y + 0.5f;
+    const uint2 rg = ranges[w];
+    const float amin = P.alpha_min, amax = P.alpha_max, tmin = P.T_min;
+
+    float T = 1.0f;
+    float cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f;
+    float S[NF], C[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) S[i] = C[i] = 0.f;
+    bool done = !inside;
+    uint32_t last = 0;
+
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BS) {
+        if (__syncthreads_count(!done) == 0) break;
+        const uint32_t j = b0 + tid;
+        if (j < rg.y) {
+            const float4* r = rec + (size_t)tval[j] * RS4;
+#pragma unroll
+            for (int q = 0; q < RS4; ++q) srec[q][tid] = r[q];
+        }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)BS, rg.y - b0);
+        for (int k = 0; k < cnt; ++k) {
+            if (done) continue;
+            const float4 r0 = srec[0][k], r1 = srec[1][k];
+            float dx, dy, G;
+            const float a = splat_alpha(r0, r1, fpx, fpy, amax, dx, dy, G);
+            if (a < amin) continue;
+            const float nT = T * (1.0f - a);
+            if (nT < tmin) {
+                done = true;
+                continue;
+            }
+            const float4 r2 = srec[2][k];
+            const float w1 = a * T;
+            const float w2 = w1 * T;
+            cr += r2.x * w1;
+            cg += r2.y * w1;
+            cb += r2.z * w1;
+            dep += r2.w * w1;
+#pragma unroll
+            for (int i = 0; i < NF; ++i) {
+                const float4 rp = srec[3 + i / 2][k];
+                const float as = (i & 1) ? rp.z : rp.x;
+                const float ac = (i & 1) ? rp.w : rp.y;
+                S[i] += as * w2;
+                C[i] += ac * w2;
+            }
+            T = nT;
+            last = b0 - rg.x + (uint32_t)k + 1u;
+        }
+    }
+    if (!inside) return;
+    const gftorf_frame& fr = frames[f];
+    const size_t HW = (size_t)P.H * P.W;
+    const size_t pix = (size_t)y * P.W + x;
+    if (out.rgb) {
+        float* o = out.rgb + (size_t)f * 3 * HW + pix;
+        o[0] = cr + fr.bg_rgb[0] * T;
+        o[HW] = cg + fr.bg_rgb[1] * T;
+        o[2 * HW] = cb + fr.bg_rgb[2] * T;
+    }
+    if (out.quad) {
+        const float Tp = P.bg_pow == 2 ? T * T : T;
+        float* o = out.quad + (size_t)f * P.nq * HW + pix;
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+            for (int jj = 0; jj < P.nphi; ++jj) {
+                const int qc = i * P.nphi + jj;
+                o[qc * HW] = P.cphi[jj] * S[i] + P.sphi[jj] * C[i] + fr.bg_quad[qc] * Tp;
+            }
+    }
+    if (out.depth) out.depth[(size_t)f * HW + pix] = dep;
+    out.T_final[(size_t)f * HW + pix] = T;
+    out.n_contrib[(size_t)f * HW + pix] = (int32_t)last;
+}
+
+template <int TW, int TH, int NF>
+__global__ void __launch_bounds__(TW * TH) k_composite_bwd(
+    Params P, const gftorf_frame* __restrict__ frames, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ tval, const float4* __restrict__ rec,
+    const float* __restrict__ T_final, const int32_t* __restrict__ n_contrib,
+    const float* __restrict__ d_rgb, const float* __restrict__ d_quad, const float* __restrict__ d_depth,
+    float* __restrict__ grec, float* __restrict__ d_bg) {
+    constexpr int BS = TW * TH;
+    constexpr int RS4 = record_float4s(NF);
+    constexpr int GS = grad_floats(NF);
+    constexpr int NG = 10 + 2 * NF;
+    __shared__ float4 srec[RS4][BS];
+    __shared__ uint32_t sitem[BS];
+    __shared__ uint32_t smax;
+
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const int f = w / P.n_tiles;
+    const int tile = w - f * P.n_tiles;
+    const int ty = tile / P.ntx, tx = tile - ty * P.ntx;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int x = tx * TW + (tid % TW), y = ty * TH + (tid / TW);
+    const bool inside = x < P.W && y < P.H;
+    const float fpx = (float)x + 0.5f, fpy = (float)y + 0.5f;
+    const uint2 rg = ranges[w];
+    const float amin = P.alpha_min, amax = P.alpha_max;
+    const gftorf_frame& fr = frames[f];
+    const size_t HW = (size_t)P.H * P.W;
+    const size_t pix = (size_t)y * P.W + x;
+
+    float Tf = 1.f;
+    uint32_t last = 0;
+    float gr[3] = {0.f, 0.f, 0.f}, gd = 0.f;
+    float gS[NF], gC[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) gS[i] = gC[i] = 0.f;
+    float bg_rgb_dot = 0.f, bg_q_dot = 0.f;
+    float Tp = 1.f;
+    if (inside) {
+        Tf = T_final[(size_t)f * HW + pix];
+        last = (uint32_t)n_contrib[(size_t)f * HW + pix];
+        Tp = P.bg_pow == 2 ? Tf * Tf : Tf;
+        if (d_rgb)
+            for (int c = 0; c < 3; ++c) gr[c] = d_rgb[((size_t)f * 3 + c) * HW + pix];
+        if (d_depth) gd = d_depth[(size_t)f * HW + pix];
+        for (int c = 0; c < 3; ++c) bg_rgb_dot += fr.bg_rgb[c] * gr[c];
+        if (d_quad) {
+#pragma unroll
+            for (int i = 0; i < NF; ++i)
+                for (int jj = 0; jj < P.nphi; ++jj) {
+                    const int qc = i * P.nphi + jj;
+                    const float g = d_quad[((size_t)f * P.nq + qc) * HW + pix];
+                    gS[i] += P.cphi[jj] * g;
+                    gC[i] += P.sphi[jj] * g;
+                    bg_q_dot += fr.bg_quad[qc] * g;
+                }
+        }
+    }
+    // background gradients: dL/dc_bg = sum d_rgb T_final, dL/dq_bg = sum d_quad T_final^p
+    if (d_bg) {
+        const int nbg = 3 + P.nq;
+        for (int c = 0; c < nbg; ++c) {
+            float v = 0.f;
+            if (inside) {
+                if (c < 3) v = gr[c] * Tf;
+                else if (d_quad) v = d_quad[((size_t)f * P.nq + (c - 3)) * HW + pix] * Tp;
+            }
+            v = wave_sum(v);
+            if (lane == 0 && v != 0.f) atomicAdd(&d_bg[(size_t)f * nbg + c], v);
+        }
+    }
+    if (tid == 0) smax = 0;
+    __syncthreads();
+    if (last) atomicMax(&smax, last);
+    __syncthreads();
+    const uint32_t maxl = smax;
+    const float bgT_rgb = bg_rgb_dot * Tf;
+    const float bgT_q = (float)P.bg_pow * bg_q_dot * Tp;
+
+    float T = Tf;
+    float acc_c[3] = {0.f, 0.f, 0.f}, acc_d = 0.f;
+    float acc_s[NF], acc_k[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) acc_s[i] = acc_k[i] = 0.f;
+    const float LN2 = 0.6931471805599453f;
+
+    for (uint32_t hi = min(rg.x + maxl, rg.y); hi > rg.x; ) {
+        const uint32_t lo = (hi - rg.x > (uint32_t)BS) ? hi - BS : rg.x;
+        const int cnt = (int)(hi - lo);
+        __syncthreads();
+        if (tid < cnt) {
+            const uint32_t item = tval[hi - 1 - tid];
+            sitem[tid] = item;
+            const float4* r = rec + (size_t)item * RS4;
+#pragma unroll
+            for (int q = 0; q < RS4; ++q) srec[q][tid] = r[q];
+        }
+        __syncthreads();
+        for (int s = 0; s < cnt; ++s) {
+            const uint32_t kidx = hi - 1 - (uint32_t)s - rg.x;   // position in the tile list
+            const float4 r0 = srec[0][s], r1 = srec[1][s];
+            float dx, dy, G;
+            const float a = splat_alpha(r0, r1, fpx, fpy, amax, dx, dy, G);
+            const bool act = (kidx < last) && (a >= amin);
+            if (__ballot(act) == 0ull) continue;
+            float g[NG];
+#pragma unroll
+            for (int i = 0; i < NG; ++i) g[i] = 0.f;
+            if (act) {
+                const float4 r2 = srec[2][s];
+                const float om = 1.0f - a;
+                T = __fdividef(T, om);
+                const float T2 = T * T;
+                float dA = gr[0] * (T * (r2.x - acc_c[0])) + gr[1] * (T * (r2.y - acc_c[1])) +
+                           gr[2] * (T * (r2.z - acc_c[2]));
+                dA += gd * (T * (r2.w - acc_d));
+                dA -= __fdividef(bgT_rgb + bgT_q, om);
+                const float w1 = a * T, w2 = a * T2;
+                g[6] = w1 * gr[0];
+                g[7] = w1 * gr[1];
+                g[8] = w1 * gr[2];
+                g[9] = w1 * gd;
+#pragma unroll
+                for (int i = 0; i < NF; ++i) {
+                    const float4 rp = srec[3 + i / 2][s];
+                    const float as = (i & 1) ? rp.z : rp.x;
+                    const float ac = (i & 1) ? rp.w : rp.y;
+                    dA += T2 * (gS[i] * (as + 2.0f * (a - 1.0f) * acc_s[i]) +
+                                gC[i] * (ac + 2.0f * (a - 1.0f) * acc_k[i]));
+                    g[10 + 2 * i] = w2 * gS[i];
+                    g[11 + 2 * i] = w2 * gC[i];
+                    acc_s[i] = a * as + om * om * acc_s[i];
+                    acc_k[i] = a * ac + om * om * acc_k[i];
+                }
+                acc_c[0] = a * r2.x + om * acc_c[0];
+                acc_c[1] = a * r2.y + om * acc_c[1];
+                acc_c[2] = a * r2.z + om * acc_c[2];
+                acc_d = a * r2.w + om * acc_d;
+                if (r1.w * G <= amax) {   // not clamped: alpha = o 2^q
+                    const float gq = dA * a * LN2;
+                    g[5] = G * dA;                                  // d/do
+                    g[2] = gq * dx * dx;                            // d/dcA
+                    g[3] = gq * dx * dy;                            // d/dcB
+                    g[4] = gq * dy * dy;                            // d/dcC
+                    g[0] = -gq * (2.0f * r1.x * dx + r1.y * dy);    // d/du
+                    g[1] = -gq * (2.0f * r1.z * dy + r1.y * dx);    // d/dv
+                }
+            }
+            float* dst = grec + (size_t)sitem[s] * GS;
+#pragma unroll
+            for (int i = 0; i < NG; ++i) {
+                const float v = wave_sum(g[i]);
+                if (lane == 0 && v != 0.f) atomicAdd(dst + i, v);
+            }
+        }
+        hi = lo;
+    }
+}
+
+template <int TW, int TH>
+hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w, int tbuf,
+                  const gftorf_outputs& out, hipStream_t s) {
+    const unsigned blocks = (unsigned)(P.F * P.n_tiles);
+    switch (P.nf) {
+        case 1: hipLaunchKernelGGL((k_composite_fwd<TW, TH, 1>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, w.ranges, w.tval[tbuf], w.rec, out); break;
+        case 2: hipLaunchKernelGGL((k_composite_fwd<TW, TH, 2>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, w.ranges, w.tval[tbuf], w.rec, out); break;
+        case 3: hipLaunchKernelGGL((k_composite_fwd<TW, TH, 3>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, w.ranges, w.tval[tbuf], w.rec, out); break;
+        default: hipLaunchKernelGGL((k_composite_fwd<TW, TH, 4>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, w.ranges, w.tval[tbuf], w.rec, out); break;
+    }
+    return hipGetLastError();
+}
+
+template <int TW, int TH>
+hipError_t bwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w, int tbuf,
+                  const gftorf_outputs& sv, const float* dr, const float* dq, const float* dd,
+                  float* dbg, hipStream_t s) {
+    const unsigned blocks = (unsigned)(P.F * P.n_tiles);
+#define GFT_BWD(NF_)                                                                             \
+    hipLaunchKernelGGL((k_composite_bwd<TW, TH, NF_>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, \
+                       w.ranges, w.tval[tbuf], w.rec, sv.T_final, sv.n_contrib, dr, dq, dd, w.grec, dbg)
+    switch (P.nf) {
+        case 1: GFT_BWD(1); break;
+        case 2: GFT_BWD(2); break;
+        case 3: GFT_BWD(3); break;
+        default: GFT_BWD(4); break;
+    }
+#undef GFT_BWD
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_composite_fwd(const Params& P, const gftorf_frame* frames, const Workspace& w,
+                                int tbuf, const gftorf_outputs& out, hipStream_t s) {
+    if (P.tw == 8 && P.th == 8) return fwd_nf<8, 8>(P, frames, w, tbuf, out, s);
+    if (P.tw == 32 && P.th == 8) return fwd_nf<32, 8>(P, frames, w, tbuf, out, s);
+    return fwd_nf<16, 16>(P, frames, w, tbuf, out, s);
+}
+
+hipError_t launch_composite_bwd(const Params& P, const gftorf_frame* frames, const Workspace& w,
+                                int tbuf, const gftorf_outputs& saved, const float* d_rgb,
+                                const float* d_quad, const float* d_depth, float* d_bg,
+                                hipStream_t s) {
+    if (P.tw == 8 && P.th == 8) return bwd_nf<8, 8>(P, frames, w, tbuf, saved, d_rgb, d_quad, d_depth, d_bg, s);
+    if (P.tw == 32 && P.th == 8) return bwd_nf<32, 8>(P, frames, w, tbuf, saved, d_rgb, d_quad, d_depth, d_bg, s);
+    return bwd_nf<16, 16>(P, frames, w, tbuf, saved, d_rgb, d_quad, d_depth, d_bg, s);
+}
+
+}  // namespace gft

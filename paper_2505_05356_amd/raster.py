@@ -1,0 +1,273 @@
+"""Python binding of the C-ToF Gaussian rasterizer (argument marshalling only).
+
+PyTorch provides device memory and streams; every step of the forward and
+backward pass runs in the HIP kernels of libgftorf.so.
+
+    params  dict of float32 CUDA tensors: mean [3,N], vel [3,N] | None,
+            acc [3,N] | None, scale [3,N], quat [4,N], omega [3,N] | None,
+            opacity_logit [N], rgb [3,N], albedo [N]
+    frames  list of frame descriptors (objects with R, t, fx, fy, cx, cy,
+            time, bg_rgb, bg_quad) or a packed float32 CUDA tensor [F, 36]
+    cfg     object with width, height, freqs, phases, tile_w, tile_h,
+            alpha_min, alpha_max, T_min, extent_sigma, dilation, near_z,
+            source_intensity, bg_T_power
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FIELDS, FRAME_FLOATS, MAX_QUAD
+
+
+@dataclasses.dataclass
+class RasterConfig:
+    """Per-call constants (same names as the C struct gftorf_config)."""
+    width: int = 640
+    height: int = 480
+    freqs: tuple = (30e6,)
+    phases: tuple = (0.0, 0.5 * math.pi, math.pi, 1.5 * math.pi)
+    tile_w: int = 16
+    tile_h: int = 16
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    extent_sigma: float = 3.0
+    dilation: float = 0.3
+    near_z: float = 0.2
+    source_intensity: float = 1.0
+    bg_T_power: int = 1
+
+
+def config_struct(cfg, max_pairs: int) -> _lib.ConfigC:
+    c = _lib.ConfigC()
+    c.width, c.height = int(cfg.width), int(cfg.height)
+    c.n_freq, c.n_phase = len(cfg.freqs), len(cfg.phases)
+    # counts beyond the struct's capacity are passed through for the library
+    # to reject (GFTORF_EINVAL)
+    for i, f in enumerate(list(cfg.freqs)[:_lib.MAX_FREQ]):
+        c.freq_hz[i] = float(np.float32(f))
+    for j, p in enumerate(list(cfg.phases)[:_lib.MAX_PHASE]):
+        c.phase[j] = float(p)
+    c.tile_w, c.tile_h = int(cfg.tile_w), int(cfg.tile_h)
+    c.alpha_min, c.alpha_max, c.T_min = cfg.alpha_min, cfg.alpha_max, cfg.T_min
+    c.extent_sigma, c.dilation, c.near_z = cfg.extent_sigma, cfg.dilation, cfg.near_z
+    c.source_intensity, c.bg_T_power = cfg.source_intensity, int(cfg.bg_T_power)
+    c.max_pairs = int(max_pairs)
+    return c
+
+
+def n_quad(cfg) -> int:
+    return len(cfg.freqs) * len(cfg.phases)
+
+
+def pack_frames(frames, cfg, device="cuda") -> torch.Tensor:
+    """Frame descriptors -> float32 device tensor [F, 36] (struct gftorf_frame)."""
+    if isinstance(frames, torch.Tensor):
+        return frames
+    F = len(frames)
+    a = np.zeros((F, FRAME_FLOATS), np.float32)
+    nq = n_quad(cfg)
+    for i, fr in enumerate(frames):
+        a[i, 0:9] = np.asarray(fr.R, np.float32).reshape(9)
+        a[i, 9:12] = np.asarray(fr.t, np.float32).reshape(3)
+        a[i, 12:16] = [fr.fx, fr.fy, fr.cx, fr.cy]
+        a[i, 16] = fr.time
+        a[i, 17:20] = np.asarray(fr.bg_rgb, np.float32).reshape(3)
+        if fr.bg_quad is not None:
+            a[i, 20:20 + nq] = np.asarray(fr.bg_quad, np.float32).reshape(-1)[:nq]
+    return torch.from_numpy(a).to(device)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def gaussians_struct(params: Dict[str, torch.Tensor]) -> _lib.GaussiansC:
+    g = _lib.GaussiansC()
+    n = params["opacity_logit"].shape[0]
+    g.n = n
+    for k in FIELDS:
+        t = params.get(k)
+        if t is None:
+            if k not in _lib.OPTIONAL:
+                raise ValueError(f"parameter {k} is required")
+            setattr(g, k, None)
+            continue
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError(f"parameter {k} must be a contiguous float32 CUDA tensor")
+        if t.numel() != _lib.ROWS[k] * n:
+            raise ValueError(f"parameter {k} has {t.numel()} elements, expected {_lib.ROWS[k] * n}")
+        setattr(g, k, t.data_ptr())
+    return g
+
+
+class Workspace:
+    """Device workspace of a (N, F, cfg) problem; keeps the forward's sorted
+    lists and records for the backward.  Grows when the pair capacity
+    overflows."""
+
+    def __init__(self, n: int, n_frames: int, cfg, max_pairs: Optional[int] = None,
+                 device="cuda"):
+        self.n, self.n_frames, self.cfg, self.device = n, n_frames, cfg, device
+        if max_pairs is None:
+            max_pairs = max(1 << 16, 48 * n * n_frames)
+        self._alloc(max_pairs)
+
+    def _alloc(self, max_pairs):
+        lib = _lib.load()
+        self.max_pairs = int(min(max_pairs, 0xF0000000))
+        self.cstruct = config_struct(self.cfg, self.max_pairs)
+        size = lib.gftorf_workspace_size(self.n, self.n_frames, ctypes.byref(self.cstruct))
+        if size == 0:
+            raise _lib.GftorfError(_lib.EINVAL, lib.gftorf_last_error().decode())
+        self.buf = torch.empty(size + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.buf.data_ptr()) % 256
+        self.ptr = self.buf.data_ptr() + off
+        self.nbytes = size
+
+    def grow(self, pairs: int):
+        self._alloc(int(pairs * 1.25) + 4096)
+
+    def status(self, stream=None) -> dict:
+        lib = _lib.load()
+        st = _lib.StatusC()
+        rc = lib.gftorf_read_status(ctypes.c_void_p(self.ptr), ctypes.byref(st), _stream(stream))
+        if rc not in (_lib.OK, _lib.EOVERFLOW):
+            _lib.check(rc)
+        return dict(n_pairs=st.n_pairs, max_pairs=st.max_pairs, overflow=bool(st.overflow),
+                    nonfinite=st.nonfinite)
+
+
+def alloc_outputs(n_frames, cfg, device="cuda", channels=("rgb", "quad", "depth")):
+    H, W = cfg.height, cfg.width
+    out = dict(T_final=torch.empty((n_frames, H, W), device=device),
+               n_contrib=torch.empty((n_frames, H, W), dtype=torch.int32, device=device))
+    if "rgb" in channels:
+        out["rgb"] = torch.empty((n_frames, 3, H, W), device=device)
+    if "quad" in channels:
+        out["quad"] = torch.empty((n_frames, n_quad(cfg), H, W), device=device)
+    if "depth" in channels:
+        out["depth"] = torch.empty((n_frames, H, W), device=device)
+    return out
+
+
+def outputs_struct(out) -> _lib.OutputsC:
+    o = _lib.OutputsC()
+    for k in ("rgb", "quad", "depth", "T_final", "n_contrib"):
+        setattr(o, k, out[k].data_ptr() if out.get(k) is not None else None)
+    return o
+
+
+def forward(params, frames_dev, cfg, ws: Workspace, out=None, stream=None, check=True):
+    """Enqueues the forward on `stream` (torch's current stream by default).
+    With check=True, reads the pair count back (one sync) and, on overflow,
+    grows the workspace and renders again."""
+    lib = _lib.load()
+    F = frames_dev.shape[0]
+    if out is None:
+        out = alloc_outputs(F, cfg, frames_dev.device)
+    g = gaussians_struct(params)
+    o = outputs_struct(out)
+    while True:
+        _lib.check(lib.gftorf_render_fwd(ctypes.byref(g), _ptr(frames_dev), F,
+                                         ctypes.byref(ws.cstruct), ctypes.byref(o),
+                                         ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
+        if not check:
+            return out
+        st = ws.status(stream)
+        if not st["overflow"]:
+            return out
+        ws.grow(st["n_pairs"])
+
+
+def backward(params, frames_dev, cfg, ws: Workspace, saved, d_rgb=None, d_quad=None,
+             d_depth=None, want_bg=False, stream=None, grads=None):
+    """Enqueues the backward; returns dict of parameter gradients (and
+    'bg' [F, 3 + NQ] if want_bg)."""
+    lib = _lib.load()
+    F = frames_dev.shape[0]
+    if grads is None:
+        grads = {k: (torch.empty_like(params[k]) if params.get(k) is not None else None)
+                 for k in FIELDS}
+    gg = _lib.GaussiansGradC()
+    for k in FIELDS:
+        setattr(gg, k, grads[k].data_ptr() if grads.get(k) is not None else None)
+    d_bg = torch.empty((F, 3 + n_quad(cfg)), device=frames_dev.device) if want_bg else None
+    g = gaussians_struct(params)
+    o = outputs_struct(saved)
+    for t in (d_rgb, d_quad, d_depth):
+        if t is not None and not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError("upstream gradients must be contiguous float32 CUDA tensors")
+    _lib.check(lib.gftorf_render_bwd(ctypes.byref(g), _ptr(frames_dev), F, ctypes.byref(ws.cstruct),
+                                     ctypes.byref(o), _ptr(d_rgb), _ptr(d_quad), _ptr(d_depth),
+                                     ctypes.byref(gg), _ptr(d_bg), ctypes.c_void_p(ws.ptr),
+                                     ws.nbytes, _stream(stream)))
+    if want_bg:
+        grads["bg"] = d_bg
+    return grads
+
+
+class RasterizeCToF(torch.autograd.Function):
+    """Differentiable render of RGB, raw quads and depth for a batch of frames.
+
+    forward(ctx, ws, frames_dev, cfg, *params) -> (rgb, quad, depth)
+    """
+
+    @staticmethod
+    def forward(ctx, ws, frames_dev, cfg, *plist):
+        params = {k: (p.contiguous() if p is not None else None) for k, p in zip(FIELDS, plist)}
+        out = forward(params, frames_dev, cfg, ws)
+        ctx.ws, ctx.cfg, ctx.frames = ws, cfg, frames_dev
+        ctx.params = params
+        ctx.saved_out = {k: out[k] for k in ("T_final", "n_contrib")}
+        ctx.present = [p is not None for p in plist]
+        ctx.mark_non_differentiable(out["T_final"], out["n_contrib"])
+        return out["rgb"], out["quad"], out["depth"], out["T_final"], out["n_contrib"]
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_quad, g_depth, _gT, _gn):
+        c = lambda t: None if t is None else t.contiguous()
+        grads = backward(ctx.params, ctx.frames, ctx.cfg, ctx.ws, ctx.saved_out,
+                         c(g_rgb), c(g_quad), c(g_depth))
+        res = [grads[k] if present else None for k, present in zip(FIELDS, ctx.present)]
+        return (None, None, None, *res)
+
+
+def render(params, frames, cfg, ws: Optional[Workspace] = None):
+    """Differentiable batched render.  Returns dict(rgb, quad, depth, T_final,
+    n_contrib, workspace)."""
+    frames_dev = pack_frames(frames, cfg)
+    n = params["opacity_logit"].shape[0]
+    if ws is None:
+        ws = Workspace(n, frames_dev.shape[0], cfg)
+    plist = [params.get(k) for k in FIELDS]
+    rgb, quad, depth, Tf, nc = RasterizeCToF.apply(ws, frames_dev, cfg, *plist)
+    return dict(rgb=rgb, quad=quad, depth=depth, T_final=Tf, n_contrib=nc, workspace=ws)
+
+
+def to_device_params(g, device="cuda", static=None) -> Dict[str, torch.Tensor]:
+    """Plain arrays (objects with the FIELDS attributes) -> float32 device tensors.
+    With static=True (or auto when vel, acc, omega are all zero) the optional
+    fields are passed as NULL."""
+    arrs = {k: np.asarray(getattr(g, k), np.float32) for k in FIELDS}
+    if static is None:
+        static = all(not np.any(arrs[k]) for k in _lib.OPTIONAL)
+    out = {}
+    for k, a in arrs.items():
+        if static and k in _lib.OPTIONAL:
+            out[k] = None
+        else:
+            out[k] = torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    return out

@@ -1,0 +1,98 @@
+"""Host-side checks of libgftorf.so that need no GPU: every symbol the header
+declares is exported, and argument validation returns the documented codes
+before anything touches the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gftorf.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2505_05356_amd import _lib, build
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gftorf_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("gftorf_render_fwd", "gftorf_render_bwd", "gftorf_workspace_size",
+                     "gftorf_read_status", "gftorf_adam_step", "gftorf_l2_loss_grad",
+                     "gftorf_graph_begin", "gftorf_graph_end", "gftorf_graph_launch",
+                     "gftorf_strerror"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    raw = ctypes.CDLL(lib._name)
+    missing = [n for n in declared_functions() if not hasattr(raw, n)]
+    assert not missing, missing
+
+
+def test_struct_sizes_match_header(lib):
+    from paper_2505_05356_amd import _lib
+    assert ctypes.sizeof(_lib.ConfigC) == 112
+    assert ctypes.sizeof(_lib.GaussiansC) == 8 * 10
+    assert _lib.FRAME_FLOATS * 4 == 144
+
+
+def _cfg(**kw):
+    from paper_2505_05356_amd import raster
+    c = raster.RasterConfig(width=64, height=48)
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_workspace_size_and_validation(lib):
+    from paper_2505_05356_amd import _lib, raster
+    good = raster.config_struct(_cfg(), 100000)
+    assert lib.gftorf_workspace_size(2000, 1, ctypes.byref(good)) > 100000 * 16
+    # grows with the pair capacity and the frame count
+    big = raster.config_struct(_cfg(), 200000)
+    assert lib.gftorf_workspace_size(2000, 1, ctypes.byref(big)) > \
+        lib.gftorf_workspace_size(2000, 1, ctypes.byref(good))
+    assert lib.gftorf_workspace_size(2000, 4, ctypes.byref(good)) > \
+        lib.gftorf_workspace_size(2000, 1, ctypes.byref(good))
+    for bad in (dict(tile_w=12), dict(alpha_max=1.0), dict(bg_T_power=3), dict(freqs=()),
+                dict(phases=(0.0,) * 5), dict(T_min=-1.0), dict(width=0)):
+        c = raster.config_struct(_cfg(**bad), 1000)
+        assert lib.gftorf_workspace_size(2000, 1, ctypes.byref(c)) == 0, bad
+    assert lib.gftorf_workspace_size(2000, 0, ctypes.byref(good)) == 0
+    assert lib.gftorf_workspace_size(-1, 1, ctypes.byref(good)) == 0
+
+
+def test_error_codes_before_device_work(lib):
+    from paper_2505_05356_amd import _lib, raster
+    cfg = raster.config_struct(_cfg(), 1000)
+    g = _lib.GaussiansC()
+    g.n = 10                      # required arrays missing
+    out = _lib.OutputsC()
+    rc = lib.gftorf_render_fwd(ctypes.byref(g), None, 1, ctypes.byref(cfg), ctypes.byref(out),
+                               None, 0, None)
+    assert rc == _lib.EINVAL
+    assert b"required" in lib.gftorf_last_error()
+    g.n = 0
+    rc = lib.gftorf_render_fwd(ctypes.byref(g), ctypes.c_void_p(256), 1, ctypes.byref(cfg),
+                               ctypes.byref(out), None, 0, None)
+    assert rc == _lib.EINVAL     # outputs missing
+    out.T_final = 256
+    out.n_contrib = 512
+    rc = lib.gftorf_render_fwd(ctypes.byref(g), ctypes.c_void_p(256), 1, ctypes.byref(cfg),
+                               ctypes.byref(out), ctypes.c_void_p(4096), 16, None)
+    assert rc == _lib.ENOWS
+    assert lib.gftorf_strerror(_lib.ENOWS) == b"workspace too small"
+    assert lib.gftorf_version() == 1

@@ -1,0 +1,158 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X)."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from oracle import binning, render as oref
+from tests.gpu_common import (assert_grads_close, assert_images_close, gpu_lists, mask_upstream,
+                              run_gpu)
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    c = {}
+    c["cfg1"] = scenes.cfg1()
+    w = scenes.cfg1(seed=3)
+    c["ragged-70x45"] = scenes.Workload("ragged", w.gaussians,
+                                        scenes.identity_frames([0.0], 70, 45, 60.0, 60.0, 4),
+                                        dataclasses.replace(w.cfg, width=70, height=45))
+    d = scenes.cfg3(seed=2, n=3000, n_frames=3)
+    fr = scenes.identity_frames([0.0, 0.1, 0.25], 96, 72, 80.0, 80.0, 4, bg_seed=5)
+    g = scenes.draw_gaussians(3000, 96, 72, 80.0, 80.0, seed=2, dynamic=True)
+    c["dynamic-3f-8x8-bg"] = scenes.Workload("dyn", g, fr, scenes.RenderConfig(
+        width=96, height=72, tile_w=8, tile_h=8))
+    c["dynamic-3f-32x8-p2"] = scenes.Workload("dyn2", g, fr, scenes.RenderConfig(
+        width=96, height=72, tile_w=32, tile_h=8, bg_T_power=2))
+    g2 = scenes.draw_gaussians(1500, 80, 60, 70.0, 70.0, seed=4, dynamic=True)
+    fr2 = scenes.identity_frames([0.05, 0.2], 80, 60, 70.0, 70.0, 8, bg_seed=6, n_freq=2)
+    c["two-freq"] = scenes.Workload("2f", g2, fr2, scenes.RenderConfig(
+        width=80, height=60, freqs=(30e6, 60e6)))
+    t = scenes.tiny_scene(40, 24, 20, seed=7, dynamic=True)
+    c["strict"] = scenes.Workload("strict", t.gaussians, scenes.frames_for_times([0.0, 0.2], t),
+                                  t.cfg.strict())
+    return c
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module")
+def oracle_cache():
+    return {}
+
+
+def _oracle(name, cache, upstream=False):
+    key = (name, upstream)
+    if key not in cache:
+        wl = CASES[name]
+        up = scenes.upstream_grads(len(wl.frames), wl.cfg, seed=1) if upstream else None
+        if upstream:
+            base = _oracle(name, cache, False)
+            up = mask_upstream(up, ~base["flagged"])
+        cache[key] = (oref.render(wl.gaussians, wl.frames, wl.cfg, upstream=up), up)
+    return cache[key]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_binning_bit_exact(name):
+    wl = CASES[name]
+    g, frames, cfg = wl.gaussians, wl.frames, wl.cfg
+    res = run_gpu(g, frames, cfg)
+    lists = gpu_lists(res, g, frames, cfg)
+    ref = binning.sorted_pairs(g, frames, cfg)
+    n_tiles = cfg.tiles_x * cfg.tiles_y
+    assert res["status"]["n_pairs"] == ref["P"]
+    assert not res["status"]["overflow"]
+    np.testing.assert_array_equal(lists["pair_key"], (ref["frame"] * n_tiles + ref["tile"]).astype(np.uint32))
+    np.testing.assert_array_equal(lists["pair_item"], (ref["frame"] * g.n + ref["index"]).astype(np.uint32))
+    # per-item rectangles, counts and depth keys
+    cnt_ref = np.concatenate([p["count"] for p in ref["projections"]]).astype(np.uint32)
+    np.testing.assert_array_equal(lists["count"], cnt_ref)
+    key_by_item = np.empty_like(lists["depth_key"])
+    key_by_item[lists["depth_item"]] = lists["depth_key"]
+    key_ref = np.concatenate([p["key"] for p in ref["projections"]])
+    np.testing.assert_array_equal(key_by_item, key_ref)
+    valid = cnt_ref > 0
+    rect_ref = np.concatenate([p["rect"].T for p in ref["projections"]])
+    got = lists["rect"]
+    gx = np.stack([got[:, 0] & 0xFFFF, got[:, 0] >> 16, got[:, 1] & 0xFFFF, got[:, 1] >> 16], 1)
+    np.testing.assert_array_equal(gx[valid], rect_ref[valid])
+    # depth order is a stable sort of the keys
+    assert np.all(np.diff(lists["depth_key"].astype(np.int64)) >= 0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_matches_oracle(name, oracle_cache):
+    wl = CASES[name]
+    ref, _ = _oracle(name, oracle_cache)
+    res = run_gpu(wl.gaussians, wl.frames, wl.cfg)
+    ok = ~ref["flagged"]
+    assert ok.mean() > 0.97, f"too many flagged pixels: {1 - ok.mean():.3%}"
+    for k in ("rgb", "quad", "depth", "T_final"):
+        assert_images_close(res[k], ref[k], ok, f"{name}/{k}")
+    np.testing.assert_array_equal(res["n_contrib"][ok], ref["n_contrib"][ok])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_backward_matches_oracle(name, oracle_cache):
+    wl = CASES[name]
+    ref, up = _oracle(name, oracle_cache, upstream=True)
+    res = run_gpu(wl.gaussians, wl.frames, wl.cfg, upstream=up, want_bg=True)
+    dynamic = np.any(wl.gaussians.vel)
+    for k, r in ref["grads"].items():
+        if not dynamic and k in ("vel", "acc", "omega"):
+            continue
+        assert_grads_close(res["grads"][k], r, f"{name}/{k}")
+    F = len(wl.frames)
+    bg_ref = np.concatenate([ref["grad_bg_rgb"], ref["grad_bg_quad"]], 1)
+    assert_grads_close(res["grad_bg"], bg_ref, f"{name}/bg")
+
+
+def test_batched_equals_per_frame():
+    wl = CASES["dynamic-3f-8x8-bg"]
+    batched = run_gpu(wl.gaussians, wl.frames, wl.cfg)
+    for f, fr in enumerate(wl.frames):
+        single = run_gpu(wl.gaussians, [fr], wl.cfg)
+        for k in ("rgb", "quad", "depth", "T_final", "n_contrib"):
+            np.testing.assert_array_equal(batched[k][f], single[k][0], err_msg=f"frame {f} {k}")
+
+
+def test_forward_deterministic():
+    wl = CASES["cfg1"]
+    a = run_gpu(wl.gaussians, wl.frames, wl.cfg)
+    b = run_gpu(wl.gaussians, wl.frames, wl.cfg)
+    for k in ("rgb", "quad", "depth", "T_final", "n_contrib"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_overflow_is_reported_and_recovered():
+    wl = CASES["cfg1"]
+    res = run_gpu(wl.gaussians, wl.frames, wl.cfg, max_pairs=100)
+    # forward() regrows the workspace and renders again
+    assert res["_ws"].max_pairs >= res["status"]["n_pairs"] > 100
+    ref = run_gpu(wl.gaussians, wl.frames, wl.cfg)
+    np.testing.assert_array_equal(res["rgb"], ref["rgb"])
+
+
+def test_empty_scene_renders_background():
+    wl = CASES["dynamic-3f-8x8-bg"]
+    g = wl.gaussians.subset(np.arange(0))
+    res = run_gpu(g, wl.frames, wl.cfg)
+    for f, fr in enumerate(wl.frames):
+        np.testing.assert_array_equal(res["rgb"][f], np.broadcast_to(fr.bg_rgb[:, None, None], res["rgb"][f].shape))
+        np.testing.assert_array_equal(res["T_final"][f], 1.0)
+        assert (res["n_contrib"] == 0).all()
+
+
+def test_nonfinite_gaussians_are_culled_and_counted():
+    wl = CASES["cfg1"]
+    g = wl.gaussians.copy()
+    g.mean[0, 5] = np.nan
+    g.scale[1, 7] = np.inf
+    res = run_gpu(g, wl.frames, wl.cfg)
+    assert res["status"]["nonfinite"] == 2
+    assert np.isfinite(res["rgb"]).all()
