@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Forward + backward frames/s of the C-ToF Gaussian rasterizer on one GPU.
+
+Workload (default): dynamic scene of 200,000 Gaussians (linear + quadratic
+trajectories, constant rotation rate), 8 time frames at t in [0, 0.25 s],
+640x480, fx = fy = 525, 30 MHz, RGB + 4 raw quads + depth, upstream gradient
+N(0, 1) on every output element.  A step is one forward + backward of all 8
+frames.  Two paths are timed on the same inputs, already resident in HBM:
+  batched   -- one gftorf_render_fwd / gftorf_render_bwd call for all frames;
+  per-frame -- the same library called with n_frames = 1 for each frame, with
+               the per-frame parameter gradients summed.
+`value` is the batched frames/s.  A second timed region of the same steps
+records HIP events around every kernel (gftorf_profile_*) for the roofline of
+the dominant kernel; the FP64 CPU oracle is timed on a bounded tile sample.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import dataclasses
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed-FP32 instructions (the kernels are built with
+# them disabled): 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+# Algorithmic work per unit (measurement section).
+FWD_FLOP_PER_EVAL = 12      # dx, dy (4 sub), quadratic form (3 mul + 2 fma = 7), exp2 1
+FWD_FLOP_PER_COMP = 16      # 1 - a, T(1-a), w1, w2 (4) + 6 FMA (rgb 3, depth 1, S, C) = 12 flop
+BWD_FLOP_PER_COMP = 70      # per composited (pixel, entry) in the backward
+SORT_BYTES_PER_KEY_PASS = 16  # read key + value, write key + value (4 B each)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=200_000)
+    ap.add_argument("--frames", type=int, default=8)
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--cpu-tiles", type=int, default=24, help="oracle sample: tiles of frame 0")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-frame", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import scenes
+    from paper_2505_05356_amd import profile, raster
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    tw, th = (int(x) for x in args.tile.split("x"))
+    wl = scenes.cfg3(n=args.n, n_frames=args.frames)
+    cfg = dataclasses.replace(wl.cfg, tile_w=tw, tile_h=th)
+    F = len(wl.frames)
+    g = wl.gaussians
+    params = raster.to_device_params(g, dev)
+    fdev = raster.pack_frames(wl.frames, cfg, dev)
+    fdev1 = [fdev[f:f + 1].contiguous() for f in range(F)]
+    up = scenes.upstream_grads(F, cfg, seed=1)
+    d = {k: torch.from_numpy(v).to(dev) for k, v in up.items()}
+    d1 = [{k: v[f:f + 1].contiguous() for k, v in d.items()} for f in range(F)]
+
+    # batched path: size the pair capacity once (one checked forward), then
+    # every timed call runs without host synchronisation
+    ws = raster.Workspace(g.n, F, cfg, device=dev)
+    out = raster.alloc_outputs(F, cfg, dev)
+    raster.forward(params, fdev, cfg, ws, out=out, check=True)
+    P = ws.status()["n_pairs"]
+    flat = torch.zeros(24 * g.n, device=dev)
+    sizes = {k: raster._lib.ROWS[k] * g.n for k in raster.FIELDS}
+    grads, o = {}, 0
+    for k in raster.FIELDS:
+        grads[k] = flat[o:o + sizes[k]].view(raster._lib.ROWS[k], g.n) if params[k] is not None else None
+        o += sizes[k]
+
+    def step_batched():
+        raster.forward(params, fdev, cfg, ws, out=out, check=False)
+        raster.backward(params, fdev, cfg, ws, out, d["rgb"], d["quad"], d["depth"], grads=grads)
+
+    # per-frame path: the same entry points with n_frames = 1
+    ws1 = raster.Workspace(g.n, 1, cfg, device=dev)
+    out1 = raster.alloc_outputs(1, cfg, dev)
+    for f in range(F):
+        raster.forward(params, fdev1[f], cfg, ws1, out=out1, check=True)
+    flat1 = torch.zeros_like(flat)
+    flat_acc = torch.zeros_like(flat)
+    grads1, o = {}, 0
+    for k in raster.FIELDS:
+        grads1[k] = flat1[o:o + sizes[k]].view(raster._lib.ROWS[k], g.n) if params[k] is not None else None
+        o += sizes[k]
+
+    def step_per_frame():
+        flat_acc.zero_()
+        for f in range(F):
+            raster.forward(params, fdev1[f], cfg, ws1, out=out1, check=False)
+            raster.backward(params, fdev1[f], cfg, ws1, out1, d1[f]["rgb"], d1[f]["quad"],
+                            d1[f]["depth"], grads=grads1)
+            flat_acc.add_(flat1)
+
+    def timed(step, k):
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        s.record()
+        for _ in range(k):
+            step()
+        e.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return s.elapsed_time(e), wall
+
+    for _ in range(args.warmup):
+        step_batched()
+    ms_b, wall_b = timed(step_batched, args.steps)
+    st = ws.status()
+    assert not st["overflow"], st
+    ms_step = ms_b / args.steps
+    value = F * args.steps / (ms_b / 1e3)
+    print(f"# batched: {ms_step:.3f} ms/step, {value:.1f} frames/s, P={P}", file=sys.stderr, flush=True)
+
+    per_frame = None
+    if not args.no_per_frame:
+        for _ in range(args.warmup):
+            step_per_frame()
+        ms_p, _ = timed(step_per_frame, args.steps)
+        per_frame = F * args.steps / (ms_p / 1e3)
+        print(f"# per-frame: {ms_p / args.steps:.3f} ms/step, {per_frame:.1f} frames/s",
+              file=sys.stderr, flush=True)
+
+    # second timed region: per-kernel HIP events around every launch
+    with profile.KernelTimer(max_launches=64 * args.steps + 64) as kt:
+        for _ in range(args.steps):
+            step_batched()
+        torch.cuda.synchronize()
+    kern = {k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1), total_ms=v[1])
+            for k, v in kt.totals.items()}
+    dominant = max(kern, key=lambda k: kern[k]["total_ms"])
+    E = int(out["n_contrib"].sum().item())   # composited-through (pixel, entry) evaluations
+    roof = roofline(dominant, kern[dominant]["avg_ms"], P=P, M=g.n * F, E=E)
+    print("# kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f}ms x{v['launches'] // args.steps}"
+                                    for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["total_ms"])),
+          file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, cfg, up, args.cpu_tiles)
+
+    line = {
+        "metric": "fwd+bwd frames/s at 640x480, 200k Gaussians; batched vs per-frame launch",
+        "value": round(value, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded dynamic Gaussian scene; no dataset)",
+        "config": {"workload": f"dynamic-{g.n // 1000}k-gaussians-{F}f-{cfg.width}x{cfg.height}",
+                   "n_gaussians": g.n, "frames": F, "width": cfg.width, "height": cfg.height,
+                   "tile": args.tile, "freqs_hz": list(cfg.freqs), "quads": cfg.n_quad,
+                   "outputs": "rgb+quad+depth", "pairs": P, "evals_E": E},
+        "per_frame_value": None if per_frame is None else round(per_frame, 2),
+        "batched_over_per_frame": None if per_frame is None else round(value / per_frame, 3),
+        "roofline": roof,
+        "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def roofline(name, avg_ms, P, M, E):
+    """Roofline object of the dominant kernel from its algorithmic work."""
+    t = avg_ms / 1e3
+    if name == "k_composite_fwd":
+        flops = E * (FWD_FLOP_PER_EVAL + FWD_FLOP_PER_COMP)
+        a = flops / t / 1e12
+        return dict(bound="alu", achieved=round(a, 3), peak=round(ALU_PEAK_TFLOPS, 1),
+                    unit="TFLOP/s", frac=round(a / ALU_PEAK_TFLOPS, 4), traffic=None,
+                    work=f"{flops:.4g} FLOP per launch = E x {FWD_FLOP_PER_EVAL + FWD_FLOP_PER_COMP}")
+    if name == "k_composite_bwd":
+        flops = E * (FWD_FLOP_PER_EVAL + BWD_FLOP_PER_COMP)
+        a = flops / t / 1e12
+        return dict(bound="alu", achieved=round(a, 3), peak=round(ALU_PEAK_TFLOPS, 1),
+                    unit="TFLOP/s", frac=round(a / ALU_PEAK_TFLOPS, 4), traffic=None,
+                    work=f"{flops:.4g} FLOP per launch = E x {FWD_FLOP_PER_EVAL + BWD_FLOP_PER_COMP}")
+    if name.startswith("k_sort"):
+        # the pair sort dominates: bytes per pass over the P pairs
+        b = P * SORT_BYTES_PER_KEY_PASS
+        a = b / t / 1e9
+        return dict(bound="hbm", achieved=round(a, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(a / HBM_PEAK_GBS, 4), traffic=None,
+                    work=f"{b:.4g} B per launch = P x {SORT_BYTES_PER_KEY_PASS}")
+    return dict(bound="hbm", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s", frac=None,
+                traffic=None, work=f"no algorithmic model for {name}")
+
+
+def cpu_baseline(wl, cfg, up, n_tiles_sample):
+    """The FP64 oracle on a bounded sample: frame 0, a seeded set of tiles,
+    forward + backward; extrapolated to frames/s over all tiles."""
+    import torch
+
+    from oracle import render as oref
+    fr = [wl.frames[0]]
+    n_tiles = cfg.tiles_x * cfg.tiles_y
+    rng = np.random.default_rng(0)
+    sample = sorted(rng.choice(n_tiles, n_tiles_sample, replace=False).tolist())
+    up0 = {k: v[:1] for k, v in up.items()}
+    # first-call costs (imports, allocator, thread pools) are paid on a tiny scene
+    import scenes
+    tiny = scenes.tiny_scene(20, 16, 16, seed=0)
+    oref.render(tiny.gaussians, tiny.frames, tiny.cfg,
+                upstream=scenes.upstream_grads(1, tiny.cfg, seed=0))
+    t_fixed = float("inf")
+    for _ in range(2):
+        t0 = time.perf_counter()
+        oref.render(wl.gaussians, fr, cfg, tiles=[[]], upstream=up0)
+        t_fixed = min(t_fixed, time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    oref.render(wl.gaussians, fr, cfg, tiles=[sample], upstream=up0)
+    t_sample = time.perf_counter() - t0
+    per_tile = max(t_sample - t_fixed, 1e-9) / n_tiles_sample
+    per_frame = t_fixed + per_tile * n_tiles
+    return {"value": round(1.0 / per_frame, 6), "unit": "frames/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"frame 0, {n_tiles_sample} of {n_tiles} tiles (seeded), fwd+bwd; "
+                      f"per frame = {t_fixed:.2f} s fixed (binning + per-Gaussian chain) + "
+                      f"{per_tile:.3f} s/tile x {n_tiles} tiles, extrapolated",
+            "measured_s": round(2 * t_fixed + t_sample, 2)}
+
+
+if __name__ == "__main__":
+    main()

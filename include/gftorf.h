@@ -232,6 +232,23 @@ int gftorf_graph_end(void* stream, void** graph_exec);
 int gftorf_graph_launch(void* graph_exec, void* stream);
 int gftorf_graph_destroy(void* graph_exec);
 
+/* Per-kernel timing with HIP events, for benchmarks (not for graph capture).
+ * Between begin and end every kernel the library launches is bracketed by
+ * two events on its stream.  begin pre-creates 2 * max_launches events;
+ * launches beyond that are not timed.  collect waits for the recorded events,
+ * adds their durations to per-kernel totals and frees the slots; end collects,
+ * copies up to max_entries totals to `out` (host) and switches timing off.
+ * Profiling state is process-wide; use it from one thread at a time. */
+typedef struct gftorf_profile_entry {
+    char name[48];       /* kernel name                      */
+    int64_t launches;    /* timed launches                   */
+    double total_ms;     /* summed event-to-event durations  */
+} gftorf_profile_entry;
+
+int gftorf_profile_begin(int32_t max_launches);
+int gftorf_profile_collect(void);
+int gftorf_profile_end(gftorf_profile_entry* out, int32_t max_entries, int32_t* n_entries);
+
 const char* gftorf_strerror(int code);
 const char* gftorf_last_error(void);
 int gftorf_version(void);

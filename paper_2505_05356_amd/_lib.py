@@ -57,6 +57,10 @@ class AdamGroupC(ctypes.Structure):
                 ("n", c_int64), ("lr", c_float)]
 
 
+class ProfileEntryC(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", c_int64), ("total_ms", c_double)]
+
+
 _SIGS = {
     "gftorf_workspace_size": (c_size_t, [c_int64, c_int32, POINTER(ConfigC)]),
     "gftorf_render_fwd": (c_int32, [POINTER(GaussiansC), c_void_p, c_int32, POINTER(ConfigC),
@@ -79,6 +83,9 @@ _SIGS = {
     "gftorf_graph_end": (c_int32, [c_void_p, POINTER(c_void_p)]),
     "gftorf_graph_launch": (c_int32, [c_void_p, c_void_p]),
     "gftorf_graph_destroy": (c_int32, [c_void_p]),
+    "gftorf_profile_begin": (c_int32, [c_int32]),
+    "gftorf_profile_collect": (c_int32, []),
+    "gftorf_profile_end": (c_int32, [POINTER(ProfileEntryC), c_int32, POINTER(c_int32)]),
     "gftorf_strerror": (c_char_p, [c_int32]),
     "gftorf_last_error": (c_char_p, []),
     "gftorf_version": (c_int32, []),

@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <vector>
 
 #include "common.h"
 
@@ -99,9 +101,95 @@ int check_gauss(const gftorf_gaussians* g) {
     return GFTORF_OK;
 }
 
+// ---- profiler ---------------------------------------------------------------
+struct ProfRec {
+    const char* name;
+    int ev;   // index of the start event; stop = ev + 1
+};
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> events;
+    std::vector<int> free_slots;      // start-event indices available
+    std::vector<ProfRec> recs;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+};
+Profiler g_prof;
+
 }  // namespace
 
+namespace gft {
+
+int prof_start(const char* name, hipStream_t s) {
+    if (!g_prof.on || g_prof.free_slots.empty()) return -1;
+    const int ev = g_prof.free_slots.back();
+    g_prof.free_slots.pop_back();
+    if (hipEventRecord(g_prof.events[ev], s) != hipSuccess) {
+        g_prof.free_slots.push_back(ev);
+        return -1;
+    }
+    g_prof.recs.push_back({name, ev});
+    return (int)g_prof.recs.size() - 1;
+}
+
+void prof_stop(int slot, hipStream_t s) {
+    if (slot < 0) return;
+    (void)hipEventRecord(g_prof.events[g_prof.recs[slot].ev + 1], s);
+}
+
+}  // namespace gft
+
 extern "C" {
+
+int gftorf_profile_begin(int32_t max_launches) {
+    if (max_launches < 1) return fail(GFTORF_EINVAL, "max_launches must be >= 1");
+    if (g_prof.on) return fail(GFTORF_EINVAL, "profiling already on");
+    g_prof = Profiler();
+    g_prof.events.resize(2 * (size_t)max_launches);
+    for (auto& e : g_prof.events) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return hip_fail(r, "gftorf_profile_begin");
+    }
+    for (int i = max_launches - 1; i >= 0; --i) g_prof.free_slots.push_back(2 * i);
+    g_prof.on = true;
+    return GFTORF_OK;
+}
+
+int gftorf_profile_collect(void) {
+    for (const ProfRec& r : g_prof.recs) {
+        hipError_t e = hipEventSynchronize(g_prof.events[r.ev + 1]);
+        if (e != hipSuccess) return hip_fail(e, "gftorf_profile_collect");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, g_prof.events[r.ev], g_prof.events[r.ev + 1]);
+        if (e != hipSuccess) return hip_fail(e, "gftorf_profile_collect");
+        auto& t = g_prof.totals[r.name];
+        t.first += 1;
+        t.second += ms;
+        g_prof.free_slots.push_back(r.ev);
+    }
+    g_prof.recs.clear();
+    return GFTORF_OK;
+}
+
+int gftorf_profile_end(gftorf_profile_entry* out, int32_t max_entries, int32_t* n_entries) {
+    int rc = gftorf_profile_collect();
+    g_prof.on = false;
+    int n = 0;
+    for (const auto& kv : g_prof.totals) {
+        if (out && n < max_entries) {
+            std::memset(&out[n], 0, sizeof(out[n]));
+            std::strncpy(out[n].name, kv.first.c_str(), sizeof(out[n].name) - 1);
+            out[n].launches = kv.second.first;
+            out[n].total_ms = kv.second.second;
+        }
+        ++n;
+    }
+    if (n_entries) *n_entries = n;
+    for (auto& e : g_prof.events) (void)hipEventDestroy(e);
+    g_prof.events.clear();
+    g_prof.free_slots.clear();
+    return rc;
+}
+
 
 size_t gftorf_workspace_size(int64_t n, int32_t n_frames, const gftorf_config* cfg) {
     gft::Params P;
@@ -269,7 +357,7 @@ int gftorf_graph_end(void* stream, void** graph_exec) {
     if (e != hipSuccess) return hip_fail(e, "gftorf_graph_end (capture)");
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(e, "gftorf_graph_end (instantiate)");
     *graph_exec = exec;
     return GFTORF_OK;

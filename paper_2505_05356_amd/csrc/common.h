@@ -120,6 +120,18 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// ---- optional per-kernel timing with HIP events (capi.cpp) -----------------
+// When profiling is on (gftorf_profile_begin), every launch is bracketed by
+// two events on its stream; otherwise prof_start returns -1 and costs a load.
+int prof_start(const char* name, hipStream_t s);
+void prof_stop(int slot, hipStream_t s);
+struct ProfScope {
+    int slot;
+    hipStream_t s;
+    ProfScope(const char* name, hipStream_t st) : slot(prof_start(name, st)), s(st) {}
+    ~ProfScope() { prof_stop(slot, s); }
+};
+
 // ---- host-side launchers (defined in the .hip files) -----------------------
 void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_frame* frames,
                        const Workspace& w, hipStream_t s);

@@ -318,12 +318,17 @@ template <int TW, int TH>
 hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w, int tbuf,
                   const gftorf_outputs& out, hipStream_t s) {
     const unsigned blocks = (unsigned)(P.F * P.n_tiles);
+    ProfScope _p("k_composite_fwd", s);
+#define GFT_FWD(NF_)                                                                             \
+    hipLaunchKernelGGL((k_composite_fwd<TW, TH, NF_>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, \
+                       w.ranges, w.tval[tbuf], w.rec, out)
     switch (P.nf) {
-        case 1: hipLaunchKernelGGL((k_composite_fwd<TW, TH, 1>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, w.ranges, w.tval[tbuf], w.rec, out); break;
-        case 2: hipLaunchKernelGGL((k_composite_fwd<TW, TH, 2>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, w.ranges, w.tval[tbuf], w.rec, out); break;
-        case 3: hipLaunchKernelGGL((k_composite_fwd<TW, TH, 3>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, w.ranges, w.tval[tbuf], w.rec, out); break;
-        default: hipLaunchKernelGGL((k_composite_fwd<TW, TH, 4>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, w.ranges, w.tval[tbuf], w.rec, out); break;
+        case 1: GFT_FWD(1); break;
+        case 2: GFT_FWD(2); break;
+        case 3: GFT_FWD(3); break;
+        default: GFT_FWD(4); break;
     }
+#undef GFT_FWD
     return hipGetLastError();
 }
 
@@ -332,6 +337,7 @@ hipError_t bwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& 
                   const gftorf_outputs& sv, const float* dr, const float* dq, const float* dd,
                   float* dbg, hipStream_t s) {
     const unsigned blocks = (unsigned)(P.F * P.n_tiles);
+    ProfScope _p("k_composite_bwd", s);
 #define GFT_BWD(NF_)                                                                             \
     hipLaunchKernelGGL((k_composite_bwd<TW, TH, NF_>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, \
                        w.ranges, w.tval[tbuf], w.rec, sv.T_final, sv.n_contrib, dr, dq, dd, w.grec, dbg)

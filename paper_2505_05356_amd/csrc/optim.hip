@@ -103,13 +103,17 @@ void launch_l2_loss(const float* pred, const float* targets, const int32_t* fram
     long long blocks = (total + 256 * 8 - 1) / (256 * 8);
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
+    { ProfScope _p("k_l2_loss", s);
     hipLaunchKernelGGL(k_l2_loss, dim3((unsigned)blocks), dim3(256), 0, s, pred, targets, frame_index,
                        n_frames, (long long)elems, weight, grad, loss);
+    }
 }
 
 void launch_adam(const gftorf_adam_group* groups, int32_t n_groups, int32_t* step, float b1,
                  float b2, float eps, hipStream_t s) {
+    { ProfScope _p("k_step_increment", s);
     hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(64), 0, s, step);
+    }
     for (int base = 0; base < n_groups; base += kMaxGroups) {
         AdamArgs A{};
         const int ng = (n_groups - base) < kMaxGroups ? (n_groups - base) : kMaxGroups;
@@ -130,15 +134,19 @@ void launch_adam(const gftorf_adam_group* groups, int32_t n_groups, int32_t* ste
         long long blocks = (A.start[ng] + 256 * 4 - 1) / (256 * 4);
         if (blocks > 8192) blocks = 8192;
         if (blocks < 1) blocks = 1;
+        { ProfScope _p("k_adam", s);
         hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, A, step);
+        }
     }
 }
 
 void launch_select_frames(gftorf_frame* frames, int32_t n_batch, const gftorf_frame* seq,
                           int32_t n_seq, const float* bg_table, int32_t n_bg, int32_t n_quad,
                           const int32_t* step, int32_t* frame_index, hipStream_t s) {
+    { ProfScope _p("k_select_frames", s);
     hipLaunchKernelGGL(k_select_frames, dim3(n_batch), dim3(64), 0, s, frames, n_batch, seq, n_seq,
                        bg_table, n_bg, n_quad, step, frame_index);
+    }
 }
 
 }  // namespace gft

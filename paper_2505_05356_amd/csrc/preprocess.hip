@@ -402,8 +402,10 @@ void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_
     const int threads = 256;
     const unsigned blocks = (unsigned)((P.n + threads - 1) / threads);
     if (blocks == 0) return;
+    { ProfScope _p("k_preprocess", s);
     hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec, w.rect,
                        w.cnt, w.dkey[0], w.dval[0], w.status);
+    }
 }
 
 void launch_preprocess_bwd(const Params& P, const gftorf_gaussians& g, const gftorf_frame* frames,
@@ -411,8 +413,10 @@ void launch_preprocess_bwd(const Params& P, const gftorf_gaussians& g, const gft
     const int threads = 256;
     const unsigned blocks = (unsigned)((P.n + threads - 1) / threads);
     if (blocks == 0) return;
+    { ProfScope _p("k_preprocess_bwd", s);
     hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.cnt,
                        w.grec, grad);
+    }
 }
 
 }  // namespace gft

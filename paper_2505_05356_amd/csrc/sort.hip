@@ -349,26 +349,36 @@ void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32
                 hipStream_t s) {
     const long long stride = w.max_sort_tiles;
     const unsigned g = grid_for(max_items, kSortTile, 2048);
+    { ProfScope _p("k_sort_upsweep", s);
     hipLaunchKernelGGL(k_sort_upsweep, dim3(g), dim3(kSortThreads), 0, s, kin, cn, shift, nbits,
                        w.counts, stride);
+    }
+    { ProfScope _p("k_sort_scan", s);
     hipLaunchKernelGGL(k_sort_scan, dim3(1u << nbits), dim3(256), 0, s, w.counts, cn, stride,
                        w.totals);
+    }
+    { ProfScope _p("k_sort_downsweep", s);
     hipLaunchKernelGGL(k_sort_downsweep, dim3(g), dim3(kSortThreads), 0, s, kin, vin, kout, vout,
                        cn, shift, nbits, w.counts, w.totals, stride);
+    }
 }
 
 }  // namespace
 
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
+    { ProfScope _p("k_fill_u32", s);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256 * 4, 4096)), dim3(256), 0, s, p, v,
                        (long long)n);
+    }
 }
 
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
+    { ProfScope _p("k_fill_f32", s);
     hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256 * 4, 4096)), dim3(256), 0, s, p, v,
                        (long long)n);
+    }
 }
 
 // Depth sort of the M items (32-bit keys, 4 passes of 8 bits); the sorted
@@ -387,13 +397,19 @@ void launch_depth_sort(const Params& P, const Workspace& w, hipStream_t s, int* 
 void launch_emit(const Params& P, const Workspace& w, int dbuf, hipStream_t s) {
     const unsigned chunks = (unsigned)w.n_chunks;
     if (chunks)
+        { ProfScope _p("k_emit_count", s);
         hipLaunchKernelGGL(k_emit_count, dim3(chunks), dim3(kEmitThreads), 0, s, w.dval[dbuf], w.cnt,
                            (long long)w.M, w.chunk_sum);
+        }
+    { ProfScope _p("k_emit_scan", s);
     hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(1024), 0, s, w.chunk_sum, (long long)w.n_chunks,
                        w.status, (unsigned long long)P.cap);
+    }
     if (chunks)
+        { ProfScope _p("k_emit", s);
         hipLaunchKernelGGL(k_emit, dim3(chunks), dim3(kEmitThreads), 0, s, P, w.dval[dbuf], w.cnt,
                            w.rect, w.chunk_sum, (long long)w.M, w.tkey[0], w.tval[0]);
+        }
 }
 
 // Stable sort of the pairs by (frame, tile); returns the buffer holding the result.
@@ -416,8 +432,10 @@ int launch_tile_sort(const Params& P, const Workspace& w, hipStream_t s) {
 void launch_ranges(const Params& P, const Workspace& w, int tbuf, hipStream_t s) {
     launch_fill_u32(reinterpret_cast<uint32_t*>(w.ranges), 0u, 2ll * P.F * P.n_tiles, s);
     Count cn{&w.status->n_pairs, 0ull, (unsigned long long)P.cap};
+    { ProfScope _p("k_ranges", s);
     hipLaunchKernelGGL(k_ranges, dim3(grid_for((long long)P.cap, 256 * 8, 8192)), dim3(256), 0, s,
                        w.tkey[tbuf], cn, w.ranges);
+    }
 }
 
 }  // namespace gft

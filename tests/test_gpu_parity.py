@@ -51,7 +51,7 @@ def _oracle(name, cache, upstream=False):
         wl = CASES[name]
         up = scenes.upstream_grads(len(wl.frames), wl.cfg, seed=1) if upstream else None
         if upstream:
-            base = _oracle(name, cache, False)
+            base = _oracle(name, cache, False)[0]
             up = mask_upstream(up, ~base["flagged"])
         cache[key] = (oref.render(wl.gaussians, wl.frames, wl.cfg, upstream=up), up)
     return cache[key]
