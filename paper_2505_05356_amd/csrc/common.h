@@ -21,6 +21,10 @@ constexpr int kSortBuckets = 256;                       // <= 8 digit bits per p
 constexpr int kEmitThreads = 256;
 constexpr int kEmitItems = 4;
 constexpr int kEmitChunk = kEmitThreads * kEmitItems;  // 1024
+// Pair writing is balanced by pairs, not items: each workgroup writes
+// kPairsPerBlock consecutive pairs, 8 per thread.
+constexpr int kPairsPerThread = 8;
+constexpr int kPairsPerBlock = kEmitThreads * kPairsPerThread;  // 2048
 
 // Per-(frame, Gaussian) record in float4 units.
 //   r0 = {u_hi, v_hi, u_lo, v_lo}   pixel centre as an unevaluated float pair
@@ -65,6 +69,8 @@ struct Workspace {
     uint32_t* dkey[2];      // [M] depth keys (double buffer)
     uint32_t* dval[2];      // [M] item ids
     unsigned long long* chunk_sum;  // [n_chunks + 1] emission chunk sums / offsets
+    unsigned long long* off;        // [M + 1] first pair of each depth-sorted item
+    uint32_t* first;                // [cap / kPairsPerBlock + 1] item holding each block's first pair
     uint32_t* tkey[2];      // [cap] (frame, tile) keys
     uint32_t* tval[2];      // [cap] item ids
     uint32_t* counts;       // [256][max_sort_tiles] per-tile digit counts
@@ -100,6 +106,8 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int n_tiles, ui
     for (int i = 0; i < 2; ++i) w.dkey[i] = reinterpret_cast<uint32_t*>(take(4 * M));
     for (int i = 0; i < 2; ++i) w.dval[i] = reinterpret_cast<uint32_t*>(take(4 * M));
     w.chunk_sum = reinterpret_cast<unsigned long long*>(take(8 * (w.n_chunks + 1)));
+    w.off = reinterpret_cast<unsigned long long*>(take(8 * (M + 1)));
+    w.first = reinterpret_cast<uint32_t*>(take(4 * (cap / kPairsPerBlock + 2)));
     for (int i = 0; i < 2; ++i) w.tkey[i] = reinterpret_cast<uint32_t*>(take(4 * cap));
     for (int i = 0; i < 2; ++i) w.tval[i] = reinterpret_cast<uint32_t*>(take(4 * cap));
     w.counts = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets * w.max_sort_tiles));

@@ -61,6 +61,61 @@ __device__ __forceinline__ float wave_sum(float v) {
             __builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 63)));
 }
 
+// Value of the lane whose index differs from this lane's in bit log2(D) and
+// agrees in all lower bits (rotations within a row of 16 satisfy this for
+// D = 4 and D = 8; D >= 16 uses a full cross-lane permute).
+template <int D>
+__device__ __forceinline__ float xchg(float x) {
+    if constexpr (D == 1) return dpp_f32<0xb1>(x);          // quad_perm [1,0,3,2]
+    else if constexpr (D == 2) return dpp_f32<0x4e>(x);     // quad_perm [2,3,0,1]
+    else if constexpr (D == 4) return dpp_f32<0x124>(x);    // row_ror:4
+    else if constexpr (D == 8) return dpp_f32<0x128>(x);    // row_ror:8
+    else return __shfl_xor(x, D, 64);
+}
+
+// Reduce-scatter of NP per-lane fields by butterfly: at distance D each lane
+// keeps the half of its live fields selected by bit log2(D) of its lane index
+// and adds the partner's copy of that half.  NP - 1 exchanges instead of
+// NP * log2(64) for NP independent reductions.
+template <int NP, int D = 1>
+__device__ __forceinline__ void butterfly(float* v, int lane) {
+    if constexpr (D < NP) {
+        constexpr int H = NP / (2 * D);
+        const bool hi = (lane & D) != 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const float send = hi ? v[i] : v[i + H];
+            const float keep = hi ? v[i + H] : v[i];
+            v[i] = keep + xchg<D>(send);
+        }
+        butterfly<NP, 2 * D>(v, lane);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ float allreduce_from(float r) {
+    if constexpr (D < 64) return allreduce_from<2 * D>(r + xchg<D>(r));
+    else return r;
+}
+
+// Field whose wave total lane `lane` holds after wave_reduce_fields<NP>.
+template <int NP>
+__device__ __forceinline__ int field_of_lane(int lane) {
+    int f = 0;
+#pragma unroll
+    for (int D = 1; D < NP; D *= 2)
+        if (lane & D) f += NP / (2 * D);
+    return f;
+}
+
+// Sums v[0..NP) over the 64 lanes; returns, in every lane, the total of
+// field field_of_lane<NP>(lane).
+template <int NP>
+__device__ __forceinline__ float wave_reduce_fields(float (&v)[NP], int lane) {
+    butterfly<NP>(v, lane);
+    return allreduce_from<NP>(v[0]);
+}
+
 template <int TW, int TH, int NF>
 __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftorf_frame* __restrict__ frames,
                                                            const uint2* __restrict__ ranges,
@@ -165,7 +220,8 @@ __global__ void __launch_bounds__(TW * TH) k_composite_bwd(
     constexpr int BS = TW * TH;
     constexpr int RS4 = record_float4s(NF);
     constexpr int GS = grad_floats(NF);
-    constexpr int NG = 10 + 2 * NF;
+    constexpr int NG = 10 + 2 * NF;            // gradient fields per entry
+    constexpr int NGP = NG <= 16 ? 16 : 32;    // padded to a power of two
     __shared__ float4 srec[RS4][BS];
     __shared__ uint32_t sitem[BS];
     __shared__ uint32_t smax;
@@ -260,9 +316,9 @@ __global__ void __launch_bounds__(TW * TH) k_composite_bwd(
             const float a = splat_alpha(r0, r1, fpx, fpy, amax, dx, dy, G);
             const bool act = (kidx < last) && (a >= amin);
             if (__ballot(act) == 0ull) continue;
-            float g[NG];
+            float g[NGP];
 #pragma unroll
-            for (int i = 0; i < NG; ++i) g[i] = 0.f;
+            for (int i = 0; i < NGP; ++i) g[i] = 0.f;
             if (act) {
                 const float4 r2 = srec[2][s];
                 const float om = 1.0f - a;
@@ -303,12 +359,12 @@ __global__ void __launch_bounds__(TW * TH) k_composite_bwd(
                     g[1] = -gq * (2.0f * r1.z * dy + r1.y * dx);    // d/dv
                 }
             }
-            float* dst = grec + (size_t)sitem[s] * GS;
-#pragma unroll
-            for (int i = 0; i < NG; ++i) {
-                const float v = wave_sum(g[i]);
-                if (lane == 0 && v != 0.f) atomicAdd(dst + i, v);
-            }
+            // one reduce-scatter over the wave, then one atomic instruction whose
+            // lanes add consecutive fields of the entry's gradient record
+            const float tot = wave_reduce_fields<NGP>(g, lane);
+            const int fld = field_of_lane<NGP>(lane);
+            if (lane < NGP && fld < NG && tot != 0.f)
+                atomicAdd(grec + (size_t)sitem[s] * GS + fld, tot);
         }
         hi = lo;
     }

@@ -39,6 +39,7 @@ __device__ __forceinline__ unsigned long long get_n(const Count& c) {
     return v < c.cap ? v : c.cap;
 }
 
+template <int TAG>  // 0: depth sort of items, 1: (frame, tile) sort of pairs
 __global__ void __launch_bounds__(kSortThreads) k_sort_upsweep(const uint32_t* __restrict__ keys,
                                                                Count cn, int shift, int nbits,
                                                                uint32_t* __restrict__ counts,
@@ -65,6 +66,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_upsweep(const uint32_t* _
 }
 
 // One workgroup per digit: exclusive scan of that digit's per-tile counts.
+template <int TAG>
 __global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ counts, Count cn,
                                                    long long stride, uint32_t* __restrict__ totals) {
     __shared__ uint32_t scratch[8];
@@ -95,6 +97,7 @@ __global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ counts
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+template <int TAG>  // 0: depth sort of items, 1: (frame, tile) sort of pairs
 __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     uint32_t* __restrict__ vout, Count cn, int shift, int nbits, const uint32_t* __restrict__ counts,
@@ -227,7 +230,8 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit_count(const uint32_t* __r
 // Single workgroup: chunk sums -> exclusive offsets; total pairs and overflow.
 __global__ void __launch_bounds__(1024) k_emit_scan(unsigned long long* __restrict__ chunk_sum,
                                                     long long n_chunks, Status* status,
-                                                    unsigned long long cap) {
+                                                    unsigned long long cap,
+                                                    unsigned long long* __restrict__ off_end) {
     __shared__ unsigned long long scratch[17];
     unsigned long long carry = 0;
     for (long long base = 0; base < n_chunks; base += 1024) {
@@ -240,6 +244,7 @@ __global__ void __launch_bounds__(1024) k_emit_scan(unsigned long long* __restri
     }
     if (threadIdx.x == 0) {
         chunk_sum[n_chunks] = carry;
+        *off_end = carry;
         status->n_pairs = carry;
         status->cap = cap;
         status->overflow = carry > cap ? 1u : 0u;
@@ -247,18 +252,15 @@ __global__ void __launch_bounds__(1024) k_emit_scan(unsigned long long* __restri
 }
 
 // Each workgroup takes 1024 consecutive depth-sorted items, scans their tile
-// counts and writes their pairs with one thread per pair position, found by
-// binary search over the local offsets: stores are fully coalesced however
-// unevenly the tile counts are distributed.
-__global__ void __launch_bounds__(kEmitThreads) k_emit(Params P, const uint32_t* __restrict__ dval,
-                                                       const uint32_t* __restrict__ cnt,
-                                                       const uint2* __restrict__ rect,
-                                                       const unsigned long long* __restrict__ chunk_off,
-                                                       long long M, uint32_t* __restrict__ tkey,
-                                                       uint32_t* __restrict__ tval) {
-    __shared__ uint32_t loff[kEmitChunk + 1];
-    __shared__ uint32_t litem[kEmitChunk];
-    __shared__ uint2 lrect[kEmitChunk];
+// counts and writes every item's first pair position; every item also marks
+// the pair blocks whose first pair it owns, so the pair-writing kernel needs
+// no search over the items.
+__global__ void __launch_bounds__(kEmitThreads) k_emit_offsets(Params P, const uint32_t* __restrict__ dval,
+                                                               const uint32_t* __restrict__ cnt,
+                                                               const unsigned long long* __restrict__ chunk_off,
+                                                               long long M,
+                                                               unsigned long long* __restrict__ off,
+                                                               uint32_t* __restrict__ first) {
     __shared__ uint32_t scratch[kEmitThreads / 64 + 1];
     const long long j0 = (long long)blockIdx.x * kEmitChunk;
     const int t = threadIdx.x;
@@ -266,51 +268,122 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(Params P, const uint32_t*
     uint32_t s = 0;
 #pragma unroll
     for (int r = 0; r < kEmitItems; ++r) {
-        const int slot = t * kEmitItems + r;
-        const long long j = j0 + slot;
-        uint32_t item = 0, cc = 0;
-        uint2 rc = make_uint2(0, 0);
-        if (j < M) {
-            item = dval[j];
-            cc = cnt[item];
-            if (cc) rc = rect[item];
-        }
-        litem[slot] = item;
-        lrect[slot] = rc;
-        c[r] = cc;
-        s += cc;
+        const long long j = j0 + t * kEmitItems + r;
+        c[r] = j < M ? cnt[dval[j]] : 0u;
+        s += c[r];
     }
     uint32_t total;
     uint32_t ex = block_exclusive_scan<uint32_t, kEmitThreads>(s, scratch, &total);
+    const unsigned long long base = chunk_off[blockIdx.x];
+    const unsigned long long cap = P.cap;
 #pragma unroll
     for (int r = 0; r < kEmitItems; ++r) {
-        loff[t * kEmitItems + r] = ex;
+        const long long j = j0 + t * kEmitItems + r;
+        if (j < M) {
+            const unsigned long long o = base + ex;
+            off[j] = o;
+            if (c[r]) {
+                const unsigned long long e = o + c[r];
+                for (unsigned long long b = (o + kPairsPerBlock - 1) / kPairsPerBlock;
+                     b * kPairsPerBlock < e && b * kPairsPerBlock < cap; ++b)
+                    first[b] = (uint32_t)j;
+            }
+        }
         ex += c[r];
     }
-    if (t == 0) loff[kEmitChunk] = total;
-    __syncthreads();
-    const unsigned long long cbase = chunk_off[blockIdx.x];
-    const unsigned long long cap = P.cap;
+}
+
+// Pair writing, balanced by pairs: workgroup b writes pairs
+// [b * 2048, (b + 1) * 2048), each thread 8 consecutive pairs (two 16-byte
+// stores per array).  The items overlapping the block are staged in LDS from
+// first[b]; a thread finds its first item by binary search and then walks.
+__global__ void __launch_bounds__(kEmitThreads) k_emit_pairs(Params P, const uint32_t* __restrict__ dval,
+                                                             const uint2* __restrict__ rect,
+                                                             const unsigned long long* __restrict__ off,
+                                                             const uint32_t* __restrict__ first,
+                                                             long long M, const Status* __restrict__ status,
+                                                             uint32_t* __restrict__ tkey,
+                                                             uint32_t* __restrict__ tval) {
+    constexpr int PB = kPairsPerBlock;
+    __shared__ int loff[PB + 2];
+    __shared__ uint32_t litem[PB + 1];
+    __shared__ uint32_t lbase[PB + 1];
+    __shared__ uint16_t lw[PB + 1];
+    const unsigned long long np_all = status->n_pairs < P.cap ? status->n_pairs : P.cap;
+    const unsigned long long b0 = (unsigned long long)blockIdx.x * PB;
+    if (b0 >= np_all) return;
+    const int npairs = (int)((np_all - b0) < (unsigned long long)PB ? (np_all - b0) : PB);
+    const uint32_t j0 = first[blockIdx.x];
+    const int t = threadIdx.x;
     const uint32_t n = (uint32_t)P.n;
-    for (uint32_t p = t; p < total; p += kEmitThreads) {
-        const unsigned long long gp = cbase + p;
-        if (gp >= cap) break;
-        // last slot with loff[slot] <= p
-        int lo = 0, hi = kEmitChunk;   // invariant: loff[lo] <= p < loff[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (loff[mid] <= p) lo = mid; else hi = mid;
+    for (int i = t; i < PB + 1; i += kEmitThreads) {
+        const long long j = (long long)j0 + i;
+        int lo = 0x7fffffff;
+        uint32_t item = 0, kb = 0;
+        uint16_t w = 1;
+        if (j < M) {
+            const unsigned long long o = off[j];
+            if (o < b0 + (unsigned long long)npairs) {
+                lo = (int)((long long)o - (long long)b0);
+                item = dval[j];
+                const uint2 rc = rect[item];
+                const uint32_t xlo = rc.x & 0xffff, xhi = rc.x >> 16, ylo = rc.y & 0xffff;
+                w = (uint16_t)(xhi - xlo + 1);
+                kb = (item / n) * (uint32_t)P.n_tiles + ylo * (uint32_t)P.ntx + xlo;
+            }
         }
-        const uint32_t local = p - loff[lo];
-        const uint2 rc = lrect[lo];
-        const uint32_t xlo = rc.x & 0xffff, xhi = rc.x >> 16, ylo = rc.y & 0xffff;
-        const uint32_t w = xhi - xlo + 1;
-        const uint32_t ty = ylo + local / w;
-        const uint32_t tx = xlo + local % w;
-        const uint32_t item = litem[lo];
-        const uint32_t f = item / n;
-        tkey[gp] = f * (uint32_t)P.n_tiles + ty * (uint32_t)P.ntx + tx;
-        tval[gp] = item;
+        loff[i] = lo;
+        litem[i] = item;
+        lbase[i] = kb;
+        lw[i] = w;
+    }
+    if (t == 0) loff[PB + 1] = 0x7fffffff;
+    __syncthreads();
+    const int p0 = t * kPairsPerThread;
+    if (p0 >= npairs) return;
+    int lo = 0, hi = PB + 1;   // loff[lo] <= p0 < loff[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (loff[mid] <= p0) lo = mid; else hi = mid;
+    }
+    int slot = lo;
+    uint32_t item = litem[slot], kb = lbase[slot], w = lw[slot];
+    const uint32_t ntx = (uint32_t)P.ntx;
+    uint32_t local = (uint32_t)(p0 - loff[slot]);
+    uint32_t ty = local / w, tx = local - ty * w;
+    int next = loff[slot + 1];
+    uint32_t k[kPairsPerThread], v[kPairsPerThread];
+#pragma unroll
+    for (int q = 0; q < kPairsPerThread; ++q) {
+        const int p = p0 + q;
+        if (p == next) {
+            ++slot;
+            item = litem[slot];
+            kb = lbase[slot];
+            w = lw[slot];
+            tx = ty = 0;
+            next = loff[slot + 1];
+        }
+        k[q] = kb + ty * ntx + tx;
+        v[q] = item;
+        if (++tx == w) {
+            tx = 0;
+            ++ty;
+        }
+    }
+    const unsigned long long g = b0 + p0;
+    if (p0 + kPairsPerThread <= npairs) {
+        uint4* kd = reinterpret_cast<uint4*>(tkey + g);
+        uint4* vd = reinterpret_cast<uint4*>(tval + g);
+        kd[0] = make_uint4(k[0], k[1], k[2], k[3]);
+        kd[1] = make_uint4(k[4], k[5], k[6], k[7]);
+        vd[0] = make_uint4(v[0], v[1], v[2], v[3]);
+        vd[1] = make_uint4(v[4], v[5], v[6], v[7]);
+    } else {
+        for (int q = 0; q < npairs - p0; ++q) {
+            tkey[g + q] = k[q];
+            tval[g + q] = v[q];
+        }
     }
 }
 
@@ -343,23 +416,31 @@ unsigned grid_for(long long items, long long per_block, unsigned cap_blocks) {
     return (unsigned)b;
 }
 
-// One stable LSD pass; returns nothing, ping-pong managed by the caller.
+// One stable LSD pass; ping-pong is managed by the caller.  TAG only names
+// the instantiation (depth or pair sort) for profiling.
+template <int TAG>
 void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                 const Count& cn, long long max_items, int shift, int nbits, const Workspace& w,
                 hipStream_t s) {
+    static const char* names[2][3] = {
+        {"k_sort_upsweep<depth>", "k_sort_scan<depth>", "k_sort_downsweep<depth>"},
+        {"k_sort_upsweep<pairs>", "k_sort_scan<pairs>", "k_sort_downsweep<pairs>"}};
     const long long stride = w.max_sort_tiles;
     const unsigned g = grid_for(max_items, kSortTile, 2048);
-    { ProfScope _p("k_sort_upsweep", s);
-    hipLaunchKernelGGL(k_sort_upsweep, dim3(g), dim3(kSortThreads), 0, s, kin, cn, shift, nbits,
-                       w.counts, stride);
+    {
+        ProfScope _p(names[TAG][0], s);
+        hipLaunchKernelGGL(k_sort_upsweep<TAG>, dim3(g), dim3(kSortThreads), 0, s, kin, cn, shift,
+                           nbits, w.counts, stride);
     }
-    { ProfScope _p("k_sort_scan", s);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1u << nbits), dim3(256), 0, s, w.counts, cn, stride,
-                       w.totals);
+    {
+        ProfScope _p(names[TAG][1], s);
+        hipLaunchKernelGGL(k_sort_scan<TAG>, dim3(1u << nbits), dim3(256), 0, s, w.counts, cn, stride,
+                           w.totals);
     }
-    { ProfScope _p("k_sort_downsweep", s);
-    hipLaunchKernelGGL(k_sort_downsweep, dim3(g), dim3(kSortThreads), 0, s, kin, vin, kout, vout,
-                       cn, shift, nbits, w.counts, w.totals, stride);
+    {
+        ProfScope _p(names[TAG][2], s);
+        hipLaunchKernelGGL(k_sort_downsweep<TAG>, dim3(g), dim3(kSortThreads), 0, s, kin, vin, kout,
+                           vout, cn, shift, nbits, w.counts, w.totals, stride);
     }
 }
 
@@ -387,8 +468,8 @@ void launch_depth_sort(const Params& P, const Workspace& w, hipStream_t s, int* 
     Count cn{nullptr, (unsigned long long)w.M, (unsigned long long)w.M};
     int cur = 0;
     for (int pass = 0; pass < 4; ++pass) {
-        radix_pass(w.dkey[cur], w.dval[cur], w.dkey[cur ^ 1], w.dval[cur ^ 1], cn, w.M, 8 * pass, 8,
-                   w, s);
+        radix_pass<0>(w.dkey[cur], w.dval[cur], w.dkey[cur ^ 1], w.dval[cur ^ 1], cn, w.M, 8 * pass,
+                      8, w, s);
         cur ^= 1;
     }
     *result_buf = cur;
@@ -396,20 +477,28 @@ void launch_depth_sort(const Params& P, const Workspace& w, hipStream_t s, int* 
 
 void launch_emit(const Params& P, const Workspace& w, int dbuf, hipStream_t s) {
     const unsigned chunks = (unsigned)w.n_chunks;
-    if (chunks)
-        { ProfScope _p("k_emit_count", s);
+    if (chunks) {
+        ProfScope _p("k_emit_count", s);
         hipLaunchKernelGGL(k_emit_count, dim3(chunks), dim3(kEmitThreads), 0, s, w.dval[dbuf], w.cnt,
                            (long long)w.M, w.chunk_sum);
-        }
-    { ProfScope _p("k_emit_scan", s);
-    hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(1024), 0, s, w.chunk_sum, (long long)w.n_chunks,
-                       w.status, (unsigned long long)P.cap);
     }
-    if (chunks)
-        { ProfScope _p("k_emit", s);
-        hipLaunchKernelGGL(k_emit, dim3(chunks), dim3(kEmitThreads), 0, s, P, w.dval[dbuf], w.cnt,
-                           w.rect, w.chunk_sum, (long long)w.M, w.tkey[0], w.tval[0]);
-        }
+    {
+        ProfScope _p("k_emit_scan", s);
+        hipLaunchKernelGGL(k_emit_scan, dim3(1), dim3(1024), 0, s, w.chunk_sum, (long long)w.n_chunks,
+                           w.status, (unsigned long long)P.cap, w.off + w.M);
+    }
+    if (chunks) {
+        ProfScope _p("k_emit_offsets", s);
+        hipLaunchKernelGGL(k_emit_offsets, dim3(chunks), dim3(kEmitThreads), 0, s, P, w.dval[dbuf],
+                           w.cnt, w.chunk_sum, (long long)w.M, w.off, w.first);
+    }
+    const unsigned long long blocks = (P.cap + kPairsPerBlock - 1) / kPairsPerBlock;
+    if (blocks) {
+        ProfScope _p("k_emit_pairs", s);
+        hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)blocks), dim3(kEmitThreads), 0, s, P,
+                           w.dval[dbuf], w.rect, w.off, w.first, (long long)w.M, w.status, w.tkey[0],
+                           w.tval[0]);
+    }
 }
 
 // Stable sort of the pairs by (frame, tile); returns the buffer holding the result.
@@ -421,8 +510,8 @@ int launch_tile_sort(const Params& P, const Workspace& w, hipStream_t s) {
     int cur = 0, shift = 0;
     for (int pass = 0; pass < passes; ++pass) {
         const int nb = (shift + per <= bits) ? per : bits - shift;
-        radix_pass(w.tkey[cur], w.tval[cur], w.tkey[cur ^ 1], w.tval[cur ^ 1], cn, (long long)P.cap,
-                   shift, nb, w, s);
+        radix_pass<1>(w.tkey[cur], w.tval[cur], w.tkey[cur ^ 1], w.tval[cur ^ 1], cn,
+                      (long long)P.cap, shift, nb, w, s);
         cur ^= 1;
         shift += nb;
     }
