@@ -32,10 +32,15 @@ HBM_PEAK_GBS = 8000.0
 # them disabled): 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz.
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
-# Algorithmic work per unit (measurement section).
-FWD_FLOP_PER_EVAL = 12      # dx, dy (4 sub), quadratic form (3 mul + 2 fma = 7), exp2 1
-FWD_FLOP_PER_COMP = 16      # 1 - a, T(1-a), w1, w2 (4) + 6 FMA (rgb 3, depth 1, S, C) = 12 flop
-BWD_FLOP_PER_COMP = 70      # per composited (pixel, entry) in the backward
+# Algorithmic work per unit (measurement section), NF = 1:
+#   alpha evaluation: dx, dy (4 sub), quadratic form (3 mul + 2 fma), exp2, o*G  -> 12
+#   forward composite: 1 - a, T(1 - a), w1, w2 (4) + 6 FMA (rgb 3, depth 1, S, C) -> 16
+#   backward composite: T / (1 - a), S2 terms for rgb and depth (16), S3 terms (11),
+#     background term (3), weights (2), per-Gaussian colour / depth / phasor grads (6),
+#     accumulator updates (20), chain to o, conic, centre (17), field sums (12)    -> 87
+FLOP_PER_EVAL = 12
+FWD_FLOP_PER_COMP = 16
+BWD_FLOP_PER_COMP = 87
 SORT_BYTES_PER_KEY_PASS = 16  # read key + value, write key + value (4 B each)
 
 
@@ -154,8 +159,10 @@ def main():
     kern = {k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1), total_ms=v[1])
             for k, v in kt.totals.items()}
     dominant = max(kern, key=lambda k: kern[k]["total_ms"])
-    E = int(out["n_contrib"].sum().item())   # composited-through (pixel, entry) evaluations
-    roof = roofline(dominant, kern[dominant]["avg_ms"], P=P, M=g.n * F, E=E)
+    st = ws.status()
+    work = dict(P=P, E_fwd=st["n_evaluated"], C=st["n_composited"],
+                E_bwd=int(out["n_contrib"].sum().item()))   # backward walks up to n_contrib
+    roof = roofline(dominant, kern[dominant]["avg_ms"], **work)
     print("# kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f}ms x{v['launches'] // args.steps}"
                                     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["total_ms"])),
           file=sys.stderr, flush=True)
@@ -180,7 +187,8 @@ def main():
         "config": {"workload": f"dynamic-{g.n // 1000}k-gaussians-{F}f-{cfg.width}x{cfg.height}",
                    "n_gaussians": g.n, "frames": F, "width": cfg.width, "height": cfg.height,
                    "tile": args.tile, "freqs_hz": list(cfg.freqs), "quads": cfg.n_quad,
-                   "outputs": "rgb+quad+depth", "pairs": P, "evals_E": E},
+                   "outputs": "rgb+quad+depth", "pairs": P, "evals_fwd": work["E_fwd"],
+                   "evals_bwd": work["E_bwd"], "composited": work["C"]},
         "per_frame_value": None if per_frame is None else round(per_frame, 2),
         "batched_over_per_frame": None if per_frame is None else round(value / per_frame, 3),
         "roofline": roof,
@@ -190,30 +198,28 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def roofline(name, avg_ms, P, M, E):
+def roofline(name, avg_ms, P, E_fwd, E_bwd, C):
     """Roofline object of the dominant kernel from its algorithmic work."""
     t = avg_ms / 1e3
+    alu = lambda flops, how: dict(
+        bound="alu", achieved=round(flops / t / 1e12, 3), peak=round(ALU_PEAK_TFLOPS, 1),
+        unit="TFLOP/s", frac=round(flops / t / 1e12 / ALU_PEAK_TFLOPS, 4), traffic=None,
+        kernel=name, avg_ms=round(avg_ms, 4), work=f"{flops:.4g} FLOP per launch = {how}")
     if name == "k_composite_fwd":
-        flops = E * (FWD_FLOP_PER_EVAL + FWD_FLOP_PER_COMP)
-        a = flops / t / 1e12
-        return dict(bound="alu", achieved=round(a, 3), peak=round(ALU_PEAK_TFLOPS, 1),
-                    unit="TFLOP/s", frac=round(a / ALU_PEAK_TFLOPS, 4), traffic=None,
-                    work=f"{flops:.4g} FLOP per launch = E x {FWD_FLOP_PER_EVAL + FWD_FLOP_PER_COMP}")
+        return alu(E_fwd * FLOP_PER_EVAL + C * FWD_FLOP_PER_COMP,
+                   f"{E_fwd} evals x {FLOP_PER_EVAL} + {C} composited x {FWD_FLOP_PER_COMP}")
     if name == "k_composite_bwd":
-        flops = E * (FWD_FLOP_PER_EVAL + BWD_FLOP_PER_COMP)
-        a = flops / t / 1e12
-        return dict(bound="alu", achieved=round(a, 3), peak=round(ALU_PEAK_TFLOPS, 1),
-                    unit="TFLOP/s", frac=round(a / ALU_PEAK_TFLOPS, 4), traffic=None,
-                    work=f"{flops:.4g} FLOP per launch = E x {FWD_FLOP_PER_EVAL + BWD_FLOP_PER_COMP}")
+        return alu(E_bwd * FLOP_PER_EVAL + C * BWD_FLOP_PER_COMP,
+                   f"{E_bwd} evals x {FLOP_PER_EVAL} + {C} composited x {BWD_FLOP_PER_COMP}")
     if name == "k_sort_downsweep<pairs>":
-        # the pair sort dominates: bytes per pass over the P pairs
         b = P * SORT_BYTES_PER_KEY_PASS
         a = b / t / 1e9
         return dict(bound="hbm", achieved=round(a, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(a / HBM_PEAK_GBS, 4), traffic=None,
-                    work=f"{b:.4g} B per launch = P x {SORT_BYTES_PER_KEY_PASS}")
+                    frac=round(a / HBM_PEAK_GBS, 4), traffic=None, kernel=name,
+                    avg_ms=round(avg_ms, 4),
+                    work=f"{b:.4g} B per launch = {P} pairs x {SORT_BYTES_PER_KEY_PASS}")
     return dict(bound="hbm", achieved=None, peak=HBM_PEAK_GBS, unit="GB/s", frac=None,
-                traffic=None, work=f"no algorithmic model for {name}")
+                traffic=None, kernel=name, work=f"no algorithmic model for {name}")
 
 
 def cpu_baseline(wl, cfg, up, budget_s):
@@ -237,13 +243,15 @@ def cpu_baseline(wl, cfg, up, budget_s):
         t0 = time.perf_counter()
         oref.render(wl.gaussians, fr, cfg, tiles=[[]], upstream=up0)
         t_fixed = min(t_fixed, time.perf_counter() - t0)
-    done, t_tiles = 0, 0.0
-    while done < n_tiles and t_tiles < budget_s:
-        chunk = order[done:done + 8]
+    done, t_tiles, step = 0, 0.0, 8
+    wall0 = time.perf_counter()
+    while done < n_tiles and t_tiles < budget_s and time.perf_counter() - wall0 < 2.5 * budget_s:
+        chunk = order[done:done + step]
         t0 = time.perf_counter()
         oref.render(wl.gaussians, fr, cfg, tiles=[chunk], upstream=up0)
         t_tiles += max(time.perf_counter() - t0 - t_fixed, 0.0)
         done += len(chunk)
+        step *= 2
     per_tile = t_tiles / max(done, 1)
     per_frame = t_fixed + per_tile * n_tiles
     return {"value": round(1.0 / per_frame, 6), "unit": "frames/s", "cores": torch.get_num_threads(),
@@ -251,7 +259,7 @@ def cpu_baseline(wl, cfg, up, budget_s):
             "sample": f"frame 0 fwd+bwd on {done} of {n_tiles} tiles (seeded order); per frame = "
                       f"{t_fixed:.2f} s fixed (binning + per-Gaussian chain) + {per_tile:.4f} s/tile "
                       f"x {n_tiles} tiles, extrapolated",
-            "measured_s": round(t_tiles + (done // 8 + 3) * t_fixed, 1)}
+            "measured_s": round(time.perf_counter() - wall0 + 3 * t_fixed, 1)}
 
 
 if __name__ == "__main__":

@@ -129,6 +129,8 @@ typedef struct gftorf_status {
     int64_t max_pairs;   /* capacity the workspace was carved for                             */
     int32_t overflow;    /* 1 if n_pairs > max_pairs: the last forward is INVALID              */
     int32_t nonfinite;   /* Gaussians culled because an input was NaN / Inf                   */
+    int64_t n_evaluated; /* (pixel, list entry) opacity evaluations of the last forward       */
+    int64_t n_composited;/* (pixel, list entry) pairs composited by the last forward          */
 } gftorf_status;
 
 /* Bytes of workspace needed for n Gaussians, n_frames frames and cfg

@@ -49,7 +49,7 @@ class OutputsC(ctypes.Structure):
 
 class StatusC(ctypes.Structure):
     _fields_ = [("n_pairs", c_int64), ("max_pairs", c_int64), ("overflow", c_int32),
-                ("nonfinite", c_int32)]
+                ("nonfinite", c_int32), ("n_evaluated", c_int64), ("n_composited", c_int64)]
 
 
 class AdamGroupC(ctypes.Structure):

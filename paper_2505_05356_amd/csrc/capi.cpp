@@ -146,7 +146,9 @@ int gftorf_profile_begin(int32_t max_launches) {
     g_prof = Profiler();
     g_prof.events.resize(2 * (size_t)max_launches);
     for (auto& e : g_prof.events) {
-        hipError_t r = hipEventCreate(&e);
+        // device-scope release: the timestamps do not wait for a system-scope
+        // cache write-back, which would inflate the measured kernel time
+        hipError_t r = hipEventCreateWithFlags(&e, hipEventReleaseToDevice);
         if (r != hipSuccess) return hip_fail(r, "gftorf_profile_begin");
     }
     for (int i = max_launches - 1; i >= 0; --i) g_prof.free_slots.push_back(2 * i);
@@ -267,6 +269,8 @@ int gftorf_read_status(const void* ws, gftorf_status* out, void* stream) {
     out->max_pairs = (int64_t)st.cap;
     out->overflow = (int32_t)st.overflow;
     out->nonfinite = (int32_t)st.nonfinite;
+    out->n_evaluated = (int64_t)st.n_eval;
+    out->n_composited = (int64_t)st.n_comp;
     if (st.overflow) return fail(GFTORF_EOVERFLOW, "pairs exceeded max_pairs: " + std::to_string(st.n_pairs));
     return GFTORF_OK;
 }

@@ -42,7 +42,9 @@ struct Status {
     unsigned long long cap;       // capacity (max_pairs)
     unsigned int overflow;
     unsigned int nonfinite;
-    unsigned int pad[10];
+    unsigned long long n_eval;   // (pixel, entry) alpha evaluations of the forward
+    unsigned long long n_comp;   // (pixel, entry) pairs composited by the forward
+    unsigned int pad[6];
 };
 
 // Everything a kernel needs to know about a call, passed by value.

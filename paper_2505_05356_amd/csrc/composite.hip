@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
                                                            const uint2* __restrict__ ranges,
                                                            const uint32_t* __restrict__ tval,
                                                            const float4* __restrict__ rec,
-                                                           gftorf_outputs out) {
+                                                           gftorf_outputs out, Status* status) {
     constexpr int BS = TW * TH;
     constexpr int RS4 = record_float4s(NF);
     __shared__ float4 srec[RS4][BS];
@@ -144,6 +144,7 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
     for (int i = 0; i < NF; ++i) S[i] = C[i] = 0.f;
     bool done = !inside;
     uint32_t last = 0;
+    uint32_t n_eval = 0, n_comp = 0;
 
     for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BS) {
         if (__syncthreads_count(!done) == 0) break;
@@ -157,6 +158,7 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
         const int cnt = (int)min((uint32_t)BS, rg.y - b0);
         for (int k = 0; k < cnt; ++k) {
             if (done) continue;
+            ++n_eval;
             const float4 r0 = srec[0][k], r1 = srec[1][k];
             float dx, dy, G;
             const float a = splat_alpha(r0, r1, fpx, fpy, amax, dx, dy, G);
@@ -182,7 +184,20 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
                 C[i] += ac * w2;
             }
             T = nT;
+            ++n_comp;
             last = b0 - rg.x + (uint32_t)k + 1u;
+        }
+    }
+    {   // workload counters (algorithmic FLOP accounting)
+        unsigned long long e = n_eval, c = n_comp;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            e += __shfl_xor(e, o, 64);
+            c += __shfl_xor(c, o, 64);
+        }
+        if ((tid & 63) == 0) {
+            atomicAdd(&status->n_eval, e);
+            atomicAdd(&status->n_comp, c);
         }
     }
     if (!inside) return;
@@ -210,155 +225,169 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
     out.n_contrib[(size_t)f * HW + pix] = (int32_t)last;
 }
 
+// Backward: one wave per (frame, tile); each lane owns PPT pixels of the tile
+// (pixel p = lane + 64 i), so the per-entry cross-lane reduction of the
+// gradient fields is paid once for PPT pixels.
 template <int TW, int TH, int NF>
-__global__ void __launch_bounds__(TW * TH) k_composite_bwd(
+__global__ void __launch_bounds__(64) k_composite_bwd(
     Params P, const gftorf_frame* __restrict__ frames, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ tval, const float4* __restrict__ rec,
     const float* __restrict__ T_final, const int32_t* __restrict__ n_contrib,
     const float* __restrict__ d_rgb, const float* __restrict__ d_quad, const float* __restrict__ d_depth,
     float* __restrict__ grec, float* __restrict__ d_bg) {
-    constexpr int BS = TW * TH;
+    constexpr int PPT = TW * TH / 64;          // pixels per lane
+    constexpr int B = 64;                      // list entries staged per batch
     constexpr int RS4 = record_float4s(NF);
     constexpr int GS = grad_floats(NF);
     constexpr int NG = 10 + 2 * NF;            // gradient fields per entry
     constexpr int NGP = NG <= 16 ? 16 : 32;    // padded to a power of two
-    __shared__ float4 srec[RS4][BS];
-    __shared__ uint32_t sitem[BS];
-    __shared__ uint32_t smax;
+    __shared__ float4 srec[RS4][B];
+    __shared__ uint32_t sitem[B];
 
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     const int f = w / P.n_tiles;
     const int tile = w - f * P.n_tiles;
     const int ty = tile / P.ntx, tx = tile - ty * P.ntx;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int x = tx * TW + (tid % TW), y = ty * TH + (tid / TW);
-    const bool inside = x < P.W && y < P.H;
-    const float fpx = (float)x + 0.5f, fpy = (float)y + 0.5f;
+    const int lane = threadIdx.x;
     const uint2 rg = ranges[w];
     const float amin = P.alpha_min, amax = P.alpha_max;
     const gftorf_frame& fr = frames[f];
     const size_t HW = (size_t)P.H * P.W;
-    const size_t pix = (size_t)y * P.W + x;
 
-    float Tf = 1.f;
-    uint32_t last = 0;
-    float gr[3] = {0.f, 0.f, 0.f}, gd = 0.f;
-    float gS[NF], gC[NF];
+    float fpx[PPT], fpy[PPT], T[PPT], bgT[PPT];
+    uint32_t last[PPT];
+    float gr[PPT][3], gd[PPT], gS[PPT][NF], gC[PPT][NF];
+    float acc_c[PPT][3], acc_d[PPT], acc_s[PPT][NF], acc_k[PPT][NF];
+    float bg_acc[3 + GFTORF_MAX_QUAD];
+    const int nbg = 3 + P.nq;
+    for (int c = 0; c < 3 + GFTORF_MAX_QUAD; ++c) bg_acc[c] = 0.f;
+    uint32_t maxl = 0;
 #pragma unroll
-    for (int i = 0; i < NF; ++i) gS[i] = gC[i] = 0.f;
-    float bg_rgb_dot = 0.f, bg_q_dot = 0.f;
-    float Tp = 1.f;
-    if (inside) {
-        Tf = T_final[(size_t)f * HW + pix];
-        last = (uint32_t)n_contrib[(size_t)f * HW + pix];
-        Tp = P.bg_pow == 2 ? Tf * Tf : Tf;
-        if (d_rgb)
-            for (int c = 0; c < 3; ++c) gr[c] = d_rgb[((size_t)f * 3 + c) * HW + pix];
-        if (d_depth) gd = d_depth[(size_t)f * HW + pix];
-        for (int c = 0; c < 3; ++c) bg_rgb_dot += fr.bg_rgb[c] * gr[c];
-        if (d_quad) {
+    for (int i = 0; i < PPT; ++i) {
+        const int pidx = lane + 64 * i;
+        const int x = tx * TW + pidx % TW, y = ty * TH + pidx / TW;
+        const bool inside = x < P.W && y < P.H;
+        fpx[i] = (float)x + 0.5f;
+        fpy[i] = (float)y + 0.5f;
+        const size_t pix = (size_t)y * P.W + x;
+        float Tf = 1.f, Tp = 1.f, brd = 0.f, bqd = 0.f;
+        last[i] = 0;
+        gr[i][0] = gr[i][1] = gr[i][2] = gd[i] = 0.f;
 #pragma unroll
-            for (int i = 0; i < NF; ++i)
-                for (int jj = 0; jj < P.nphi; ++jj) {
-                    const int qc = i * P.nphi + jj;
-                    const float g = d_quad[((size_t)f * P.nq + qc) * HW + pix];
-                    gS[i] += P.cphi[jj] * g;
-                    gC[i] += P.sphi[jj] * g;
-                    bg_q_dot += fr.bg_quad[qc] * g;
-                }
+        for (int k = 0; k < NF; ++k) gS[i][k] = gC[i][k] = 0.f;
+        if (inside) {
+            Tf = T_final[(size_t)f * HW + pix];
+            last[i] = (uint32_t)n_contrib[(size_t)f * HW + pix];
+            Tp = P.bg_pow == 2 ? Tf * Tf : Tf;
+            if (d_rgb)
+                for (int c = 0; c < 3; ++c) gr[i][c] = d_rgb[((size_t)f * 3 + c) * HW + pix];
+            if (d_depth) gd[i] = d_depth[(size_t)f * HW + pix];
+            for (int c = 0; c < 3; ++c) {
+                brd += fr.bg_rgb[c] * gr[i][c];
+                bg_acc[c] += gr[i][c] * Tf;
+            }
+            if (d_quad) {
+#pragma unroll
+                for (int k = 0; k < NF; ++k)
+                    for (int jj = 0; jj < P.nphi; ++jj) {
+                        const int qc = k * P.nphi + jj;
+                        const float g = d_quad[((size_t)f * P.nq + qc) * HW + pix];
+                        gS[i][k] += P.cphi[jj] * g;
+                        gC[i][k] += P.sphi[jj] * g;
+                        bqd += fr.bg_quad[qc] * g;
+                        bg_acc[3 + qc] += g * Tp;
+                    }
+            }
         }
+        // background terms of dL/dalpha_k, before division by (1 - alpha_k):
+        // c_bg . dL/dc T_final + p q_bg . dL/dq T_final^p
+        bgT[i] = brd * Tf + (float)P.bg_pow * bqd * Tp;
+        T[i] = Tf;
+        acc_c[i][0] = acc_c[i][1] = acc_c[i][2] = acc_d[i] = 0.f;
+#pragma unroll
+        for (int k = 0; k < NF; ++k) acc_s[i][k] = acc_k[i][k] = 0.f;
+        maxl = max(maxl, last[i]);
     }
     // background gradients: dL/dc_bg = sum d_rgb T_final, dL/dq_bg = sum d_quad T_final^p
     if (d_bg) {
-        const int nbg = 3 + P.nq;
         for (int c = 0; c < nbg; ++c) {
-            float v = 0.f;
-            if (inside) {
-                if (c < 3) v = gr[c] * Tf;
-                else if (d_quad) v = d_quad[((size_t)f * P.nq + (c - 3)) * HW + pix] * Tp;
-            }
-            v = wave_sum(v);
+            const float v = wave_sum(bg_acc[c]);
             if (lane == 0 && v != 0.f) atomicAdd(&d_bg[(size_t)f * nbg + c], v);
         }
     }
-    if (tid == 0) smax = 0;
-    __syncthreads();
-    if (last) atomicMax(&smax, last);
-    __syncthreads();
-    const uint32_t maxl = smax;
-    const float bgT_rgb = bg_rgb_dot * Tf;
-    const float bgT_q = (float)P.bg_pow * bg_q_dot * Tp;
-
-    float T = Tf;
-    float acc_c[3] = {0.f, 0.f, 0.f}, acc_d = 0.f;
-    float acc_s[NF], acc_k[NF];
 #pragma unroll
-    for (int i = 0; i < NF; ++i) acc_s[i] = acc_k[i] = 0.f;
+    for (int o = 32; o > 0; o >>= 1) maxl = max(maxl, (uint32_t)__shfl_xor((int)maxl, o, 64));
     const float LN2 = 0.6931471805599453f;
 
     for (uint32_t hi = min(rg.x + maxl, rg.y); hi > rg.x; ) {
-        const uint32_t lo = (hi - rg.x > (uint32_t)BS) ? hi - BS : rg.x;
+        const uint32_t lo = (hi - rg.x > (uint32_t)B) ? hi - B : rg.x;
         const int cnt = (int)(hi - lo);
         __syncthreads();
-        if (tid < cnt) {
-            const uint32_t item = tval[hi - 1 - tid];
-            sitem[tid] = item;
+        if (lane < cnt) {
+            const uint32_t item = tval[hi - 1 - lane];
+            sitem[lane] = item;
             const float4* r = rec + (size_t)item * RS4;
 #pragma unroll
-            for (int q = 0; q < RS4; ++q) srec[q][tid] = r[q];
+            for (int q = 0; q < RS4; ++q) srec[q][lane] = r[q];
         }
         __syncthreads();
         for (int s = 0; s < cnt; ++s) {
             const uint32_t kidx = hi - 1 - (uint32_t)s - rg.x;   // position in the tile list
-            const float4 r0 = srec[0][s], r1 = srec[1][s];
-            float dx, dy, G;
-            const float a = splat_alpha(r0, r1, fpx, fpy, amax, dx, dy, G);
-            const bool act = (kidx < last) && (a >= amin);
-            if (__ballot(act) == 0ull) continue;
+            const float4 r0 = srec[0][s], r1 = srec[1][s], r2 = srec[2][s];
+            float as[NF], ac[NF];
+#pragma unroll
+            for (int k = 0; k < NF; ++k) {
+                const float4 rp = srec[3 + k / 2][s];
+                as[k] = (k & 1) ? rp.z : rp.x;
+                ac[k] = (k & 1) ? rp.w : rp.y;
+            }
             float g[NGP];
 #pragma unroll
-            for (int i = 0; i < NGP; ++i) g[i] = 0.f;
-            if (act) {
-                const float4 r2 = srec[2][s];
-                const float om = 1.0f - a;
-                T = __fdividef(T, om);
-                const float T2 = T * T;
-                float dA = gr[0] * (T * (r2.x - acc_c[0])) + gr[1] * (T * (r2.y - acc_c[1])) +
-                           gr[2] * (T * (r2.z - acc_c[2]));
-                dA += gd * (T * (r2.w - acc_d));
-                dA -= __fdividef(bgT_rgb + bgT_q, om);
-                const float w1 = a * T, w2 = a * T2;
-                g[6] = w1 * gr[0];
-                g[7] = w1 * gr[1];
-                g[8] = w1 * gr[2];
-                g[9] = w1 * gd;
+            for (int q = 0; q < NGP; ++q) g[q] = 0.f;
+            bool any = false;
 #pragma unroll
-                for (int i = 0; i < NF; ++i) {
-                    const float4 rp = srec[3 + i / 2][s];
-                    const float as = (i & 1) ? rp.z : rp.x;
-                    const float ac = (i & 1) ? rp.w : rp.y;
-                    dA += T2 * (gS[i] * (as + 2.0f * (a - 1.0f) * acc_s[i]) +
-                                gC[i] * (ac + 2.0f * (a - 1.0f) * acc_k[i]));
-                    g[10 + 2 * i] = w2 * gS[i];
-                    g[11 + 2 * i] = w2 * gC[i];
-                    acc_s[i] = a * as + om * om * acc_s[i];
-                    acc_k[i] = a * ac + om * om * acc_k[i];
+            for (int i = 0; i < PPT; ++i) {
+                float dx, dy, G;
+                const float a = splat_alpha(r0, r1, fpx[i], fpy[i], amax, dx, dy, G);
+                if (!(kidx < last[i] && a >= amin)) continue;
+                any = true;
+                const float om = 1.0f - a;
+                const float Ti = __fdividef(T[i], om);
+                T[i] = Ti;
+                const float T2 = Ti * Ti;
+                float dA = gr[i][0] * (Ti * (r2.x - acc_c[i][0])) + gr[i][1] * (Ti * (r2.y - acc_c[i][1])) +
+                           gr[i][2] * (Ti * (r2.z - acc_c[i][2]));
+                dA += gd[i] * (Ti * (r2.w - acc_d[i]));
+                dA -= __fdividef(bgT[i], om);
+                const float w1 = a * Ti, w2 = a * T2;
+                g[6] += w1 * gr[i][0];
+                g[7] += w1 * gr[i][1];
+                g[8] += w1 * gr[i][2];
+                g[9] += w1 * gd[i];
+#pragma unroll
+                for (int k = 0; k < NF; ++k) {
+                    dA += T2 * (gS[i][k] * (as[k] + 2.0f * (a - 1.0f) * acc_s[i][k]) +
+                                gC[i][k] * (ac[k] + 2.0f * (a - 1.0f) * acc_k[i][k]));
+                    g[10 + 2 * k] += w2 * gS[i][k];
+                    g[11 + 2 * k] += w2 * gC[i][k];
+                    acc_s[i][k] = a * as[k] + om * om * acc_s[i][k];
+                    acc_k[i][k] = a * ac[k] + om * om * acc_k[i][k];
                 }
-                acc_c[0] = a * r2.x + om * acc_c[0];
-                acc_c[1] = a * r2.y + om * acc_c[1];
-                acc_c[2] = a * r2.z + om * acc_c[2];
-                acc_d = a * r2.w + om * acc_d;
+                acc_c[i][0] = a * r2.x + om * acc_c[i][0];
+                acc_c[i][1] = a * r2.y + om * acc_c[i][1];
+                acc_c[i][2] = a * r2.z + om * acc_c[i][2];
+                acc_d[i] = a * r2.w + om * acc_d[i];
                 if (r1.w * G <= amax) {   // not clamped: alpha = o 2^q
                     const float gq = dA * a * LN2;
-                    g[5] = G * dA;                                  // d/do
-                    g[2] = gq * dx * dx;                            // d/dcA
-                    g[3] = gq * dx * dy;                            // d/dcB
-                    g[4] = gq * dy * dy;                            // d/dcC
-                    g[0] = -gq * (2.0f * r1.x * dx + r1.y * dy);    // d/du
-                    g[1] = -gq * (2.0f * r1.z * dy + r1.y * dx);    // d/dv
+                    g[5] += G * dA;                                  // d/do
+                    g[2] += gq * dx * dx;                            // d/dcA
+                    g[3] += gq * dx * dy;                            // d/dcB
+                    g[4] += gq * dy * dy;                            // d/dcC
+                    g[0] -= gq * (2.0f * r1.x * dx + r1.y * dy);     // d/du
+                    g[1] -= gq * (2.0f * r1.z * dy + r1.y * dx);     // d/dv
                 }
             }
+            if (__ballot(any) == 0ull) continue;
             // one reduce-scatter over the wave, then one atomic instruction whose
             // lanes add consecutive fields of the entry's gradient record
             const float tot = wave_reduce_fields<NGP>(g, lane);
@@ -377,7 +406,7 @@ hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& 
     ProfScope _p("k_composite_fwd", s);
 #define GFT_FWD(NF_)                                                                             \
     hipLaunchKernelGGL((k_composite_fwd<TW, TH, NF_>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, \
-                       w.ranges, w.tval[tbuf], w.rec, out)
+                       w.ranges, w.tval[tbuf], w.rec, out, w.status)
     switch (P.nf) {
         case 1: GFT_FWD(1); break;
         case 2: GFT_FWD(2); break;
@@ -395,7 +424,7 @@ hipError_t bwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& 
     const unsigned blocks = (unsigned)(P.F * P.n_tiles);
     ProfScope _p("k_composite_bwd", s);
 #define GFT_BWD(NF_)                                                                             \
-    hipLaunchKernelGGL((k_composite_bwd<TW, TH, NF_>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, \
+    hipLaunchKernelGGL((k_composite_bwd<TW, TH, NF_>), dim3(blocks), dim3(64), 0, s, P, frames,    \
                        w.ranges, w.tval[tbuf], w.rec, sv.T_final, sv.n_contrib, dr, dq, dd, w.grec, dbg)
     switch (P.nf) {
         case 1: GFT_BWD(1); break;

@@ -147,7 +147,8 @@ class Workspace:
         if rc not in (_lib.OK, _lib.EOVERFLOW):
             _lib.check(rc)
         return dict(n_pairs=st.n_pairs, max_pairs=st.max_pairs, overflow=bool(st.overflow),
-                    nonfinite=st.nonfinite)
+                    nonfinite=st.nonfinite, n_evaluated=st.n_evaluated,
+                    n_composited=st.n_composited)
 
 
 def alloc_outputs(n_frames, cfg, device="cuda", channels=("rgb", "quad", "depth")):
