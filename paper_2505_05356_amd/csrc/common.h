@@ -78,6 +78,7 @@ struct Workspace {
     uint32_t* counts;       // [256][max_sort_tiles] per-tile digit counts
     uint32_t* totals;       // [256]
     uint2* ranges;          // [F * n_tiles]
+    uint2* wcount;          // [F * n_tiles] forward (evaluations, composited) per work item
     float* grec;            // [M][grad_floats]
     int64_t M;
     int64_t n_chunks;
@@ -115,6 +116,7 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int n_tiles, ui
     w.counts = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets * w.max_sort_tiles));
     w.totals = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets));
     w.ranges = reinterpret_cast<uint2*>(take(sizeof(uint2) * (int64_t)F * n_tiles));
+    w.wcount = reinterpret_cast<uint2*>(take(sizeof(uint2) * (int64_t)F * n_tiles));
     w.grec = reinterpret_cast<float*>(take(4 * (size_t)grad_floats(nf) * M));
     w.bytes = off + 256;
     return w;

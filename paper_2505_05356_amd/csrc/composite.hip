@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
                                                            const uint2* __restrict__ ranges,
                                                            const uint32_t* __restrict__ tval,
                                                            const float4* __restrict__ rec,
-                                                           gftorf_outputs out, Status* status) {
+                                                           gftorf_outputs out, uint2* __restrict__ wcount) {
     constexpr int BS = TW * TH;
     constexpr int RS4 = record_float4s(NF);
     __shared__ float4 srec[RS4][BS];
@@ -188,16 +188,24 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
             last = b0 - rg.x + (uint32_t)k + 1u;
         }
     }
-    {   // workload counters (algorithmic FLOP accounting)
-        unsigned long long e = n_eval, c = n_comp;
+    {   // workload counters of this work item (algorithmic FLOP accounting);
+        // summed over work items by k_sum_counts, not by same-address atomics
+        __shared__ uint2 wred[BS / 64];
+        uint32_t e = n_eval, c = n_comp;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
-            e += __shfl_xor(e, o, 64);
-            c += __shfl_xor(c, o, 64);
+            e += (uint32_t)__shfl_xor((int)e, o, 64);
+            c += (uint32_t)__shfl_xor((int)c, o, 64);
         }
-        if ((tid & 63) == 0) {
-            atomicAdd(&status->n_eval, e);
-            atomicAdd(&status->n_comp, c);
+        if ((tid & 63) == 0) wred[tid / 64] = make_uint2(e, c);
+        __syncthreads();
+        if (tid == 0) {
+            uint2 t = wred[0];
+            for (int q = 1; q < BS / 64; ++q) {
+                t.x += wred[q].x;
+                t.y += wred[q].y;
+            }
+            wcount[w] = t;
         }
     }
     if (!inside) return;
@@ -399,21 +407,53 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
     }
 }
 
+__global__ void __launch_bounds__(1024) k_sum_counts(const uint2* __restrict__ wcount, int n,
+                                                     Status* status) {
+    __shared__ unsigned long long scratch[2][16];
+    unsigned long long e = 0, c = 0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        e += wcount[i].x;
+        c += wcount[i].y;
+    }
+    e = wave_reduce_sum(e);
+    c = wave_reduce_sum(c);
+    if (lane_id() == 0) {
+        scratch[0][threadIdx.x / 64] = e;
+        scratch[1][threadIdx.x / 64] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long te = 0, tc = 0;
+        for (int q = 0; q < 16; ++q) {
+            te += scratch[0][q];
+            tc += scratch[1][q];
+        }
+        status->n_eval = te;
+        status->n_comp = tc;
+    }
+}
+
 template <int TW, int TH>
 hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w, int tbuf,
                   const gftorf_outputs& out, hipStream_t s) {
     const unsigned blocks = (unsigned)(P.F * P.n_tiles);
-    ProfScope _p("k_composite_fwd", s);
 #define GFT_FWD(NF_)                                                                             \
     hipLaunchKernelGGL((k_composite_fwd<TW, TH, NF_>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, \
-                       w.ranges, w.tval[tbuf], w.rec, out, w.status)
-    switch (P.nf) {
-        case 1: GFT_FWD(1); break;
-        case 2: GFT_FWD(2); break;
-        case 3: GFT_FWD(3); break;
-        default: GFT_FWD(4); break;
+                       w.ranges, w.tval[tbuf], w.rec, out, w.wcount)
+    {
+        ProfScope _p("k_composite_fwd", s);
+        switch (P.nf) {
+            case 1: GFT_FWD(1); break;
+            case 2: GFT_FWD(2); break;
+            case 3: GFT_FWD(3); break;
+            default: GFT_FWD(4); break;
+        }
     }
 #undef GFT_FWD
+    {
+        ProfScope _q("k_sum_counts", s);
+        hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, w.wcount, (int)blocks, w.status);
+    }
     return hipGetLastError();
 }
 
