@@ -140,9 +140,10 @@ size_t gftorf_workspace_size(int64_t n, int32_t n_frames, const gftorf_config* c
 /* Forward rendering of n_frames frames in one batched launch per stage
  * (paper §3 Eqs. 2, 4, 5; every frame carries its own time, so raw quads
  * of a dynamic scene can be rendered at the instants they were captured).
- * Stages: per (frame, Gaussian) projection and binning -> depth sort ->
- * (tile, Gaussian) pair emission in depth order -> stable sort by
- * (frame, tile) -> per-tile ranges -> front-to-back compositing.
+ * Stages: per (frame, Gaussian) projection and tile rectangle -> stable
+ * frame-major depth sort of the items -> per-tile Gaussian lists built in
+ * depth order (chunk counts, column scan, ordered placement) -> front-to-back
+ * compositing, one workgroup per (frame, tile).
  * The workspace `ws` keeps the sorted lists and per-Gaussian records that
  * gftorf_render_bwd needs: pass the same ws, untouched, to the backward.
  * If the pair count exceeds cfg->max_pairs the outputs are invalid and

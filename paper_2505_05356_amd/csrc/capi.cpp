@@ -28,11 +28,6 @@ bool tile_ok(int tw, int th) {
     return (tw == 8 && th == 8) || (tw == 16 && th == 16) || (tw == 32 && th == 8);
 }
 
-int key_bits_for(int64_t keys) {
-    int b = 1;
-    while ((int64_t(1) << b) < keys) ++b;
-    return b;
-}
 
 int build_params(int64_t n, int32_t F, const gftorf_config* c, gft::Params* P) {
     if (!c) return fail(GFTORF_EINVAL, "config is NULL");
@@ -68,6 +63,9 @@ int build_params(int64_t n, int32_t F, const gftorf_config* c, gft::Params* P) {
     p.nty = (c->height + c->tile_h - 1) / c->tile_h;
     p.n_tiles = p.ntx * p.nty;
     if ((int64_t)p.n_tiles * F > (int64_t)0x7FFFFFFF) return fail(GFTORF_EINVAL, "too many tiles");
+    if (p.n_tiles > gft::kMaxTilesPerFrame)
+        return fail(GFTORF_EINVAL, "more than " + std::to_string(gft::kMaxTilesPerFrame) +
+                                       " tiles per frame; use a larger tile shape");
     p.nf = c->n_freq;
     p.nphi = c->n_phase;
     p.nq = p.nf * p.nphi;
@@ -85,14 +83,11 @@ int build_params(int64_t n, int32_t F, const gftorf_config* c, gft::Params* P) {
     p.s_int = c->source_intensity;
     p.bg_pow = c->bg_T_power;
     p.cap = (unsigned long long)c->max_pairs;
-    p.key_bits = key_bits_for((int64_t)F * p.n_tiles);
     return GFTORF_OK;
 }
 
-int sorted_buffer(const gft::Params& P) {
-    const int passes = (P.key_bits + 7) / 8;
-    return passes & 1;
-}
+// Buffer holding the depth-sorted items after the forward.
+int depth_buffer(const gft::Params& P) { return gft::depth_sort_passes(P.F) & 1; }
 
 int check_gauss(const gftorf_gaussians* g) {
     if (!g) return fail(GFTORF_EINVAL, "gaussians is NULL");
@@ -217,12 +212,9 @@ int gftorf_render_fwd(const gftorf_gaussians* g, const gftorf_frame* frames, int
 
     gft::launch_fill_u32(reinterpret_cast<uint32_t*>(w.status), 0u, sizeof(gft::Status) / 4, s);
     gft::launch_preprocess(P, *g, frames, w, s);
-    int dbuf = 0;
-    gft::launch_depth_sort(P, w, s, &dbuf);
-    gft::launch_emit(P, w, dbuf, s);
-    const int tbuf = gft::launch_tile_sort(P, w, s);
-    gft::launch_ranges(P, w, tbuf, s);
-    hipError_t e = gft::launch_composite_fwd(P, frames, w, tbuf, *out, s);
+    const int dbuf = gft::launch_depth_sort(P, w, s);
+    hipError_t e = gft::launch_binning(P, w, dbuf, s);
+    if (e == hipSuccess) e = gft::launch_composite_fwd(P, frames, w, *out, s);
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "gftorf_render_fwd");
     return GFTORF_OK;
@@ -248,7 +240,7 @@ int gftorf_render_bwd(const gftorf_gaussians* g, const gftorf_frame* frames, int
 
     gft::launch_fill_f32(w.grec, 0.f, (int64_t)gft::grad_floats(P.nf) * w.M, s);
     if (d_bg) gft::launch_fill_f32(d_bg, 0.f, (int64_t)n_frames * (3 + P.nq), s);
-    hipError_t e = gft::launch_composite_bwd(P, frames, w, sorted_buffer(P), *saved, d_rgb, d_quad,
+    hipError_t e = gft::launch_composite_bwd(P, frames, w, *saved, d_rgb, d_quad,
                                              d_depth, d_bg, s);
     if (e == hipSuccess) {
         gft::launch_preprocess_bwd(P, *g, frames, w, *grad, s);
@@ -291,14 +283,17 @@ int gftorf_copy_lists(const void* ws, int64_t n, int32_t n_frames, const gftorf_
     if (e != hipSuccess) return hip_fail(e, "gftorf_copy_lists");
     unsigned long long np = st.n_pairs < P.cap ? st.n_pairs : P.cap;
     if (pair_capacity >= 0 && np > (unsigned long long)pair_capacity) np = (unsigned long long)pair_capacity;
-    const int tb = sorted_buffer(P);
+    const int db = depth_buffer(P);
     auto cp = [&](void* dst, const void* src, size_t bytes) {
         if (dst && bytes && e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
     };
-    cp(pair_key, w.tkey[tb], 4 * np);
-    cp(pair_item, w.tval[tb], 4 * np);
-    cp(depth_key, w.dkey[0], 4 * (size_t)w.M);
-    cp(depth_item, w.dval[0], 4 * (size_t)w.M);
+    if (pair_key && np) {
+        gft::launch_keys_from_ranges(P, w, pair_key, np, s);
+        e = hipGetLastError();
+    }
+    cp(pair_item, w.tval, 4 * np);
+    cp(depth_key, w.dkey[db], 4 * (size_t)w.M);
+    cp(depth_item, w.dval[db], 4 * (size_t)w.M);
     cp(item_count, w.cnt, 4 * (size_t)w.M);
     cp(item_rect, w.rect, 8 * (size_t)w.M);
     if (e != hipSuccess) return hip_fail(e, "gftorf_copy_lists");

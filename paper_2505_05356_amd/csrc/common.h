@@ -17,14 +17,14 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
 constexpr int kSortBuckets = 256;                       // <= 8 digit bits per pass
 
-// Pair emission: items (frame, Gaussian) per block of the emit kernel.
-constexpr int kEmitThreads = 256;
-constexpr int kEmitItems = 4;
-constexpr int kEmitChunk = kEmitThreads * kEmitItems;  // 1024
-// Pair writing is balanced by pairs, not items: each workgroup writes
-// kPairsPerBlock consecutive pairs, 8 per thread.
-constexpr int kPairsPerThread = 8;
-constexpr int kPairsPerBlock = kEmitThreads * kPairsPerThread;  // 2048
+// Tile binning works on chunks of depth-sorted items of one frame; the LDS
+// cursor array holds one counter per tile of a frame.
+constexpr int kMaxTilesPerFrame = 16384;   // 64 KiB of LDS cursors
+struct BinGeom {
+    int C;    // items per chunk
+    int QC;   // chunks per frame
+};
+BinGeom bin_geometry(int64_t n, int n_tiles);
 
 // Per-(frame, Gaussian) record in float4 units.
 //   r0 = {u_hi, v_hi, u_lo, v_lo}   pixel centre as an unevaluated float pair
@@ -59,7 +59,6 @@ struct Params {
     float alpha_min, alpha_max, T_min, extent, dilation, near_z, s_int;
     int32_t bg_pow;
     unsigned long long cap;  // pair capacity
-    int32_t key_bits;        // bits of the (frame, tile) key
 };
 
 // Device pointers carved out of the caller's workspace.
@@ -70,18 +69,15 @@ struct Workspace {
     uint32_t* cnt;          // [M] tiles covered
     uint32_t* dkey[2];      // [M] depth keys (double buffer)
     uint32_t* dval[2];      // [M] item ids
-    unsigned long long* chunk_sum;  // [n_chunks + 1] emission chunk sums / offsets
-    unsigned long long* off;        // [M + 1] first pair of each depth-sorted item
-    uint32_t* first;                // [cap / kPairsPerBlock + 1] item holding each block's first pair
-    uint32_t* tkey[2];      // [cap] (frame, tile) keys
-    uint32_t* tval[2];      // [cap] item ids
-    uint32_t* counts;       // [256][max_sort_tiles] per-tile digit counts
+    uint32_t* counts;       // [256][max_sort_tiles] per-tile digit counts of the depth sort
     uint32_t* totals;       // [256]
-    uint2* ranges;          // [F * n_tiles]
+    uint32_t* cntmat;       // [F][QC][n_tiles] per-chunk tile counts, then column prefixes
+    uint32_t* tcount;       // [F * n_tiles] pairs per (frame, tile)
+    uint2* ranges;          // [F * n_tiles] [start, end) of each tile list in tval
+    uint32_t* tval;         // [cap] item ids of the tile lists
     uint2* wcount;          // [F * n_tiles] forward (evaluations, composited) per work item
     float* grec;            // [M][grad_floats]
     int64_t M;
-    int64_t n_chunks;
     int64_t max_sort_tiles;
     size_t bytes;
 };
@@ -97,26 +93,24 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int n_tiles, ui
         return p;
     };
     const int64_t M = n * F;
+    const BinGeom g = bin_geometry(n, n_tiles);
     w.M = M;
-    w.n_chunks = (M + kEmitChunk - 1) / kEmitChunk;
-    int64_t sort_n = M > (int64_t)cap ? M : (int64_t)cap;
-    w.max_sort_tiles = (sort_n + kSortTile - 1) / kSortTile;
+    w.max_sort_tiles = (M + kSortTile - 1) / kSortTile;
     if (w.max_sort_tiles < 1) w.max_sort_tiles = 1;
+    const int64_t K = (int64_t)F * n_tiles;
     w.status = reinterpret_cast<Status*>(take(sizeof(Status)));
     w.rec = reinterpret_cast<float4*>(take(sizeof(float4) * record_float4s(nf) * M));
     w.rect = reinterpret_cast<uint2*>(take(sizeof(uint2) * M));
     w.cnt = reinterpret_cast<uint32_t*>(take(4 * M));
     for (int i = 0; i < 2; ++i) w.dkey[i] = reinterpret_cast<uint32_t*>(take(4 * M));
     for (int i = 0; i < 2; ++i) w.dval[i] = reinterpret_cast<uint32_t*>(take(4 * M));
-    w.chunk_sum = reinterpret_cast<unsigned long long*>(take(8 * (w.n_chunks + 1)));
-    w.off = reinterpret_cast<unsigned long long*>(take(8 * (M + 1)));
-    w.first = reinterpret_cast<uint32_t*>(take(4 * (cap / kPairsPerBlock + 2)));
-    for (int i = 0; i < 2; ++i) w.tkey[i] = reinterpret_cast<uint32_t*>(take(4 * cap));
-    for (int i = 0; i < 2; ++i) w.tval[i] = reinterpret_cast<uint32_t*>(take(4 * cap));
     w.counts = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets * w.max_sort_tiles));
     w.totals = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets));
-    w.ranges = reinterpret_cast<uint2*>(take(sizeof(uint2) * (int64_t)F * n_tiles));
-    w.wcount = reinterpret_cast<uint2*>(take(sizeof(uint2) * (int64_t)F * n_tiles));
+    w.cntmat = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * g.QC * n_tiles));
+    w.tcount = reinterpret_cast<uint32_t*>(take(4 * K));
+    w.ranges = reinterpret_cast<uint2*>(take(sizeof(uint2) * K));
+    w.tval = reinterpret_cast<uint32_t*>(take(4 * cap));
+    w.wcount = reinterpret_cast<uint2*>(take(sizeof(uint2) * K));
     w.grec = reinterpret_cast<float*>(take(4 * (size_t)grad_floats(nf) * M));
     w.bytes = off + 256;
     return w;
@@ -147,14 +141,15 @@ struct ProfScope {
 // ---- host-side launchers (defined in the .hip files) -----------------------
 void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_frame* frames,
                        const Workspace& w, hipStream_t s);
-void launch_depth_sort(const Params& P, const Workspace& w, hipStream_t s, int* result_buf);
-void launch_emit(const Params& P, const Workspace& w, int dbuf, hipStream_t s);
-int launch_tile_sort(const Params& P, const Workspace& w, hipStream_t s);
-void launch_ranges(const Params& P, const Workspace& w, int tbuf, hipStream_t s);
+int depth_sort_passes(int n_frames);
+int launch_depth_sort(const Params& P, const Workspace& w, hipStream_t s);
+hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStream_t s);
+void launch_keys_from_ranges(const Params& P, const Workspace& w, uint32_t* keys,
+                             unsigned long long limit, hipStream_t s);
 hipError_t launch_composite_fwd(const Params& P, const gftorf_frame* frames, const Workspace& w,
-                                int tbuf, const gftorf_outputs& out, hipStream_t s);
+                                const gftorf_outputs& out, hipStream_t s);
 hipError_t launch_composite_bwd(const Params& P, const gftorf_frame* frames, const Workspace& w,
-                                int tbuf, const gftorf_outputs& saved, const float* d_rgb,
+                                const gftorf_outputs& saved, const float* d_rgb,
                                 const float* d_quad, const float* d_depth, float* d_bg,
                                 hipStream_t s);
 void launch_preprocess_bwd(const Params& P, const gftorf_gaussians& g, const gftorf_frame* frames,

@@ -434,12 +434,12 @@ __global__ void __launch_bounds__(1024) k_sum_counts(const uint2* __restrict__ w
 }
 
 template <int TW, int TH>
-hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w, int tbuf,
+hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w,
                   const gftorf_outputs& out, hipStream_t s) {
     const unsigned blocks = (unsigned)(P.F * P.n_tiles);
 #define GFT_FWD(NF_)                                                                             \
     hipLaunchKernelGGL((k_composite_fwd<TW, TH, NF_>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, \
-                       w.ranges, w.tval[tbuf], w.rec, out, w.wcount)
+                       w.ranges, w.tval, w.rec, out, w.wcount)
     {
         ProfScope _p("k_composite_fwd", s);
         switch (P.nf) {
@@ -458,14 +458,14 @@ hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& 
 }
 
 template <int TW, int TH>
-hipError_t bwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w, int tbuf,
+hipError_t bwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w,
                   const gftorf_outputs& sv, const float* dr, const float* dq, const float* dd,
                   float* dbg, hipStream_t s) {
     const unsigned blocks = (unsigned)(P.F * P.n_tiles);
     ProfScope _p("k_composite_bwd", s);
 #define GFT_BWD(NF_)                                                                             \
     hipLaunchKernelGGL((k_composite_bwd<TW, TH, NF_>), dim3(blocks), dim3(64), 0, s, P, frames,    \
-                       w.ranges, w.tval[tbuf], w.rec, sv.T_final, sv.n_contrib, dr, dq, dd, w.grec, dbg)
+                       w.ranges, w.tval, w.rec, sv.T_final, sv.n_contrib, dr, dq, dd, w.grec, dbg)
     switch (P.nf) {
         case 1: GFT_BWD(1); break;
         case 2: GFT_BWD(2); break;
@@ -479,19 +479,19 @@ hipError_t bwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& 
 }  // namespace
 
 hipError_t launch_composite_fwd(const Params& P, const gftorf_frame* frames, const Workspace& w,
-                                int tbuf, const gftorf_outputs& out, hipStream_t s) {
-    if (P.tw == 8 && P.th == 8) return fwd_nf<8, 8>(P, frames, w, tbuf, out, s);
-    if (P.tw == 32 && P.th == 8) return fwd_nf<32, 8>(P, frames, w, tbuf, out, s);
-    return fwd_nf<16, 16>(P, frames, w, tbuf, out, s);
+                                const gftorf_outputs& out, hipStream_t s) {
+    if (P.tw == 8 && P.th == 8) return fwd_nf<8, 8>(P, frames, w, out, s);
+    if (P.tw == 32 && P.th == 8) return fwd_nf<32, 8>(P, frames, w, out, s);
+    return fwd_nf<16, 16>(P, frames, w, out, s);
 }
 
 hipError_t launch_composite_bwd(const Params& P, const gftorf_frame* frames, const Workspace& w,
-                                int tbuf, const gftorf_outputs& saved, const float* d_rgb,
+                                const gftorf_outputs& saved, const float* d_rgb,
                                 const float* d_quad, const float* d_depth, float* d_bg,
                                 hipStream_t s) {
-    if (P.tw == 8 && P.th == 8) return bwd_nf<8, 8>(P, frames, w, tbuf, saved, d_rgb, d_quad, d_depth, d_bg, s);
-    if (P.tw == 32 && P.th == 8) return bwd_nf<32, 8>(P, frames, w, tbuf, saved, d_rgb, d_quad, d_depth, d_bg, s);
-    return bwd_nf<16, 16>(P, frames, w, tbuf, saved, d_rgb, d_quad, d_depth, d_bg, s);
+    if (P.tw == 8 && P.th == 8) return bwd_nf<8, 8>(P, frames, w, saved, d_rgb, d_quad, d_depth, d_bg, s);
+    if (P.tw == 32 && P.th == 8) return bwd_nf<32, 8>(P, frames, w, saved, d_rgb, d_quad, d_depth, d_bg, s);
+    return bwd_nf<16, 16>(P, frames, w, saved, d_rgb, d_quad, d_depth, d_bg, s);
 }
 
 }  // namespace gft
