@@ -1,30 +1,33 @@
 // Tile binning: per-(frame, tile) Gaussian lists in depth order, built from
 // the frame-major depth-sorted items without sorting (tile, Gaussian) pairs.
 //
-// Each item covers a rectangle of tiles.  The pair of (item j, tile t) must
-// land at start[t] + #{items before j in depth order that cover t}, which is
-// the order the compositing loop of paper §3 walks.  The depth-ordered items
-// of each frame are cut into chunks of C items:
-//   k_bin_count   one workgroup per chunk: per-tile counts of the chunk in
-//                 LDS (rectangles expanded with LDS atomics), written as one
-//                 row of the [chunk][tile] count matrix;
-//   k_bin_colscan exclusive scan of every tile's column over the chunks of
-//                 its frame (16 waves split the rows), and per-tile totals;
-//   k_bin_keyscan exclusive scan of the totals over (frame, tile): the list
-//                 ranges, the pair count and the capacity check;
-//   k_bin_place   one wave per chunk: LDS cursors start[t] + column prefix,
-//                 then the chunk's items in depth order, the lanes expanding
-//                 one item's rectangle at a time; each lane writes the item id
-//                 at its tile's cursor and advances it.
-// HBM traffic is the pair list written once (4 B per pair) plus the count
-// matrix (4 B per chunk and tile, read and written twice), instead of an
-// emitted key/value pair list and two radix passes over it.
+// The compositing loop of paper §3 walks, for every pixel, the Gaussians of
+// its tile front to back.  Each item (frame, Gaussian) covers a rectangle of
+// tiles; its entry for tile t must sit at start[t] + (number of items before
+// it in depth order that cover t).  The lists are built in two levels:
+//
+// Level A -- items into groups of 8x8 tiles.  The depth-ordered items of a
+//   frame are cut into chunks: per-chunk group counts (LDS), a column scan
+//   over the chunks, an exclusive scan over (frame, group), then one wave per
+//   chunk places its items in depth order into the group lists.  An item
+//   touches only a few groups, so these lists are short.
+// Level B -- group lists into tile lists.  Each group list is cut into
+//   segments of 512 entries; one wave per segment, lane l owning tile l of
+//   the group.  A counting pass, a column scan over each group's segments and
+//   an exclusive scan over (frame, tile) give every lane a cursor; the
+//   placing pass then walks the segment in order and each lane appends the
+//   items that cover its tile.  Every tile list is written by one lane at a
+//   time in increasing addresses, so the writes coalesce, and the order is
+//   the depth order by construction.
 #include "block_scan.h"
 #include "common.h"
 
 namespace gft {
 
 namespace {
+
+constexpr int kGroupW = 8, kGroupH = 8;   // tiles per group (one per lane)
+constexpr int kSegment = 512;             // group-list entries per level-B wave
 
 __device__ __forceinline__ void unpack_rect(uint2 rc, uint32_t& xlo, uint32_t& xhi, uint32_t& ylo,
                                             uint32_t& yhi) {
@@ -34,17 +37,30 @@ __device__ __forceinline__ void unpack_rect(uint2 rc, uint32_t& xlo, uint32_t& x
     yhi = rc.y >> 16;
 }
 
-__global__ void __launch_bounds__(256) k_bin_count(Params P, int C, int QC,
-                                                   const uint32_t* __restrict__ dval,
-                                                   const uint32_t* __restrict__ cnt,
-                                                   const uint2* __restrict__ rect,
-                                                   uint32_t* __restrict__ cntmat) {
-    extern __shared__ uint32_t lcnt[];
+struct Groups {
+    int ngx, ngy, ng;   // groups per row, per column, per frame
+};
+
+__device__ __forceinline__ Groups groups_of(const Params& P) {
+    Groups g;
+    g.ngx = (P.ntx + kGroupW - 1) / kGroupW;
+    g.ngy = (P.nty + kGroupH - 1) / kGroupH;
+    g.ng = g.ngx * g.ngy;
+    return g;
+}
+
+// ---- level A: items -> groups ----------------------------------------------
+
+__global__ void __launch_bounds__(256) k_group_count(Params P, int C, int QC,
+                                                     const uint32_t* __restrict__ dval,
+                                                     const uint32_t* __restrict__ cnt,
+                                                     const uint2* __restrict__ rect,
+                                                     uint32_t* __restrict__ cntA) {
+    __shared__ uint32_t lcnt[kMaxGroupsPerFrame];
+    const Groups G = groups_of(P);
     const int chunk = blockIdx.x;
     const int f = chunk / QC, q = chunk - f * QC;
-    const int nt = P.n_tiles;
-    const int ntx = P.ntx;
-    for (int t = threadIdx.x; t < nt; t += 256) lcnt[t] = 0;
+    for (int t = threadIdx.x; t < G.ng; t += 256) lcnt[t] = 0;
     __syncthreads();
     const long long beg = (long long)f * P.n + (long long)q * C;
     const long long end = min(beg + C, (long long)(f + 1) * P.n);
@@ -53,52 +69,217 @@ __global__ void __launch_bounds__(256) k_bin_count(Params P, int C, int QC,
         if (cnt[item] == 0) continue;
         uint32_t xlo, xhi, ylo, yhi;
         unpack_rect(rect[item], xlo, xhi, ylo, yhi);
-        for (uint32_t ty = ylo; ty <= yhi; ++ty)
-            for (uint32_t tx = xlo; tx <= xhi; ++tx) atomicAdd(&lcnt[ty * ntx + tx], 1u);
+        for (uint32_t gy = ylo / kGroupH; gy <= yhi / kGroupH; ++gy)
+            for (uint32_t gx = xlo / kGroupW; gx <= xhi / kGroupW; ++gx)
+                atomicAdd(&lcnt[gy * G.ngx + gx], 1u);
     }
     __syncthreads();
-    uint32_t* out = cntmat + (size_t)chunk * nt;
-    for (int t = threadIdx.x; t < nt; t += 256) out[t] = lcnt[t];
+    uint32_t* out = cntA + (size_t)chunk * G.ng;
+    for (int t = threadIdx.x; t < G.ng; t += 256) out[t] = lcnt[t];
 }
 
-// grid (ceil(nt / 64), F), 1024 threads: lane = tile within a group of 64,
-// wave = one sixteenth of the frame's chunk rows.
-__global__ void __launch_bounds__(1024) k_bin_colscan(Params P, int QC, uint32_t* __restrict__ cntmat,
-                                                      uint32_t* __restrict__ tcount) {
-    __shared__ uint32_t part[16][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nt = P.n_tiles;
-    const int t = blockIdx.x * 64 + lane;
-    const int f = blockIdx.y;
-    const int rows = (QC + 15) / 16;
-    const int q0 = wave * rows, q1 = min(q0 + rows, QC);
-    uint32_t* col = cntmat + (size_t)f * QC * nt + t;
-    uint32_t s = 0;
-    if (t < nt)
-        for (int q = q0; q < q1; ++q) s += col[(size_t)q * nt];
-    part[wave][lane] = s;
-    __syncthreads();
-    uint32_t run = 0, total = 0;
-    for (int w = 0; w < 16; ++w) {
-        if (w < wave) run += part[w][lane];
-        total += part[w][lane];
+// One thread per (frame, group): exclusive scan of the group's column over
+// the chunks of its frame; totals per (frame, group).
+__global__ void k_group_colscan(Params P, int QC, uint32_t* __restrict__ cntA,
+                                uint32_t* __restrict__ lenA) {
+    const Groups G = groups_of(P);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.F * G.ng) return;
+    const int f = i / G.ng, gi = i - f * G.ng;
+    uint32_t* col = cntA + (size_t)f * QC * G.ng + gi;
+    uint32_t run = 0;
+    for (int q = 0; q < QC; ++q) {
+        const uint32_t v = col[(size_t)q * G.ng];
+        col[(size_t)q * G.ng] = run;
+        run += v;
     }
-    if (t < nt) {
-        for (int q = q0; q < q1; ++q) {
-            const uint32_t v = col[(size_t)q * nt];
-            col[(size_t)q * nt] = run;
-            run += v;
+    lenA[i] = run;
+}
+
+// Single workgroup: group-list ranges (exclusive scan of the lengths) and the
+// first level-B segment of every group.  The level-A lists are bounded by the
+// pair capacity (every group entry yields at least one pair).
+__global__ void __launch_bounds__(1024) k_group_scan(const uint32_t* __restrict__ lenA, int K,
+                                                     unsigned long long cap, uint2* __restrict__ granges,
+                                                     uint32_t* __restrict__ seg_start) {
+    __shared__ unsigned long long scratch[17];
+    __shared__ uint32_t scratch32[17];
+    unsigned long long carry = 0;
+    uint32_t scarry = 0;
+    for (int base = 0; base < K; base += 1024) {
+        const int i = base + threadIdx.x;
+        const unsigned long long v = i < K ? lenA[i] : 0ull;
+        const uint32_t nsg = (uint32_t)((v + kSegment - 1) / kSegment);
+        unsigned long long tot;
+        uint32_t stot;
+        const unsigned long long ex = block_exclusive_scan<unsigned long long, 1024>(v, scratch, &tot);
+        const uint32_t sex = block_exclusive_scan<uint32_t, 1024>(nsg, scratch32, &stot);
+        if (i < K) {
+            const unsigned long long a = carry + ex, b = a + v;
+            granges[i] = make_uint2((uint32_t)(a < cap ? a : cap), (uint32_t)(b < cap ? b : cap));
+            seg_start[i] = scarry + sex;
         }
-        if (wave == 0) tcount[(size_t)f * nt + t] = total;
+        carry += tot;
+        scarry += stot;
+    }
+    if (threadIdx.x == 0) seg_start[K] = scarry;
+}
+
+// One wave per chunk: the chunk's items in depth order append themselves to
+// the lists of the groups they touch (LDS cursors, lanes over the groups).
+__global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
+                                                    const uint32_t* __restrict__ dval,
+                                                    const uint32_t* __restrict__ cnt,
+                                                    const uint2* __restrict__ rect,
+                                                    const uint32_t* __restrict__ cntA,
+                                                    const uint2* __restrict__ granges,
+                                                    uint32_t* __restrict__ gval) {
+    __shared__ uint32_t cursor[kMaxGroupsPerFrame];
+    __shared__ uint32_t sitem[64];
+    __shared__ uint2 srect[64];
+    const Groups G = groups_of(P);
+    const int chunk = blockIdx.x;
+    const int f = chunk / QC, q = chunk - f * QC;
+    const int lane = threadIdx.x;
+    const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
+    const uint32_t* pre = cntA + (size_t)chunk * G.ng;
+    for (int t = lane; t < G.ng; t += 64) cursor[t] = granges[(size_t)f * G.ng + t].x + pre[t];
+    const long long beg = (long long)f * P.n + (long long)q * C;
+    const long long end = min(beg + C, (long long)(f + 1) * P.n);
+    volatile uint32_t* cur = cursor;
+    for (long long j0 = beg; j0 < end; j0 += 64) {
+        __syncthreads();
+        const int m = (int)min(64ll, end - j0);
+        if (lane < m) {
+            const uint32_t item = dval[j0 + lane];
+            const bool ok = cnt[item] != 0;
+            sitem[lane] = ok ? item : 0xffffffffu;
+            srect[lane] = ok ? rect[item] : make_uint2(0, 0);
+        }
+        __syncthreads();
+        for (int i = 0; i < m; ++i) {
+            const uint32_t item = sitem[i];
+            if (item == 0xffffffffu) continue;
+            uint32_t xlo, xhi, ylo, yhi;
+            unpack_rect(srect[i], xlo, xhi, ylo, yhi);
+            const uint32_t gx0 = xlo / kGroupW, gy0 = ylo / kGroupH;
+            const uint32_t gw = xhi / kGroupW - gx0 + 1;
+            const uint32_t area = gw * (yhi / kGroupH - gy0 + 1);
+            for (uint32_t k = lane; k < area; k += 64) {
+                const uint32_t gy = gy0 + k / gw, gx = gx0 + k % gw;
+                const uint32_t t = gy * (uint32_t)G.ngx + gx;
+                const uint32_t pos = cur[t];
+                cur[t] = pos + 1;
+                if (pos < cap) gval[pos] = item;
+            }
+        }
     }
 }
 
-// Single workgroup: list ranges = exclusive scan of the per-(frame, tile)
+// ---- level B: group lists -> tile lists ----------------------------------------
+
+struct Segment {
+    int fg;             // frame * ng + group
+    uint32_t beg, end;  // entries of the group list
+};
+
+// Segment b -> (frame, group) and its entries; fg < 0 if b is past the last.
+__device__ __forceinline__ Segment find_segment(int b, const uint32_t* __restrict__ seg_start, int K,
+                                                const uint2* __restrict__ granges) {
+    Segment s;
+    s.fg = -1;
+    if ((uint32_t)b >= seg_start[K]) return s;
+    int lo = 0, hi = K;   // seg_start[lo] <= b < seg_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg_start[mid] <= (uint32_t)b) lo = mid; else hi = mid;
+    }
+    const uint2 r = granges[lo];
+    s.fg = lo;
+    s.beg = r.x + (uint32_t)(b - (int)seg_start[lo]) * kSegment;
+    s.end = min(s.beg + (uint32_t)kSegment, r.y);
+    return s;
+}
+
+// Lane l of the wave owns tile (gx * 8 + l % 8, gy * 8 + l / 8) of the group.
+template <bool PLACE>
+__global__ void __launch_bounds__(64) k_tile_pass(Params P, const uint32_t* __restrict__ seg_start,
+                                                  const uint2* __restrict__ granges,
+                                                  const uint32_t* __restrict__ gval,
+                                                  const uint2* __restrict__ rect,
+                                                  uint32_t* __restrict__ cntB,
+                                                  const uint2* __restrict__ ranges,
+                                                  uint32_t* __restrict__ tval) {
+    __shared__ uint32_t sitem[64];
+    __shared__ uint2 srect[64];
+    const Groups G = groups_of(P);
+    const int K = P.F * G.ng;
+    const uint32_t nseg = seg_start[K];
+    for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
+    const Segment sg = find_segment((int)b, seg_start, K, granges);
+    const int lane = threadIdx.x;
+    const int f = sg.fg / G.ng, gi = sg.fg - f * G.ng;
+    const uint32_t gy = gi / G.ngx, gx = gi - gy * G.ngx;
+    const uint32_t tx = gx * kGroupW + lane % kGroupW, ty = gy * kGroupH + lane / kGroupW;
+    const bool mine = tx < (uint32_t)P.ntx && ty < (uint32_t)P.nty;
+    const uint32_t tile = ty * (uint32_t)P.ntx + tx;
+    const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
+    uint32_t c = 0;
+    if (PLACE && mine) c = ranges[(size_t)f * P.n_tiles + tile].x + cntB[(size_t)b * 64 + lane];
+    for (uint32_t j0 = sg.beg; j0 < sg.end; j0 += 64) {
+        const int m = (int)min(64u, sg.end - j0);
+        __syncthreads();
+        if (lane < m) {
+            const uint32_t item = gval[j0 + lane];
+            sitem[lane] = item;
+            srect[lane] = rect[item];
+        }
+        __syncthreads();
+        for (int i = 0; i < m; ++i) {
+            uint32_t xlo, xhi, ylo, yhi;
+            unpack_rect(srect[i], xlo, xhi, ylo, yhi);
+            const bool cov = mine && tx >= xlo && tx <= xhi && ty >= ylo && ty <= yhi;
+            if (PLACE) {
+                if (cov) {
+                    if (c < cap) tval[c] = sitem[i];
+                    ++c;
+                }
+            } else {
+                c += cov ? 1u : 0u;
+            }
+        }
+    }
+    if (!PLACE) cntB[(size_t)b * 64 + lane] = c;
+    }
+}
+
+// One wave per (frame, group): exclusive scan of each lane's tile column over
+// the group's segments; per-tile totals.
+__global__ void __launch_bounds__(64) k_tile_colscan(Params P, const uint32_t* __restrict__ seg_start,
+                                                     uint32_t* __restrict__ cntB,
+                                                     uint32_t* __restrict__ tcount) {
+    const Groups G = groups_of(P);
+    const int fg = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int f = fg / G.ng, gi = fg - f * G.ng;
+    const uint32_t gy = gi / G.ngx, gx = gi - gy * G.ngx;
+    const uint32_t tx = gx * kGroupW + lane % kGroupW, ty = gy * kGroupH + lane / kGroupW;
+    uint32_t run = 0;
+    for (uint32_t b = seg_start[fg]; b < seg_start[fg + 1]; ++b) {
+        const uint32_t v = cntB[(size_t)b * 64 + lane];
+        cntB[(size_t)b * 64 + lane] = run;
+        run += v;
+    }
+    if (tx < (uint32_t)P.ntx && ty < (uint32_t)P.nty)
+        tcount[(size_t)f * P.n_tiles + ty * P.ntx + tx] = run;
+}
+
+// Single workgroup: tile-list ranges = exclusive scan of the per-(frame, tile)
 // totals; pair count, capacity and overflow into the status block.  Ranges
 // are clamped to the capacity so that an overflowed forward stays in bounds.
-__global__ void __launch_bounds__(1024) k_bin_keyscan(const uint32_t* __restrict__ tcount, long long K,
-                                                      unsigned long long cap, uint2* __restrict__ ranges,
-                                                      Status* status) {
+__global__ void __launch_bounds__(1024) k_tile_keyscan(const uint32_t* __restrict__ tcount, long long K,
+                                                       unsigned long long cap, uint2* __restrict__ ranges,
+                                                       Status* status) {
     __shared__ unsigned long long scratch[17];
     unsigned long long carry = 0;
     for (long long base = 0; base < K; base += 1024) {
@@ -119,61 +300,6 @@ __global__ void __launch_bounds__(1024) k_bin_keyscan(const uint32_t* __restrict
     }
 }
 
-// One wave per chunk (blockDim 64).  Dynamic LDS: nt cursors.
-__global__ void __launch_bounds__(64) k_bin_place(Params P, int C, int QC,
-                                                  const uint32_t* __restrict__ dval,
-                                                  const uint32_t* __restrict__ cnt,
-                                                  const uint2* __restrict__ rect,
-                                                  const uint32_t* __restrict__ cntmat,
-                                                  const uint2* __restrict__ ranges,
-                                                  uint32_t* __restrict__ tval) {
-    extern __shared__ uint32_t cursor[];
-    __shared__ uint32_t sitem[64];
-    __shared__ uint2 srect[64];
-    const int chunk = blockIdx.x;
-    const int f = chunk / QC, q = chunk - f * QC;
-    const int nt = P.n_tiles;
-    const uint32_t ntx = (uint32_t)P.ntx;
-    const int lane = threadIdx.x;
-    const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
-    const uint32_t* pre = cntmat + (size_t)chunk * nt;
-    for (int t = lane; t < nt; t += 64) cursor[t] = ranges[(size_t)f * nt + t].x + pre[t];
-    const long long beg = (long long)f * P.n + (long long)q * C;
-    const long long end = min(beg + C, (long long)(f + 1) * P.n);
-    volatile uint32_t* cur = cursor;
-    for (long long j0 = beg; j0 < end; j0 += 64) {
-        __syncthreads();
-        const int m = (int)min(64ll, end - j0);
-        if (lane < m) {
-            const uint32_t item = dval[j0 + lane];
-            const bool ok = cnt[item] != 0;
-            sitem[lane] = ok ? item : 0xffffffffu;
-            srect[lane] = ok ? rect[item] : make_uint2(0, 0);
-        }
-        __syncthreads();
-        for (int i = 0; i < m; ++i) {
-            const uint32_t item = sitem[i];
-            if (item == 0xffffffffu) continue;
-            uint32_t xlo, xhi, ylo, yhi;
-            unpack_rect(srect[i], xlo, xhi, ylo, yhi);
-            const uint32_t w = xhi - xlo + 1;
-            const uint32_t area = w * (yhi - ylo + 1);
-            const float inv_w = 1.0f / (float)w;
-            for (uint32_t k = lane; k < area; k += 64) {
-                // k / w by a float reciprocal, corrected to the exact quotient
-                uint32_t ty = (uint32_t)((float)k * inv_w);
-                if (ty * w > k) --ty;
-                if ((ty + 1) * w <= k) ++ty;
-                const uint32_t tx = k - ty * w;
-                const uint32_t t = (ylo + ty) * ntx + xlo + tx;
-                const uint32_t pos = cur[t];
-                cur[t] = pos + 1;
-                if (pos < cap) tval[pos] = item;
-            }
-        }
-    }
-}
-
 // Introspection: expands the ranges into per-pair (frame, tile) keys.
 __global__ void k_keys_from_ranges(const uint2* __restrict__ ranges, long long K,
                                    unsigned long long limit, uint32_t* __restrict__ keys) {
@@ -186,40 +312,69 @@ __global__ void k_keys_from_ranges(const uint2* __restrict__ ranges, long long K
 
 }  // namespace
 
-BinGeom bin_geometry(int64_t n, int n_tiles) {
+BinGeom bin_geometry(int64_t n, int32_t n_frames, int ntx, int nty, uint64_t cap) {
     BinGeom g;
-    int C = 512;
-    while (C < 8192 && C < n_tiles / 4) C *= 2;
+    // level-A chunks: enough waves to fill the chip, at least 128 items each
+    const int64_t M = n * (int64_t)n_frames;
+    int C = 128;
+    while (C < 2048 && M / C > 4096) C *= 2;
     g.C = C;
     g.QC = n > 0 ? (int)((n + C - 1) / C) : 0;
+    g.ng = ((ntx + kGroupW - 1) / kGroupW) * ((nty + kGroupH - 1) / kGroupH);
+    // every segment but the last of each group list holds kSegment entries,
+    // and the group lists hold at most min(cap, M * groups) entries
+    uint64_t entries = cap;
+    if ((uint64_t)M * g.ng < entries) entries = (uint64_t)M * g.ng;
+    g.max_segments = (int64_t)((entries + kSegment - 1) / kSegment) + (int64_t)n_frames * g.ng;
     return g;
 }
 
 hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStream_t s) {
-    const BinGeom g = bin_geometry(P.n, P.n_tiles);
+    const BinGeom g = bin_geometry(P.n, P.F, P.ntx, P.nty, P.cap);
+    const int K = P.F * g.ng;
     const unsigned chunks = (unsigned)(P.F * g.QC);
-    const size_t lds = sizeof(uint32_t) * (size_t)P.n_tiles;
     if (chunks) {
-        ProfScope _p("k_bin_count", s);
-        hipLaunchKernelGGL(k_bin_count, dim3(chunks), dim3(256), lds, s, P, g.C, g.QC, w.dval[dbuf],
-                           w.cnt, w.rect, w.cntmat);
+        ProfScope _p("k_group_count", s);
+        hipLaunchKernelGGL(k_group_count, dim3(chunks), dim3(256), 0, s, P, g.C, g.QC, w.dval[dbuf],
+                           w.cnt, w.rect, w.cntA);
     }
     if (chunks) {
-        ProfScope _p("k_bin_colscan", s);
-        hipLaunchKernelGGL(k_bin_colscan, dim3((P.n_tiles + 63) / 64, P.F), dim3(1024), 0, s, P, g.QC,
-                           w.cntmat, w.tcount);
+        ProfScope _p("k_group_colscan", s);
+        hipLaunchKernelGGL(k_group_colscan, dim3((K + 255) / 256), dim3(256), 0, s, P, g.QC, w.cntA,
+                           w.lenA);
     } else {
-        launch_fill_u32(w.tcount, 0u, (int64_t)P.F * P.n_tiles, s);
+        launch_fill_u32(w.lenA, 0u, K, s);
     }
     {
-        ProfScope _p("k_bin_keyscan", s);
-        hipLaunchKernelGGL(k_bin_keyscan, dim3(1), dim3(1024), 0, s, w.tcount,
-                           (long long)P.F * P.n_tiles, (unsigned long long)P.cap, w.ranges, w.status);
+        ProfScope _p("k_group_scan", s);
+        hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, s, w.lenA, K, (unsigned long long)P.cap,
+                           w.granges, w.seg_start);
     }
     if (chunks) {
-        ProfScope _p("k_bin_place", s);
-        hipLaunchKernelGGL(k_bin_place, dim3(chunks), dim3(64), lds, s, P, g.C, g.QC, w.dval[dbuf],
-                           w.cnt, w.rect, w.cntmat, w.ranges, w.tval);
+        ProfScope _p("k_group_place", s);
+        hipLaunchKernelGGL(k_group_place, dim3(chunks), dim3(64), 0, s, P, g.C, g.QC, w.dval[dbuf],
+                           w.cnt, w.rect, w.cntA, w.granges, w.gval);
+    }
+    // persistent level-B grid: every wave loops over segments
+    const unsigned segs = (unsigned)(g.max_segments < 16384 ? g.max_segments : 16384);
+    {
+        ProfScope _p("k_tile_count", s);
+        hipLaunchKernelGGL(k_tile_pass<false>, dim3(segs), dim3(64), 0, s, P, w.seg_start, w.granges,
+                           w.gval, w.rect, w.cntB, w.ranges, w.tval);
+    }
+    {
+        ProfScope _p("k_tile_colscan", s);
+        hipLaunchKernelGGL(k_tile_colscan, dim3(K), dim3(64), 0, s, P, w.seg_start, w.cntB, w.tcount);
+    }
+    {
+        ProfScope _p("k_tile_keyscan", s);
+        hipLaunchKernelGGL(k_tile_keyscan, dim3(1), dim3(1024), 0, s, w.tcount,
+                           (long long)P.F * P.n_tiles, (unsigned long long)P.cap, w.ranges, w.status);
+    }
+    {
+        ProfScope _p("k_tile_place", s);
+        hipLaunchKernelGGL(k_tile_pass<true>, dim3(segs), dim3(64), 0, s, P, w.seg_start, w.granges,
+                           w.gval, w.rect, w.cntB, w.ranges, w.tval);
     }
     return hipGetLastError();
 }

@@ -63,9 +63,9 @@ int build_params(int64_t n, int32_t F, const gftorf_config* c, gft::Params* P) {
     p.nty = (c->height + c->tile_h - 1) / c->tile_h;
     p.n_tiles = p.ntx * p.nty;
     if ((int64_t)p.n_tiles * F > (int64_t)0x7FFFFFFF) return fail(GFTORF_EINVAL, "too many tiles");
-    if (p.n_tiles > gft::kMaxTilesPerFrame)
-        return fail(GFTORF_EINVAL, "more than " + std::to_string(gft::kMaxTilesPerFrame) +
-                                       " tiles per frame; use a larger tile shape");
+    if (((p.ntx + 7) / 8) * ((p.nty + 7) / 8) > gft::kMaxGroupsPerFrame)
+        return fail(GFTORF_EINVAL, "more than " + std::to_string(gft::kMaxGroupsPerFrame) +
+                                       " groups of 8x8 tiles per frame; use a larger tile shape");
     p.nf = c->n_freq;
     p.nphi = c->n_phase;
     p.nq = p.nf * p.nphi;
@@ -191,7 +191,7 @@ int gftorf_profile_end(gftorf_profile_entry* out, int32_t max_entries, int32_t* 
 size_t gftorf_workspace_size(int64_t n, int32_t n_frames, const gftorf_config* cfg) {
     gft::Params P;
     if (build_params(n, n_frames, cfg, &P) != GFTORF_OK) return 0;
-    return gft::carve(nullptr, n, n_frames, P.nf, P.n_tiles, P.cap).bytes;
+    return gft::carve(nullptr, n, n_frames, P.nf, P.ntx, P.nty, P.cap).bytes;
 }
 
 int gftorf_render_fwd(const gftorf_gaussians* g, const gftorf_frame* frames, int32_t n_frames,
@@ -205,7 +205,7 @@ int gftorf_render_fwd(const gftorf_gaussians* g, const gftorf_frame* frames, int
     if (!out || !out->T_final || !out->n_contrib) return fail(GFTORF_EINVAL, "outputs: T_final and n_contrib are required");
     if (!ws) return fail(GFTORF_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GFTORF_EINVAL, "workspace must be 256-byte aligned");
-    const gft::Workspace w = gft::carve(ws, g->n, n_frames, P.nf, P.n_tiles, P.cap);
+    const gft::Workspace w = gft::carve(ws, g->n, n_frames, P.nf, P.ntx, P.nty, P.cap);
     if (ws_bytes < w.bytes) return fail(GFTORF_ENOWS, "workspace too small: need " + std::to_string(w.bytes) + " bytes");
     hipStream_t s = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
@@ -233,7 +233,7 @@ int gftorf_render_bwd(const gftorf_gaussians* g, const gftorf_frame* frames, int
     if (!grad) return fail(GFTORF_EINVAL, "grad is NULL");
     if (!ws) return fail(GFTORF_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GFTORF_EINVAL, "workspace must be 256-byte aligned");
-    const gft::Workspace w = gft::carve(ws, g->n, n_frames, P.nf, P.n_tiles, P.cap);
+    const gft::Workspace w = gft::carve(ws, g->n, n_frames, P.nf, P.ntx, P.nty, P.cap);
     if (ws_bytes < w.bytes) return fail(GFTORF_ENOWS, "workspace too small: need " + std::to_string(w.bytes) + " bytes");
     hipStream_t s = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
@@ -275,7 +275,7 @@ int gftorf_copy_lists(const void* ws, int64_t n, int32_t n_frames, const gftorf_
     int rc = build_params(n, n_frames, cfg, &P);
     if (rc) return rc;
     if (!ws) return fail(GFTORF_EINVAL, "workspace is NULL");
-    const gft::Workspace w = gft::carve(const_cast<void*>(ws), n, n_frames, P.nf, P.n_tiles, P.cap);
+    const gft::Workspace w = gft::carve(const_cast<void*>(ws), n, n_frames, P.nf, P.ntx, P.nty, P.cap);
     hipStream_t s = static_cast<hipStream_t>(stream);
     gft::Status st;
     hipError_t e = hipMemcpyAsync(&st, ws, sizeof(st), hipMemcpyDeviceToHost, s);

@@ -17,14 +17,17 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
 constexpr int kSortBuckets = 256;                       // <= 8 digit bits per pass
 
-// Tile binning works on chunks of depth-sorted items of one frame; the LDS
-// cursor array holds one counter per tile of a frame.
-constexpr int kMaxTilesPerFrame = 16384;   // 64 KiB of LDS cursors
+// Tile binning works on chunks of depth-sorted items of one frame, first into
+// groups of 8x8 tiles (one LDS counter per group of a frame), then into tiles.
+constexpr int kMaxTilesPerFrame = 1 << 20;
+constexpr int kMaxGroupsPerFrame = 1024;   // groups of 8x8 tiles (LDS counters)
 struct BinGeom {
-    int C;    // items per chunk
-    int QC;   // chunks per frame
+    int C;                 // items per level-A chunk
+    int QC;                // chunks per frame
+    int ng;                // groups of 8x8 tiles per frame
+    int64_t max_segments;  // bound on the level-B segments
 };
-BinGeom bin_geometry(int64_t n, int n_tiles);
+BinGeom bin_geometry(int64_t n, int32_t n_frames, int ntx, int nty, uint64_t cap);
 
 // Per-(frame, Gaussian) record in float4 units.
 //   r0 = {u_hi, v_hi, u_lo, v_lo}   pixel centre as an unevaluated float pair
@@ -71,7 +74,12 @@ struct Workspace {
     uint32_t* dval[2];      // [M] item ids
     uint32_t* counts;       // [256][max_sort_tiles] per-tile digit counts of the depth sort
     uint32_t* totals;       // [256]
-    uint32_t* cntmat;       // [F][QC][n_tiles] per-chunk tile counts, then column prefixes
+    uint32_t* cntA;         // [F][QC][ng] per-chunk group counts, then column prefixes
+    uint32_t* lenA;         // [F * ng] group-list lengths
+    uint2* granges;         // [F * ng] group-list ranges in gval
+    uint32_t* seg_start;    // [F * ng + 1] first level-B segment of each group
+    uint32_t* gval;         // [cap] item ids of the group lists
+    uint32_t* cntB;         // [max_segments][64] per-segment tile counts, then prefixes
     uint32_t* tcount;       // [F * n_tiles] pairs per (frame, tile)
     uint2* ranges;          // [F * n_tiles] [start, end) of each tile list in tval
     uint32_t* tval;         // [cap] item ids of the tile lists
@@ -83,7 +91,8 @@ struct Workspace {
 };
 
 // Carves `base` (may be NULL to only compute the size).
-inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int n_tiles, uint64_t cap) {
+inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nty, uint64_t cap) {
+    const int n_tiles = ntx * nty;
     Workspace w{};
     size_t off = 0;
     auto take = [&](size_t bytes) -> char* {
@@ -93,7 +102,7 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int n_tiles, ui
         return p;
     };
     const int64_t M = n * F;
-    const BinGeom g = bin_geometry(n, n_tiles);
+    const BinGeom g = bin_geometry(n, F, ntx, nty, cap);
     w.M = M;
     w.max_sort_tiles = (M + kSortTile - 1) / kSortTile;
     if (w.max_sort_tiles < 1) w.max_sort_tiles = 1;
@@ -106,7 +115,13 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int n_tiles, ui
     for (int i = 0; i < 2; ++i) w.dval[i] = reinterpret_cast<uint32_t*>(take(4 * M));
     w.counts = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets * w.max_sort_tiles));
     w.totals = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets));
-    w.cntmat = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * g.QC * n_tiles));
+    const int64_t KG = (int64_t)F * g.ng;
+    w.cntA = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * g.QC * g.ng));
+    w.lenA = reinterpret_cast<uint32_t*>(take(4 * KG));
+    w.granges = reinterpret_cast<uint2*>(take(sizeof(uint2) * KG));
+    w.seg_start = reinterpret_cast<uint32_t*>(take(4 * (KG + 1)));
+    w.gval = reinterpret_cast<uint32_t*>(take(4 * cap));
+    w.cntB = reinterpret_cast<uint32_t*>(take(4 * 64 * (size_t)g.max_segments));
     w.tcount = reinterpret_cast<uint32_t*>(take(4 * K));
     w.ranges = reinterpret_cast<uint2*>(take(sizeof(uint2) * K));
     w.tval = reinterpret_cast<uint32_t*>(take(4 * cap));

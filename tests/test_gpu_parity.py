@@ -81,8 +81,14 @@ def test_binning_bit_exact(name):
     got = lists["rect"]
     gx = np.stack([got[:, 0] & 0xFFFF, got[:, 0] >> 16, got[:, 1] & 0xFFFF, got[:, 1] >> 16], 1)
     np.testing.assert_array_equal(gx[valid], rect_ref[valid])
-    # depth order is a stable sort of the keys
-    assert np.all(np.diff(lists["depth_key"].astype(np.int64)) >= 0)
+    # items are frame-major and depth-ordered inside each frame, ties by index
+    frames_of = lists["depth_item"] // g.n
+    assert np.all(np.diff(frames_of.astype(np.int64)) >= 0)
+    for f in range(len(frames)):
+        sel = frames_of == f
+        k = lists["depth_key"][sel].astype(np.int64)
+        i = lists["depth_item"][sel].astype(np.int64)
+        assert np.all((np.diff(k) > 0) | ((np.diff(k) == 0) & (np.diff(i) > 0)))
 
 
 @pytest.mark.parametrize("name", list(CASES))
