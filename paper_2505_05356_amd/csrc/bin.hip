@@ -27,7 +27,7 @@ namespace gft {
 namespace {
 
 constexpr int kGroupW = 8, kGroupH = 8;   // tiles per group (one per lane)
-constexpr int kSegment = 512;             // group-list entries per level-B wave
+constexpr int kLine = 32;                 // u32 entries per 128-byte cache line
 
 __device__ __forceinline__ void unpack_rect(uint2 rc, uint32_t& xlo, uint32_t& xhi, uint32_t& ylo,
                                             uint32_t& yhi) {
@@ -78,28 +78,43 @@ __global__ void __launch_bounds__(256) k_group_count(Params P, int C, int QC,
     for (int t = threadIdx.x; t < G.ng; t += 256) out[t] = lcnt[t];
 }
 
-// One thread per (frame, group): exclusive scan of the group's column over
-// the chunks of its frame; totals per (frame, group).
-__global__ void k_group_colscan(Params P, int QC, uint32_t* __restrict__ cntA,
-                                uint32_t* __restrict__ lenA) {
+// grid (ceil(ng / 64), F), 1024 threads: lane = group within a block of 64,
+// wave = one sixteenth of the frame's chunk rows.  Exclusive scan of every
+// group's column over the chunks of its frame; totals per (frame, group).
+__global__ void __launch_bounds__(1024) k_group_colscan(Params P, int QC, uint32_t* __restrict__ cntA,
+                                                        uint32_t* __restrict__ lenA) {
+    __shared__ uint32_t part[16][64];
     const Groups G = groups_of(P);
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P.F * G.ng) return;
-    const int f = i / G.ng, gi = i - f * G.ng;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gi = blockIdx.x * 64 + lane;
+    const int f = blockIdx.y;
+    const int rows = (QC + 15) / 16;
+    const int q0 = wave * rows, q1 = min(q0 + rows, QC);
     uint32_t* col = cntA + (size_t)f * QC * G.ng + gi;
-    uint32_t run = 0;
-    for (int q = 0; q < QC; ++q) {
-        const uint32_t v = col[(size_t)q * G.ng];
-        col[(size_t)q * G.ng] = run;
-        run += v;
+    uint32_t s = 0;
+    if (gi < G.ng)
+        for (int q = q0; q < q1; ++q) s += col[(size_t)q * G.ng];
+    part[wave][lane] = s;
+    __syncthreads();
+    uint32_t run = 0, total = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wave) run += part[w][lane];
+        total += part[w][lane];
     }
-    lenA[i] = run;
+    if (gi < G.ng) {
+        for (int q = q0; q < q1; ++q) {
+            const uint32_t v = col[(size_t)q * G.ng];
+            col[(size_t)q * G.ng] = run;
+            run += v;
+        }
+        if (wave == 0) lenA[(size_t)f * G.ng + gi] = total;
+    }
 }
 
 // Single workgroup: group-list ranges (exclusive scan of the lengths) and the
 // first level-B segment of every group.  The level-A lists are bounded by the
 // pair capacity (every group entry yields at least one pair).
-__global__ void __launch_bounds__(1024) k_group_scan(const uint32_t* __restrict__ lenA, int K,
+__global__ void __launch_bounds__(1024) k_group_scan(const uint32_t* __restrict__ lenA, int K, int S,
                                                      unsigned long long cap, uint2* __restrict__ granges,
                                                      uint32_t* __restrict__ seg_start) {
     __shared__ unsigned long long scratch[17];
@@ -109,7 +124,7 @@ __global__ void __launch_bounds__(1024) k_group_scan(const uint32_t* __restrict_
     for (int base = 0; base < K; base += 1024) {
         const int i = base + threadIdx.x;
         const unsigned long long v = i < K ? lenA[i] : 0ull;
-        const uint32_t nsg = (uint32_t)((v + kSegment - 1) / kSegment);
+        const uint32_t nsg = (uint32_t)((v + S - 1) / S);
         unsigned long long tot;
         uint32_t stot;
         const unsigned long long ex = block_exclusive_scan<unsigned long long, 1024>(v, scratch, &tot);
@@ -126,7 +141,10 @@ __global__ void __launch_bounds__(1024) k_group_scan(const uint32_t* __restrict_
 }
 
 // One wave per chunk: the chunk's items in depth order append themselves to
-// the lists of the groups they touch (LDS cursors, lanes over the groups).
+// the lists of the groups they touch.  The cursors live in LDS and advance by
+// LDS atomics (in issue order within the wave, so depth order is kept); the
+// group rectangles of 64 items are prepared in parallel before the ordered
+// walk.
 __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
                                                     const uint32_t* __restrict__ dval,
                                                     const uint32_t* __restrict__ cnt,
@@ -136,7 +154,7 @@ __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
                                                     uint32_t* __restrict__ gval) {
     __shared__ uint32_t cursor[kMaxGroupsPerFrame];
     __shared__ uint32_t sitem[64];
-    __shared__ uint2 srect[64];
+    __shared__ uint4 sgrp[64];   // first group, groups per row, area, 1 / row as float bits
     const Groups G = groups_of(P);
     const int chunk = blockIdx.x;
     const int f = chunk / QC, q = chunk - f * QC;
@@ -146,31 +164,33 @@ __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
     for (int t = lane; t < G.ng; t += 64) cursor[t] = granges[(size_t)f * G.ng + t].x + pre[t];
     const long long beg = (long long)f * P.n + (long long)q * C;
     const long long end = min(beg + C, (long long)(f + 1) * P.n);
-    volatile uint32_t* cur = cursor;
     for (long long j0 = beg; j0 < end; j0 += 64) {
         __syncthreads();
         const int m = (int)min(64ll, end - j0);
         if (lane < m) {
             const uint32_t item = dval[j0 + lane];
-            const bool ok = cnt[item] != 0;
-            sitem[lane] = ok ? item : 0xffffffffu;
-            srect[lane] = ok ? rect[item] : make_uint2(0, 0);
+            uint4 gr = make_uint4(0, 1, 0, 0);
+            if (cnt[item] != 0) {
+                uint32_t xlo, xhi, ylo, yhi;
+                unpack_rect(rect[item], xlo, xhi, ylo, yhi);
+                const uint32_t gx0 = xlo / kGroupW, gy0 = ylo / kGroupH;
+                const uint32_t gw = xhi / kGroupW - gx0 + 1;
+                gr = make_uint4(gy0 * (uint32_t)G.ngx + gx0, gw, gw * (yhi / kGroupH - gy0 + 1),
+                                __float_as_uint(1.0f / (float)gw));
+            }
+            sitem[lane] = item;
+            sgrp[lane] = gr;
         }
         __syncthreads();
         for (int i = 0; i < m; ++i) {
-            const uint32_t item = sitem[i];
-            if (item == 0xffffffffu) continue;
-            uint32_t xlo, xhi, ylo, yhi;
-            unpack_rect(srect[i], xlo, xhi, ylo, yhi);
-            const uint32_t gx0 = xlo / kGroupW, gy0 = ylo / kGroupH;
-            const uint32_t gw = xhi / kGroupW - gx0 + 1;
-            const uint32_t area = gw * (yhi / kGroupH - gy0 + 1);
-            for (uint32_t k = lane; k < area; k += 64) {
-                const uint32_t gy = gy0 + k / gw, gx = gx0 + k % gw;
-                const uint32_t t = gy * (uint32_t)G.ngx + gx;
-                const uint32_t pos = cur[t];
-                cur[t] = pos + 1;
-                if (pos < cap) gval[pos] = item;
+            const uint4 gr = sgrp[i];
+            for (uint32_t k = lane; k < gr.z; k += 64) {
+                // k -> (row, column) of the item's group rectangle; the quotient
+                // of these small integers is exact with the float reciprocal
+                const uint32_t r = (uint32_t)(((float)k + 0.5f) * __uint_as_float(gr.w));
+                const uint32_t t = gr.x + r * (uint32_t)G.ngx + (k - r * gr.y);
+                const uint32_t pos = atomicAdd(&cursor[t], 1u);
+                if (pos < cap) gval[pos] = sitem[i];
             }
         }
     }
@@ -185,7 +205,7 @@ struct Segment {
 
 // Segment b -> (frame, group) and its entries; fg < 0 if b is past the last.
 __device__ __forceinline__ Segment find_segment(int b, const uint32_t* __restrict__ seg_start, int K,
-                                                const uint2* __restrict__ granges) {
+                                                int S, const uint2* __restrict__ granges) {
     Segment s;
     s.fg = -1;
     if ((uint32_t)b >= seg_start[K]) return s;
@@ -196,60 +216,136 @@ __device__ __forceinline__ Segment find_segment(int b, const uint32_t* __restric
     }
     const uint2 r = granges[lo];
     s.fg = lo;
-    s.beg = r.x + (uint32_t)(b - (int)seg_start[lo]) * kSegment;
-    s.end = min(s.beg + (uint32_t)kSegment, r.y);
+    s.beg = r.x + (uint32_t)(b - (int)seg_start[lo]) * (uint32_t)S;
+    s.end = min(s.beg + (uint32_t)S, r.y);
     return s;
 }
 
 // Lane l of the wave owns tile (gx * 8 + l % 8, gy * 8 + l / 8) of the group.
-template <bool PLACE>
-__global__ void __launch_bounds__(64) k_tile_pass(Params P, const uint32_t* __restrict__ seg_start,
-                                                  const uint2* __restrict__ granges,
-                                                  const uint32_t* __restrict__ gval,
-                                                  const uint2* __restrict__ rect,
-                                                  uint32_t* __restrict__ cntB,
-                                                  const uint2* __restrict__ ranges,
-                                                  uint32_t* __restrict__ tval) {
-    __shared__ uint32_t sitem[64];
+struct LaneTile {
+    int f;
+    uint32_t tx, ty, tile;
+    bool mine;
+};
+
+__device__ __forceinline__ LaneTile lane_tile(const Params& P, const Groups& G, int fg, int lane) {
+    LaneTile t;
+    t.f = fg / G.ng;
+    const int gi = fg - t.f * G.ng;
+    const uint32_t gy = gi / G.ngx, gx = gi - gy * G.ngx;
+    t.tx = gx * kGroupW + lane % kGroupW;
+    t.ty = gy * kGroupH + lane / kGroupW;
+    t.mine = t.tx < (uint32_t)P.ntx && t.ty < (uint32_t)P.nty;
+    t.tile = t.ty * (uint32_t)P.ntx + t.tx;
+    return t;
+}
+
+// Counting pass: entries of the segment that cover each lane's tile.
+__global__ void __launch_bounds__(64) k_tile_count(Params P, int S, const uint32_t* __restrict__ seg_start,
+                                                   const uint2* __restrict__ granges,
+                                                   const uint32_t* __restrict__ gval,
+                                                   const uint2* __restrict__ rect,
+                                                   uint32_t* __restrict__ cntB) {
     __shared__ uint2 srect[64];
     const Groups G = groups_of(P);
     const int K = P.F * G.ng;
     const uint32_t nseg = seg_start[K];
-    for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
-    const Segment sg = find_segment((int)b, seg_start, K, granges);
     const int lane = threadIdx.x;
-    const int f = sg.fg / G.ng, gi = sg.fg - f * G.ng;
-    const uint32_t gy = gi / G.ngx, gx = gi - gy * G.ngx;
-    const uint32_t tx = gx * kGroupW + lane % kGroupW, ty = gy * kGroupH + lane / kGroupW;
-    const bool mine = tx < (uint32_t)P.ntx && ty < (uint32_t)P.nty;
-    const uint32_t tile = ty * (uint32_t)P.ntx + tx;
-    const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
-    uint32_t c = 0;
-    if (PLACE && mine) c = ranges[(size_t)f * P.n_tiles + tile].x + cntB[(size_t)b * 64 + lane];
-    for (uint32_t j0 = sg.beg; j0 < sg.end; j0 += 64) {
-        const int m = (int)min(64u, sg.end - j0);
-        __syncthreads();
-        if (lane < m) {
-            const uint32_t item = gval[j0 + lane];
-            sitem[lane] = item;
-            srect[lane] = rect[item];
-        }
-        __syncthreads();
-        for (int i = 0; i < m; ++i) {
-            uint32_t xlo, xhi, ylo, yhi;
-            unpack_rect(srect[i], xlo, xhi, ylo, yhi);
-            const bool cov = mine && tx >= xlo && tx <= xhi && ty >= ylo && ty <= yhi;
-            if (PLACE) {
-                if (cov) {
-                    if (c < cap) tval[c] = sitem[i];
-                    ++c;
-                }
-            } else {
-                c += cov ? 1u : 0u;
+    for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
+        const Segment sg = find_segment((int)b, seg_start, K, S, granges);
+        const LaneTile lt = lane_tile(P, G, sg.fg, lane);
+        uint32_t c = 0;
+        for (uint32_t j0 = sg.beg; j0 < sg.end; j0 += 64) {
+            const int m = (int)min(64u, sg.end - j0);
+            __syncthreads();
+            if (lane < m) srect[lane] = rect[gval[j0 + lane]];
+            __syncthreads();
+            for (int i = 0; i < m; ++i) {
+                uint32_t xlo, xhi, ylo, yhi;
+                unpack_rect(srect[i], xlo, xhi, ylo, yhi);
+                c += (lt.mine && lt.tx >= xlo && lt.tx <= xhi && lt.ty >= ylo && lt.ty <= yhi) ? 1u : 0u;
             }
         }
+        cntB[(size_t)b * 64 + lane] = c;
     }
-    if (!PLACE) cntB[(size_t)b * 64 + lane] = c;
+}
+
+// Placing pass.  Each lane appends the covering entries of its tile to a
+// 32-entry LDS line buffer that mirrors the 128-byte line of the tile list
+// it is filling; a full line is written by 32 lanes at once, so global
+// stores are whole lines except at the ends of each lane's run.
+__global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32_t* __restrict__ seg_start,
+                                                   const uint2* __restrict__ granges,
+                                                   const uint32_t* __restrict__ gval,
+                                                   const uint2* __restrict__ rect,
+                                                   const uint32_t* __restrict__ cntB,
+                                                   const uint2* __restrict__ ranges,
+                                                   uint32_t* __restrict__ tval) {
+    __shared__ uint32_t sitem[64];
+    __shared__ uint2 srect[64];
+    __shared__ uint32_t lbuf_[64][kLine + 1];  // +1: lanes of one slot hit different banks
+    // Lanes read lines other lanes wrote: LDS operations of one wave complete
+    // in issue order, and volatile keeps the compiler from reordering them.
+    volatile uint32_t(*lbuf)[kLine + 1] = lbuf_;
+    const Groups G = groups_of(P);
+    const int K = P.F * G.ng;
+    const uint32_t nseg = seg_start[K];
+    const int lane = threadIdx.x;
+    const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
+
+    // writes slots [lo, hi) of lane L's buffer to tval[base + slot]
+    auto flush = [&](uint32_t base, uint32_t lo, uint32_t hi, int L) {
+        const uint32_t k = (uint32_t)lane;
+        if (k >= lo && k < hi && base + k < cap) tval[base + k] = lbuf[L][k];
+    };
+
+    for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
+        const Segment sg = find_segment((int)b, seg_start, K, S, granges);
+        const LaneTile lt = lane_tile(P, G, sg.fg, lane);
+        uint32_t c = 0;   // next list position of this lane's tile
+        if (lt.mine) c = ranges[(size_t)lt.f * P.n_tiles + lt.tile].x + cntB[(size_t)b * 64 + lane];
+        uint32_t base = c & ~(uint32_t)(kLine - 1);   // list position of buffer slot 0
+        uint32_t lo = c - base;                       // first slot this lane owns
+        for (uint32_t j0 = sg.beg; j0 < sg.end; j0 += 64) {
+            const int m = (int)min(64u, sg.end - j0);
+            __syncthreads();
+            if (lane < m) {
+                const uint32_t item = gval[j0 + lane];
+                sitem[lane] = item;
+                srect[lane] = rect[item];
+            }
+            __syncthreads();
+            for (int i = 0; i < m; ++i) {
+                uint32_t xlo, xhi, ylo, yhi;
+                unpack_rect(srect[i], xlo, xhi, ylo, yhi);
+                const bool cov = lt.mine && lt.tx >= xlo && lt.tx <= xhi && lt.ty >= ylo && lt.ty <= yhi;
+                if (cov) {
+                    lbuf[lane][c - base] = sitem[i];
+                    ++c;
+                }
+                unsigned long long full = __ballot(c - base == (uint32_t)kLine);
+                while (full) {
+                    const int L = __builtin_ctzll(full);
+                    full &= full - 1;
+                    const uint32_t bL = __builtin_amdgcn_readlane(base, L);
+                    const uint32_t lL = __builtin_amdgcn_readlane(lo, L);
+                    flush(bL, lL, kLine, L);
+                }
+                if (c - base == (uint32_t)kLine) {
+                    base += kLine;
+                    lo = 0;
+                }
+            }
+        }
+        // partial last lines
+        unsigned long long rest = __ballot(c - base > lo);
+        while (rest) {
+            const int L = __builtin_ctzll(rest);
+            rest &= rest - 1;
+            flush(__builtin_amdgcn_readlane(base, L), __builtin_amdgcn_readlane(lo, L),
+                  __builtin_amdgcn_readlane(c - base, L), L);
+        }
+        __syncthreads();
     }
 }
 
@@ -321,11 +417,13 @@ BinGeom bin_geometry(int64_t n, int32_t n_frames, int ntx, int nty, uint64_t cap
     g.C = C;
     g.QC = n > 0 ? (int)((n + C - 1) / C) : 0;
     g.ng = ((ntx + kGroupW - 1) / kGroupW) * ((nty + kGroupH - 1) / kGroupH);
-    // every segment but the last of each group list holds kSegment entries,
-    // and the group lists hold at most min(cap, M * groups) entries
+    // level-B segment: long runs per lane for large batches, more waves for small ones
+    g.S = M >= (1 << 20) ? 512 : 128;
+    // every segment but the last of each group list holds S entries, and the
+    // group lists hold at most min(cap, M * groups) entries
     uint64_t entries = cap;
     if ((uint64_t)M * g.ng < entries) entries = (uint64_t)M * g.ng;
-    g.max_segments = (int64_t)((entries + kSegment - 1) / kSegment) + (int64_t)n_frames * g.ng;
+    g.max_segments = (int64_t)((entries + g.S - 1) / g.S) + (int64_t)n_frames * g.ng;
     return g;
 }
 
@@ -340,15 +438,15 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     if (chunks) {
         ProfScope _p("k_group_colscan", s);
-        hipLaunchKernelGGL(k_group_colscan, dim3((K + 255) / 256), dim3(256), 0, s, P, g.QC, w.cntA,
-                           w.lenA);
+        hipLaunchKernelGGL(k_group_colscan, dim3((g.ng + 63) / 64, P.F), dim3(1024), 0, s, P, g.QC,
+                           w.cntA, w.lenA);
     } else {
         launch_fill_u32(w.lenA, 0u, K, s);
     }
     {
         ProfScope _p("k_group_scan", s);
-        hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, s, w.lenA, K, (unsigned long long)P.cap,
-                           w.granges, w.seg_start);
+        hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, s, w.lenA, K, g.S,
+                           (unsigned long long)P.cap, w.granges, w.seg_start);
     }
     if (chunks) {
         ProfScope _p("k_group_place", s);
@@ -359,8 +457,8 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     const unsigned segs = (unsigned)(g.max_segments < 16384 ? g.max_segments : 16384);
     {
         ProfScope _p("k_tile_count", s);
-        hipLaunchKernelGGL(k_tile_pass<false>, dim3(segs), dim3(64), 0, s, P, w.seg_start, w.granges,
-                           w.gval, w.rect, w.cntB, w.ranges, w.tval);
+        hipLaunchKernelGGL(k_tile_count, dim3(segs), dim3(64), 0, s, P, g.S, w.seg_start, w.granges,
+                           w.gval, w.rect, w.cntB);
     }
     {
         ProfScope _p("k_tile_colscan", s);
@@ -373,7 +471,7 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     {
         ProfScope _p("k_tile_place", s);
-        hipLaunchKernelGGL(k_tile_pass<true>, dim3(segs), dim3(64), 0, s, P, w.seg_start, w.granges,
+        hipLaunchKernelGGL(k_tile_place, dim3(segs), dim3(64), 0, s, P, g.S, w.seg_start, w.granges,
                            w.gval, w.rect, w.cntB, w.ranges, w.tval);
     }
     return hipGetLastError();

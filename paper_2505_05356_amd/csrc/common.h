@@ -25,6 +25,7 @@ struct BinGeom {
     int C;                 // items per level-A chunk
     int QC;                // chunks per frame
     int ng;                // groups of 8x8 tiles per frame
+    int S;                 // group-list entries per level-B segment
     int64_t max_segments;  // bound on the level-B segments
 };
 BinGeom bin_geometry(int64_t n, int32_t n_frames, int ntx, int nty, uint64_t cap);
