@@ -181,12 +181,15 @@ int gftorf_read_status(const void* ws, gftorf_status* out, void* stream);
  *     key (float32 bits of the camera-space z; 0xFFFFFFFF for culled items);
  *   item_count: tiles covered per item (0 = culled), item order;
  *   item_rect: [M][2] packed tile rectangles (x_lo | x_hi << 16,
- *     y_lo | y_hi << 16), item order.
- * Every destination may be NULL. */
+ *     y_lo | y_hi << 16), item order;
+ *   tile_ranges: [n_frames * n_tiles][2] [start, end) of every tile list in
+ *     the pair arrays.
+ * Every destination may be NULL.  Synchronises `stream` to read the pair
+ * count. */
 int gftorf_copy_lists(const void* ws, int64_t n, int32_t n_frames, const gftorf_config* cfg,
                       uint32_t* pair_key, uint32_t* pair_item, int64_t pair_capacity,
                       uint32_t* depth_key, uint32_t* depth_item, uint32_t* item_count,
-                      uint32_t* item_rect, void* stream);
+                      uint32_t* item_rect, uint32_t* tile_ranges, void* stream);
 
 /* L2 loss (paper Eq. 9, L2 part): for f < n_frames, with target frame
  * s = frame_index[f] (device int32 [n_frames], or NULL for s = f):

@@ -197,3 +197,18 @@ def tile_lists(pairs, frame, n_tiles):
     idx = pairs["index"][sel]
     bounds = np.searchsorted(tile, np.arange(n_tiles + 1))
     return [idx[bounds[t]:bounds[t + 1]] for t in range(n_tiles)]
+
+
+def lists_for_tiles(proj, cfg, tiles):
+    """Sorted Gaussian lists of selected tiles of one frame, straight from the
+    rectangle test: the same lists as `frame_pairs`, for a few tiles of a
+    large frame without building every pair."""
+    xl, xh, yl, yh = proj["rect"]
+    valid = proj["valid"]
+    out = {}
+    for tid in tiles:
+        ty, tx = divmod(int(tid), cfg.tiles_x)
+        idx = np.nonzero(valid & (xl <= tx) & (tx <= xh) & (yl <= ty) & (ty <= yh))[0]
+        order = np.lexsort((idx, proj["key"][idx]))
+        out[int(tid)] = idx[order]
+    return out

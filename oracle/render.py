@@ -241,7 +241,8 @@ def render(g, frames, cfg, tiles=None, upstream=None, flag_rel=(1e-5, 1e-4),
     ntx, nty = cfg.tiles_x, cfg.tiles_y
     n_tiles = ntx * nty
     NQ = cfg.n_quad
-    pairs = binning.sorted_pairs(g, frames, cfg)
+    # every tile: all pairs of the batch; a tile subset: only those tiles' lists
+    pairs = binning.sorted_pairs(g, frames, cfg) if tiles is None else None
     out = dict(rgb=np.full((F, 3, H, Wd), np.nan), quad=np.full((F, NQ, H, Wd), np.nan),
                depth=np.full((F, H, Wd), np.nan), T_final=np.full((F, H, Wd), np.nan),
                n_contrib=np.full((F, H, Wd), -1, np.int64),
@@ -261,8 +262,12 @@ def render(g, frames, cfg, tiles=None, upstream=None, flag_rel=(1e-5, 1e-4),
         bgr = torch.tensor(_w(frame.bg_rgb), requires_grad=want_grad)
         bq_np = np.zeros(NQ) if frame.bg_quad is None else _w(frame.bg_quad).reshape(-1)
         bgq = torch.tensor(bq_np, requires_grad=want_grad)
-        lists = binning.tile_lists(pairs, f, n_tiles)
-        tile_ids = range(n_tiles) if tiles is None else tiles[f]
+        if tiles is None:
+            lists = binning.tile_lists(pairs, f, n_tiles)
+            tile_ids = range(n_tiles)
+        else:
+            tile_ids = tiles[f]
+            lists = binning.lists_for_tiles(binning.project(g, frame, cfg), cfg, tile_ids)
         for tid in tile_ids:
             ty, tx = divmod(int(tid), ntx)
             gx = tx * cfg.tile_w + lx

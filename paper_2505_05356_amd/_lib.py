@@ -71,7 +71,7 @@ _SIGS = {
     "gftorf_read_status": (c_int32, [c_void_p, POINTER(StatusC), c_void_p]),
     "gftorf_copy_lists": (c_int32, [c_void_p, c_int64, c_int32, POINTER(ConfigC), c_void_p,
                                     c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
-                                    c_void_p]),
+                                    c_void_p, c_void_p]),
     "gftorf_l2_loss_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int64, c_float,
                                       c_void_p, c_void_p, c_void_p]),
     "gftorf_adam_step": (c_int32, [POINTER(AdamGroupC), c_int32, c_void_p, c_float, c_float,

@@ -270,7 +270,7 @@ int gftorf_read_status(const void* ws, gftorf_status* out, void* stream) {
 int gftorf_copy_lists(const void* ws, int64_t n, int32_t n_frames, const gftorf_config* cfg,
                       uint32_t* pair_key, uint32_t* pair_item, int64_t pair_capacity,
                       uint32_t* depth_key, uint32_t* depth_item, uint32_t* item_count,
-                      uint32_t* item_rect, void* stream) {
+                      uint32_t* item_rect, uint32_t* tile_ranges, void* stream) {
     gft::Params P;
     int rc = build_params(n, n_frames, cfg, &P);
     if (rc) return rc;
@@ -296,6 +296,7 @@ int gftorf_copy_lists(const void* ws, int64_t n, int32_t n_frames, const gftorf_
     cp(depth_item, w.dval[db], 4 * (size_t)w.M);
     cp(item_count, w.cnt, 4 * (size_t)w.M);
     cp(item_rect, w.rect, 8 * (size_t)w.M);
+    cp(tile_ranges, w.ranges, 8 * (size_t)P.F * P.n_tiles);
     if (e != hipSuccess) return hip_fail(e, "gftorf_copy_lists");
     return GFTORF_OK;
 }

@@ -32,28 +32,36 @@ def run_gpu(g, frames, cfg, upstream=None, max_pairs=None, want_bg=False, device
     return res
 
 
-def gpu_lists(res, g, frames, cfg):
-    """Sorted pairs and per-item binning copied out of the workspace."""
+def gpu_lists(res, g, frames, cfg, pairs_to_host=True):
+    """Tile lists and per-item binning copied out of the workspace.  With
+    pairs_to_host=False the pair arrays stay on the device (large batches)."""
     lib = _lib.load()
     ws = res["_ws"]
     n, F = g.n, len(frames)
     M = n * F
+    K = F * cfg.tiles_x * cfg.tiles_y
     P = min(res["status"]["n_pairs"], ws.max_pairs)
     dev = "cuda"
-    pk = torch.empty(max(P, 1), dtype=torch.int32, device=dev)
+    pk = torch.empty(max(P, 1), dtype=torch.int32, device=dev) if pairs_to_host else None
     pi = torch.empty(max(P, 1), dtype=torch.int32, device=dev)
     dk = torch.empty(max(M, 1), dtype=torch.int32, device=dev)
     di = torch.empty(max(M, 1), dtype=torch.int32, device=dev)
     cnt = torch.empty(max(M, 1), dtype=torch.int32, device=dev)
     rect = torch.empty(max(2 * M, 1), dtype=torch.int32, device=dev)
-    v = lambda t: ctypes.c_void_p(t.data_ptr())
+    rng = torch.empty(2 * K, dtype=torch.int32, device=dev)
+    v = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
     _lib.check(lib.gftorf_copy_lists(ctypes.c_void_p(ws.ptr), n, F, ctypes.byref(ws.cstruct),
-                                     v(pk), v(pi), P, v(dk), v(di), v(cnt), v(rect),
+                                     v(pk), v(pi), P, v(dk), v(di), v(cnt), v(rect), v(rng),
                                      ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
     torch.cuda.synchronize()
     u = lambda t, k: t.cpu().numpy().view(np.uint32)[:k]
-    return dict(pair_key=u(pk, P), pair_item=u(pi, P), depth_key=u(dk, M), depth_item=u(di, M),
-                count=u(cnt, M), rect=u(rect, 2 * M).reshape(M, 2), P=P)
+    out = dict(depth_key=u(dk, M), depth_item=u(di, M), count=u(cnt, M),
+               rect=u(rect, 2 * M).reshape(M, 2), ranges=u(rng, 2 * K).reshape(K, 2), P=P)
+    if pairs_to_host:
+        out["pair_key"], out["pair_item"] = u(pk, P), u(pi, P)
+    else:
+        out["pair_item_dev"] = pi
+    return out
 
 
 def assert_images_close(got, ref, ok, name, rtol=FWD_RTOL):

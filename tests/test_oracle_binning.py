@@ -127,3 +127,15 @@ def test_scene_generation_deterministic():
         assert getattr(a, k).tobytes() == getattr(b, k).tobytes()
         assert getattr(a, k).dtype == np.float32
     assert a.mean.tobytes() != c.mean.tobytes()
+
+
+def test_lists_for_tiles_equal_full_binning():
+    wl = scenes.cfg3(n=2000, n_frames=2)
+    pairs = binning.sorted_pairs(wl.gaussians, wl.frames, wl.cfg)
+    n_tiles = wl.cfg.tiles_x * wl.cfg.tiles_y
+    for f, fr in enumerate(wl.frames):
+        full = binning.tile_lists(pairs, f, n_tiles)
+        some = binning.lists_for_tiles(binning.project(wl.gaussians, fr, wl.cfg), wl.cfg,
+                                       [0, 7, n_tiles // 2, n_tiles - 1])
+        for t, lst in some.items():
+            np.testing.assert_array_equal(lst, full[t])
