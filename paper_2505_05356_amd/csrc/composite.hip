@@ -236,6 +236,16 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
 // Backward: one wave per (frame, tile); each lane owns PPT pixels of the tile
 // (pixel p = lane + 64 i), so the per-entry cross-lane reduction of the
 // gradient fields is paid once for PPT pixels.
+//
+// The upstream gradients are constant per pixel, so the recursions of Eq. S2
+// (RGB and depth, factor 1 - alpha) and Eq. S3 (quads, factor (1 - alpha)^2)
+// only enter dL/dalpha through two scalars per pixel:
+//   s1 = sum_c dL/dc_c acc_c + dL/dd acc_d,
+//   s2 = sum_f dL/dS_f acc_S,f + dL/dC_f acc_C,f,
+// which obey the same recursions with the per-entry values
+//   u = sum_c dL/dc_c c_k,c + dL/dd d_k and v = sum_f dL/dS_f a sin psi + dL/dC_f a cos psi:
+//   dL/dalpha_k = T_k (u - s1) + T_k^2 (v + 2 (alpha_k - 1) s2) - bg / (1 - alpha_k),
+//   s1 <- alpha_k u + (1 - alpha_k) s1,  s2 <- alpha_k v + (1 - alpha_k)^2 s2.
 template <int TW, int TH, int NF>
 __global__ void __launch_bounds__(64) k_composite_bwd(
     Params P, const gftorf_frame* __restrict__ frames, const uint2* __restrict__ ranges,
@@ -262,10 +272,9 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
     const gftorf_frame& fr = frames[f];
     const size_t HW = (size_t)P.H * P.W;
 
-    float fpx[PPT], fpy[PPT], T[PPT], bgT[PPT];
+    float fpx[PPT], fpy[PPT], T[PPT], bgT[PPT], s1[PPT], s2[PPT];
     uint32_t last[PPT];
     float gr[PPT][3], gd[PPT], gS[PPT][NF], gC[PPT][NF];
-    float acc_c[PPT][3], acc_d[PPT], acc_s[PPT][NF], acc_k[PPT][NF];
     float bg_acc[3 + GFTORF_MAX_QUAD];
     const int nbg = 3 + P.nq;
     for (int c = 0; c < 3 + GFTORF_MAX_QUAD; ++c) bg_acc[c] = 0.f;
@@ -311,9 +320,7 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
         // c_bg . dL/dc T_final + p q_bg . dL/dq T_final^p
         bgT[i] = brd * Tf + (float)P.bg_pow * bqd * Tp;
         T[i] = Tf;
-        acc_c[i][0] = acc_c[i][1] = acc_c[i][2] = acc_d[i] = 0.f;
-#pragma unroll
-        for (int k = 0; k < NF; ++k) acc_s[i][k] = acc_k[i][k] = 0.f;
+        s1[i] = s2[i] = 0.f;
         maxl = max(maxl, last[i]);
     }
     // background gradients: dL/dc_bg = sum d_rgb T_final, dL/dq_bg = sum d_quad T_final^p
@@ -353,47 +360,48 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
 #pragma unroll
             for (int q = 0; q < NGP; ++q) g[q] = 0.f;
             bool any = false;
+            // Branch-free per pixel: inactive pixels contribute zero and keep
+            // their state (selects instead of divergent blocks, so the field
+            // registers are never copied at control-flow joins).
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 float dx, dy, G;
                 const float a = splat_alpha(r0, r1, fpx[i], fpy[i], amax, dx, dy, G);
-                if (!(kidx < last[i] && a >= amin)) continue;
-                any = true;
+                const bool act = kidx < last[i] && a >= amin;
+                any |= act;
                 const float om = 1.0f - a;
-                const float Ti = __fdividef(T[i], om);
-                T[i] = Ti;
+                const float rom = __builtin_amdgcn_rcpf(om);
+                const float Ti = T[i] * rom;
                 const float T2 = Ti * Ti;
-                float dA = gr[i][0] * (Ti * (r2.x - acc_c[i][0])) + gr[i][1] * (Ti * (r2.y - acc_c[i][1])) +
-                           gr[i][2] * (Ti * (r2.z - acc_c[i][2]));
-                dA += gd[i] * (Ti * (r2.w - acc_d[i]));
-                dA -= __fdividef(bgT[i], om);
-                const float w1 = a * Ti, w2 = a * T2;
+                const float u = gr[i][0] * r2.x + gr[i][1] * r2.y + gr[i][2] * r2.z + gd[i] * r2.w;
+                float v = 0.f;
+#pragma unroll
+                for (int k = 0; k < NF; ++k) v += gS[i][k] * as[k] + gC[i][k] * ac[k];
+                const float dA = Ti * (u - s1[i]) + T2 * (v + 2.0f * (a - 1.0f) * s2[i]) - bgT[i] * rom;
+                T[i] = act ? Ti : T[i];
+                s1[i] = act ? a * u + om * s1[i] : s1[i];
+                s2[i] = act ? a * v + (om * om) * s2[i] : s2[i];
+                const float w1 = act ? a * Ti : 0.0f;
+                const float w2 = act ? a * T2 : 0.0f;
                 g[6] += w1 * gr[i][0];
                 g[7] += w1 * gr[i][1];
                 g[8] += w1 * gr[i][2];
                 g[9] += w1 * gd[i];
 #pragma unroll
                 for (int k = 0; k < NF; ++k) {
-                    dA += T2 * (gS[i][k] * (as[k] + 2.0f * (a - 1.0f) * acc_s[i][k]) +
-                                gC[i][k] * (ac[k] + 2.0f * (a - 1.0f) * acc_k[i][k]));
                     g[10 + 2 * k] += w2 * gS[i][k];
                     g[11 + 2 * k] += w2 * gC[i][k];
-                    acc_s[i][k] = a * as[k] + om * om * acc_s[i][k];
-                    acc_k[i][k] = a * ac[k] + om * om * acc_k[i][k];
                 }
-                acc_c[i][0] = a * r2.x + om * acc_c[i][0];
-                acc_c[i][1] = a * r2.y + om * acc_c[i][1];
-                acc_c[i][2] = a * r2.z + om * acc_c[i][2];
-                acc_d[i] = a * r2.w + om * acc_d[i];
-                if (r1.w * G <= amax) {   // not clamped: alpha = o 2^q
-                    const float gq = dA * a * LN2;
-                    g[5] += G * dA;                                  // d/do
-                    g[2] += gq * dx * dx;                            // d/dcA
-                    g[3] += gq * dx * dy;                            // d/dcB
-                    g[4] += gq * dy * dy;                            // d/dcC
-                    g[0] -= gq * (2.0f * r1.x * dx + r1.y * dy);     // d/du
-                    g[1] -= gq * (2.0f * r1.z * dy + r1.y * dx);     // d/dv
-                }
+                // alpha = o 2^q unless clamped (then alpha has no gradient)
+                const float dAe = (act && r1.w * G <= amax) ? dA : 0.0f;
+                const float gq = dAe * a * LN2;
+                const float gx = gq * dx, gy = gq * dy;
+                g[5] += G * dAe;                                 // d/do
+                g[2] += gx * dx;                                 // d/dcA
+                g[3] += gx * dy;                                 // d/dcB
+                g[4] += gy * dy;                                 // d/dcC
+                g[0] -= 2.0f * r1.x * gx + r1.y * gy;            // d/du
+                g[1] -= 2.0f * r1.z * gy + r1.y * gx;            // d/dv
             }
             if (__ballot(any) == 0ull) continue;
             // one reduce-scatter over the wave, then one atomic instruction whose
