@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--frames", type=int, default=8)
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="16x16", help="WxH (8x8, 16x16, 32x8) or auto")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle tile work in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -72,16 +72,24 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    tw, th = (int(x) for x in args.tile.split("x"))
     wl = scenes.cfg3(n=args.n, n_frames=args.frames)
-    cfg = dataclasses.replace(wl.cfg, tile_w=tw, tile_h=th)
     F = len(wl.frames)
     g = wl.gaussians
     params = raster.to_device_params(g, dev)
+    up = scenes.upstream_grads(F, wl.cfg, seed=1)
+    d = {k: torch.from_numpy(v).to(dev) for k, v in up.items()}
+    tile_times = None
+    if args.tile == "auto":
+        from paper_2505_05356_amd import autotune
+        cfg, tile_times = autotune.autotune(params, raster.pack_frames(wl.frames, wl.cfg, dev),
+                                            wl.cfg, upstream=d, reps=5, warmup=2)
+        args.tile = f"{cfg.tile_w}x{cfg.tile_h}"
+        print(f"# autotuned tile {args.tile}: {tile_times}", file=sys.stderr, flush=True)
+    else:
+        tw, th = (int(x) for x in args.tile.split("x"))
+        cfg = dataclasses.replace(wl.cfg, tile_w=tw, tile_h=th)
     fdev = raster.pack_frames(wl.frames, cfg, dev)
     fdev1 = [fdev[f:f + 1].contiguous() for f in range(F)]
-    up = scenes.upstream_grads(F, cfg, seed=1)
-    d = {k: torch.from_numpy(v).to(dev) for k, v in up.items()}
     d1 = [{k: v[f:f + 1].contiguous() for k, v in d.items()} for f in range(F)]
 
     # batched path: size the pair capacity once (one checked forward), then
@@ -188,7 +196,8 @@ def main():
                    "n_gaussians": g.n, "frames": F, "width": cfg.width, "height": cfg.height,
                    "tile": args.tile, "freqs_hz": list(cfg.freqs), "quads": cfg.n_quad,
                    "outputs": "rgb+quad+depth", "pairs": P, "evals_fwd": work["E_fwd"],
-                   "evals_bwd": work["E_bwd"], "composited": work["C"]},
+                   "evals_bwd": work["E_bwd"], "composited": work["C"],
+                   "tile_times_ms": tile_times},
         "per_frame_value": None if per_frame is None else round(per_frame, 2),
         "batched_over_per_frame": None if per_frame is None else round(value / per_frame, 3),
         "roofline": roof,
