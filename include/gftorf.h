@@ -115,13 +115,24 @@ typedef struct gftorf_config {
 /* Forward outputs.  rgb [F][3][H][W], quad [F][n_freq*n_phase][H][W] (quad
  * channel index = freq * n_phase + phase), depth [F][H][W]: each may be NULL
  * (not written).  T_final [F][H][W] and n_contrib [F][H][W] are required:
- * the backward pass reads them. */
+ * the backward pass reads them.
+ * Time-of-flight epilogue, per frequency f, from the rendered quads Q_j
+ * (background included): S^ = sum_j cos(phi_j) Q_j, C^ = sum_j sin(phi_j) Q_j
+ * -- for the offsets 0, pi/2, pi, 3pi/2 exactly Q0 - Qpi and Qpi/2 - Q3pi/2
+ * of paper Eq. 1.  phasor [F][n_freq][2][H][W] = (C^, S^), the phasor of
+ * Eq. 3; d_tof [F][n_freq][H][W] = c / (4 pi f) (atan2(S^, C^) mod 2 pi)
+ * (Eq. 1 with the quadrant resolved); amplitude [F][n_freq][H][W] =
+ * |(C^, S^)| / 2 (paper §2).  These three may be NULL; they are outputs only
+ * (the backward pass does not differentiate them). */
 typedef struct gftorf_outputs {
     float* rgb;
     float* quad;
     float* depth;
     float* T_final;
     int32_t* n_contrib;
+    float* phasor;
+    float* d_tof;
+    float* amplitude;
 } gftorf_outputs;
 
 typedef struct gftorf_status {

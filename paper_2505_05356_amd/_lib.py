@@ -44,7 +44,8 @@ class ConfigC(ctypes.Structure):
 
 class OutputsC(ctypes.Structure):
     _fields_ = [("rgb", c_void_p), ("quad", c_void_p), ("depth", c_void_p),
-                ("T_final", c_void_p), ("n_contrib", c_void_p)]
+                ("T_final", c_void_p), ("n_contrib", c_void_p), ("phasor", c_void_p),
+                ("d_tof", c_void_p), ("amplitude", c_void_p)]
 
 
 class StatusC(ctypes.Structure):

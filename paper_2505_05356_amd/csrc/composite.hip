@@ -228,6 +228,30 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
                 o[qc * HW] = P.cphi[jj] * S[i] + P.sphi[jj] * C[i] + fr.bg_quad[qc] * Tp;
             }
     }
+    if (out.phasor || out.d_tof || out.amplitude) {
+        const float Tp = P.bg_pow == 2 ? T * T : T;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            float sh = 0.f, ch = 0.f;   // projections of the rendered quads (Eq. 1)
+            for (int jj = 0; jj < P.nphi; ++jj) {
+                const int qc = i * P.nphi + jj;
+                const float q = P.cphi[jj] * S[i] + P.sphi[jj] * C[i] + fr.bg_quad[qc] * Tp;
+                sh += P.cphi[jj] * q;
+                ch += P.sphi[jj] * q;
+            }
+            const size_t o = ((size_t)f * P.nf + i) * HW + pix;
+            if (out.phasor) {
+                out.phasor[(((size_t)f * P.nf + i) * 2) * HW + pix] = ch;
+                out.phasor[(((size_t)f * P.nf + i) * 2 + 1) * HW + pix] = sh;
+            }
+            if (out.d_tof) {
+                float ph = atan2f(sh, ch);
+                if (ph < 0.f) ph += 6.283185307179586f;
+                out.d_tof[o] = (float)(kSpeedOfLight / (4.0 * M_PI * P.freq[i])) * ph;
+            }
+            if (out.amplitude) out.amplitude[o] = 0.5f * sqrtf(sh * sh + ch * ch);
+        }
+    }
     if (out.depth) out.depth[(size_t)f * HW + pix] = dep;
     out.T_final[(size_t)f * HW + pix] = T;
     out.n_contrib[(size_t)f * HW + pix] = (int32_t)last;

@@ -161,12 +161,19 @@ def alloc_outputs(n_frames, cfg, device="cuda", channels=("rgb", "quad", "depth"
         out["quad"] = torch.empty((n_frames, n_quad(cfg), H, W), device=device)
     if "depth" in channels:
         out["depth"] = torch.empty((n_frames, H, W), device=device)
+    nf = len(cfg.freqs)
+    if "phasor" in channels:
+        out["phasor"] = torch.empty((n_frames, nf, 2, H, W), device=device)
+    if "d_tof" in channels:
+        out["d_tof"] = torch.empty((n_frames, nf, H, W), device=device)
+    if "amplitude" in channels:
+        out["amplitude"] = torch.empty((n_frames, nf, H, W), device=device)
     return out
 
 
 def outputs_struct(out) -> _lib.OutputsC:
     o = _lib.OutputsC()
-    for k in ("rgb", "quad", "depth", "T_final", "n_contrib"):
+    for k in ("rgb", "quad", "depth", "T_final", "n_contrib", "phasor", "d_tof", "amplitude"):
         setattr(o, k, out[k].data_ptr() if out.get(k) is not None else None)
     return o
 

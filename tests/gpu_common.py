@@ -11,11 +11,13 @@ FWD_RTOL = 1e-4     # per channel image: |gpu - ref| <= 1e-4 (|ref| + max |ref|)
 GRAD_RTOL = 2e-2    # per parameter tensor: relative L2 and elementwise (|ref| + max |ref|)
 
 
-def run_gpu(g, frames, cfg, upstream=None, max_pairs=None, want_bg=False, device="cuda"):
+def run_gpu(g, frames, cfg, upstream=None, max_pairs=None, want_bg=False, device="cuda",
+            channels=("rgb", "quad", "depth")):
     params = raster.to_device_params(g, device)
     fdev = raster.pack_frames(frames, cfg, device)
     ws = raster.Workspace(g.n, len(frames), cfg, max_pairs=max_pairs, device=device)
-    out = raster.forward(params, fdev, cfg, ws)
+    out = raster.forward(params, fdev, cfg, ws,
+                         out=raster.alloc_outputs(len(frames), cfg, device, channels))
     res = {k: v.cpu().numpy() for k, v in out.items()}
     res["status"] = ws.status()
     res["_ws"], res["_params"], res["_frames"], res["_out"] = ws, params, fdev, out

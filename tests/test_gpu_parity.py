@@ -162,3 +162,44 @@ def test_nonfinite_gaussians_are_culled_and_counted():
     res = run_gpu(g, wl.frames, wl.cfg)
     assert res["status"]["nonfinite"] == 2
     assert np.isfinite(res["rgb"]).all()
+
+
+@pytest.mark.parametrize("name", ["cfg1", "two-freq", "dynamic-3f-32x8-p2"])
+def test_tof_epilogue_matches_oracle(name, oracle_cache):
+    # Phasor, d_ToF and amplitude written by the forward kernel against the
+    # oracle's epilogue applied to the oracle's own quads.  The bound follows
+    # from the quad tolerance: each projection is a sum of the n_phase quads
+    # with weights of modulus <= 1, so its error is at most
+    # e = FWD_RTOL * sum_j (|Q_j| + max |Q_j|); the amplitude then moves by at
+    # most e / sqrt(2) and the phase by about sqrt(2) e / |phasor| where the
+    # phasor is well away from zero.
+    from oracle import tof
+    from tests.gpu_common import FWD_RTOL
+    wl = CASES[name]
+    cfg = wl.cfg
+    ref, _ = _oracle(name, oracle_cache)
+    res = run_gpu(wl.gaussians, wl.frames, cfg,
+                  channels=("quad", "phasor", "d_tof", "amplitude"))
+    exp = tof.tof_epilogue(ref["quad"], cfg)
+    ok = ~ref["flagged"]
+    F, H, W = ok.shape
+    nf, nphi = len(cfg.freqs), len(cfg.phases)
+    q = ref["quad"].astype(np.float64).reshape(F, nf, nphi, H, W)
+    qmax = np.abs(q).max(axis=(-2, -1), keepdims=True)
+    e = FWD_RTOL * (np.abs(q) + qmax).sum(2) * 1.01 + 1e-6 * qmax.max()
+    okf = np.broadcast_to(ok[:, None], e.shape)
+    for c in range(2):
+        err = np.abs(res["phasor"][:, :, c].astype(np.float64) - exp["phasor"][:, :, c])
+        assert np.all(err[okf] <= e[okf]), f"{name}/phasor[{c}] max excess {np.max(err[okf] - e[okf]):.3g}"
+    err = np.abs(res["amplitude"].astype(np.float64) - exp["amplitude"])
+    assert np.all(err[okf] <= e[okf]), f"{name}/amplitude"
+    # phase: only where the phasor is at least 10 error bounds long
+    mag = 2 * exp["amplitude"]
+    well = okf & (mag > 10 * np.sqrt(2) * e)
+    assert well.mean() > 0.5, f"{name}: too few well-conditioned pixels ({well.mean():.2%})"
+    lam = np.array([299_792_458.0 / (2 * f) for f in cfg.freqs])[None, :, None, None]
+    dd = np.abs(res["d_tof"].astype(np.float64) - exp["d_tof"])
+    dd = np.minimum(dd, lam - dd)            # distance modulo the ambiguity range c / 2f
+    tol = lam / (2 * np.pi) * (1.5 * np.sqrt(2) * e / np.maximum(mag, 1e-30)) + 1e-6 * lam
+    assert np.all(dd[well] <= tol[well]), f"{name}/d_tof max excess {np.max(dd[well] - tol[well]):.3g} m"
+    assert np.all((res["d_tof"] >= 0) & (res["d_tof"] <= lam * (1 + 1e-6)))
