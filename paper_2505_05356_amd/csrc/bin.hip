@@ -9,16 +9,15 @@
 // Level A -- items into groups of 8x8 tiles.  The depth-ordered items of a
 //   frame are cut into chunks: per-chunk group counts (LDS), a column scan
 //   over the chunks, an exclusive scan over (frame, group), then one wave per
-//   chunk places its items in depth order into the group lists.  An item
-//   touches only a few groups, so these lists are short.
+//   chunk places 64 items at a time, every lane at once: the lanes that share
+//   a group come from four ballot masks (by group column and row), and a
+//   lane's rank among them is its offset in that group's list.
 // Level B -- group lists into tile lists.  Each group list is cut into
-//   segments of 512 entries; one wave per segment, lane l owning tile l of
-//   the group.  A counting pass, a column scan over each group's segments and
-//   an exclusive scan over (frame, tile) give every lane a cursor; the
-//   placing pass then walks the segment in order and each lane appends the
-//   items that cover its tile.  Every tile list is written by one lane at a
-//   time in increasing addresses, so the writes coalesce, and the order is
-//   the depth order by construction.
+//   segments; one wave per segment.  A counting pass (an 8x8 difference array
+//   per segment), a column scan over each group's segments and an exclusive
+//   scan over (frame, tile) give every tile a cursor; the placing pass takes
+//   64 entries at a time and, tile by tile, ballots the covering lanes, which
+//   write one contiguous run of the tile's list in depth order.
 #include "block_scan.h"
 #include "common.h"
 
@@ -27,7 +26,6 @@ namespace gft {
 namespace {
 
 constexpr int kGroupW = 8, kGroupH = 8;   // tiles per group (one per lane)
-constexpr int kLine = 32;                 // u32 entries per 128-byte cache line
 
 __device__ __forceinline__ void unpack_rect(uint2 rc, uint32_t& xlo, uint32_t& xhi, uint32_t& ylo,
                                             uint32_t& yhi) {
@@ -140,11 +138,17 @@ __global__ void __launch_bounds__(1024) k_group_scan(const uint32_t* __restrict_
     if (threadIdx.x == 0) seg_start[K] = scarry;
 }
 
-// One wave per chunk: the chunk's items in depth order append themselves to
-// the lists of the groups they touch.  The cursors live in LDS and advance by
-// LDS atomics (in issue order within the wave, so depth order is kept); the
-// group rectangles of 64 items are prepared in parallel before the ordered
-// walk.
+// Rank of this lane among the lanes of `peers` below it.
+__device__ __forceinline__ uint32_t rank_below(uint64_t peers) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+}
+
+// One wave per chunk, 64 depth-ordered items at a time (lane = item).  Every
+// (item, group) entry takes the position cursor[group] + (number of lanes
+// below it whose group rectangle also contains that group); the set of such
+// lanes is the AND of four ballot masks looked up by column and row, so all
+// lanes place their entries at once and the depth order inside every group
+// list is kept.  The leaders (lowest lane per group) then advance the cursors.
 __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
                                                     const uint32_t* __restrict__ dval,
                                                     const uint32_t* __restrict__ cnt,
@@ -152,10 +156,13 @@ __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
                                                     const uint32_t* __restrict__ cntA,
                                                     const uint2* __restrict__ granges,
                                                     uint32_t* __restrict__ gval) {
-    __shared__ uint32_t cursor[kMaxGroupsPerFrame];
-    __shared__ uint32_t sitem[64];
-    __shared__ uint4 sgrp[64];   // first group, groups per row, area, 1 / row as float bits
+    extern __shared__ uint64_t dyn_[];
     const Groups G = groups_of(P);
+    uint64_t* x_lo = dyn_;             // [ngx] lanes whose first group column <= v
+    uint64_t* x_hi = x_lo + G.ngx;     // [ngx] lanes whose last group column >= v
+    uint64_t* y_lo = x_hi + G.ngx;     // [ngy] same for rows
+    uint64_t* y_hi = y_lo + G.ngy;
+    uint32_t* cursor = reinterpret_cast<uint32_t*>(y_hi + G.ngy);   // [ng]
     const int chunk = blockIdx.x;
     const int f = chunk / QC, q = chunk - f * QC;
     const int lane = threadIdx.x;
@@ -164,33 +171,49 @@ __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
     for (int t = lane; t < G.ng; t += 64) cursor[t] = granges[(size_t)f * G.ng + t].x + pre[t];
     const long long beg = (long long)f * P.n + (long long)q * C;
     const long long end = min(beg + C, (long long)(f + 1) * P.n);
+    const int nv = max(G.ngx, G.ngy);
     for (long long j0 = beg; j0 < end; j0 += 64) {
-        __syncthreads();
-        const int m = (int)min(64ll, end - j0);
-        if (lane < m) {
-            const uint32_t item = dval[j0 + lane];
-            uint4 gr = make_uint4(0, 1, 0, 0);
+        int gx0 = 1, gx1 = 0, gy0 = 1, gy1 = 0;   // empty: never in a ballot
+        uint32_t item = 0;
+        if (j0 + lane < end) {
+            item = dval[j0 + lane];
             if (cnt[item] != 0) {
                 uint32_t xlo, xhi, ylo, yhi;
                 unpack_rect(rect[item], xlo, xhi, ylo, yhi);
-                const uint32_t gx0 = xlo / kGroupW, gy0 = ylo / kGroupH;
-                const uint32_t gw = xhi / kGroupW - gx0 + 1;
-                gr = make_uint4(gy0 * (uint32_t)G.ngx + gx0, gw, gw * (yhi / kGroupH - gy0 + 1),
-                                __float_as_uint(1.0f / (float)gw));
+                gx0 = (int)(xlo / kGroupW);
+                gx1 = (int)(xhi / kGroupW);
+                gy0 = (int)(ylo / kGroupH);
+                gy1 = (int)(yhi / kGroupH);
             }
-            sitem[lane] = item;
-            sgrp[lane] = gr;
+        }
+        __syncthreads();   // the previous round's table and cursor reads are done
+        for (int v = 0; v < nv; ++v) {
+            const uint64_t a = __ballot(gx0 <= v), b = __ballot(gx1 >= v);
+            const uint64_t c = __ballot(gy0 <= v), d = __ballot(gy1 >= v);
+            if (lane == 0) {
+                if (v < G.ngx) { x_lo[v] = a; x_hi[v] = b; }
+                if (v < G.ngy) { y_lo[v] = c; y_hi[v] = d; }
+            }
         }
         __syncthreads();
-        for (int i = 0; i < m; ++i) {
-            const uint4 gr = sgrp[i];
-            for (uint32_t k = lane; k < gr.z; k += 64) {
-                // k -> (row, column) of the item's group rectangle; the quotient
-                // of these small integers is exact with the float reciprocal
-                const uint32_t r = (uint32_t)(((float)k + 0.5f) * __uint_as_float(gr.w));
-                const uint32_t t = gr.x + r * (uint32_t)G.ngx + (k - r * gr.y);
-                const uint32_t pos = atomicAdd(&cursor[t], 1u);
-                if (pos < cap) gval[pos] = sitem[i];
+        const int gw = gx1 - gx0 + 1;
+        const int area = gw > 0 ? gw * (gy1 - gy0 + 1) : 0;
+        {
+            int gx = gx0, gy = gy0;
+            for (int k = 0; k < area; ++k) {
+                const uint64_t peers = x_lo[gx] & x_hi[gx] & y_lo[gy] & y_hi[gy];
+                const uint32_t pos = cursor[gy * G.ngx + gx] + rank_below(peers);
+                if (pos < cap) gval[pos] = item;
+                if (++gx > gx1) { gx = gx0; ++gy; }
+            }
+        }
+        __syncthreads();   // every lane has read the cursors of this round
+        {
+            int gx = gx0, gy = gy0;
+            for (int k = 0; k < area; ++k) {
+                const uint64_t peers = x_lo[gx] & x_hi[gx] & y_lo[gy] & y_hi[gy];
+                if (rank_below(peers) == 0) cursor[gy * G.ngx + gx] += (uint32_t)__popcll(peers);
+                if (++gx > gx1) { gx = gx0; ++gy; }
             }
         }
     }
@@ -240,13 +263,40 @@ __device__ __forceinline__ LaneTile lane_tile(const Params& P, const Groups& G, 
     return t;
 }
 
-// Counting pass: entries of the segment that cover each lane's tile.
+// An entry's tile rectangle clipped to the 8x8 tiles of its group, in group
+// coordinates (the entry is in the group's list, so the clip is not empty).
+struct LocalRect {
+    uint32_t x0, x1, y0, y1;
+};
+
+__device__ __forceinline__ LocalRect local_rect(uint2 rc, uint32_t ox, uint32_t oy) {
+    uint32_t xlo, xhi, ylo, yhi;
+    unpack_rect(rc, xlo, xhi, ylo, yhi);
+    LocalRect r;
+    r.x0 = max(xlo, ox) - ox;
+    r.x1 = min(xhi, ox + kGroupW - 1) - ox;
+    r.y0 = max(ylo, oy) - oy;
+    r.y1 = min(yhi, oy + kGroupH - 1) - oy;
+    return r;
+}
+
+// Bit y * 8 + x set for every tile (x, y) of the rectangle.
+__device__ __forceinline__ uint64_t cover_mask(const LocalRect& r) {
+    const uint64_t row = (uint64_t)(((2u << r.x1) - (1u << r.x0)) & 0xffu) * 0x0101010101010101ull;
+    const uint64_t upto = r.y1 >= 7 ? ~0ull : ((1ull << (8 * (r.y1 + 1))) - 1);
+    const uint64_t below = (1ull << (8 * r.y0)) - 1;
+    return row & upto & ~below;
+}
+
+// Counting pass: entries of the segment that cover each lane's tile.  Every
+// entry adds the four corners of its rectangle to an 8x8 difference array
+// in LDS; a 2-D prefix sum across the lanes turns it into per-tile counts.
 __global__ void __launch_bounds__(64) k_tile_count(Params P, int S, const uint32_t* __restrict__ seg_start,
                                                    const uint2* __restrict__ granges,
                                                    const uint32_t* __restrict__ gval,
                                                    const uint2* __restrict__ rect,
                                                    uint32_t* __restrict__ cntB) {
-    __shared__ uint2 srect[64];
+    __shared__ int diff[64];
     const Groups G = groups_of(P);
     const int K = P.F * G.ng;
     const uint32_t nseg = seg_start[K];
@@ -254,26 +304,37 @@ __global__ void __launch_bounds__(64) k_tile_count(Params P, int S, const uint32
     for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
         const Segment sg = find_segment((int)b, seg_start, K, S, granges);
         const LaneTile lt = lane_tile(P, G, sg.fg, lane);
-        uint32_t c = 0;
-        for (uint32_t j0 = sg.beg; j0 < sg.end; j0 += 64) {
-            const int m = (int)min(64u, sg.end - j0);
-            __syncthreads();
-            if (lane < m) srect[lane] = rect[gval[j0 + lane]];
-            __syncthreads();
-            for (int i = 0; i < m; ++i) {
-                uint32_t xlo, xhi, ylo, yhi;
-                unpack_rect(srect[i], xlo, xhi, ylo, yhi);
-                c += (lt.mine && lt.tx >= xlo && lt.tx <= xhi && lt.ty >= ylo && lt.ty <= yhi) ? 1u : 0u;
-            }
+        const uint32_t ox = lt.tx - lane % kGroupW, oy = lt.ty - lane / kGroupW;
+        diff[lane] = 0;
+        __syncthreads();
+        for (uint32_t j = sg.beg + lane; j < sg.end; j += 64) {
+            const LocalRect r = local_rect(rect[gval[j]], ox, oy);
+            const bool xin = r.x1 + 1 < (uint32_t)kGroupW, yin = r.y1 + 1 < (uint32_t)kGroupH;
+            atomicAdd(&diff[r.y0 * kGroupW + r.x0], 1);
+            if (xin) atomicAdd(&diff[r.y0 * kGroupW + r.x1 + 1], -1);
+            if (yin) atomicAdd(&diff[(r.y1 + 1) * kGroupW + r.x0], -1);
+            if (xin && yin) atomicAdd(&diff[(r.y1 + 1) * kGroupW + r.x1 + 1], 1);
         }
-        cntB[(size_t)b * 64 + lane] = c;
+        __syncthreads();
+        int v = diff[lane];
+        for (int d = 1; d < kGroupW; d <<= 1) {
+            const int u = __shfl_up(v, d, 64);
+            if (lane % kGroupW >= d) v += u;
+        }
+        for (int d = kGroupW; d < 64; d <<= 1) {
+            const int u = __shfl_up(v, d, 64);
+            if (lane >= d) v += u;
+        }
+        cntB[(size_t)b * 64 + lane] = (uint32_t)v;
+        __syncthreads();   // diff is cleared for the next segment
     }
 }
 
-// Placing pass.  Each lane appends the covering entries of its tile to a
-// 32-entry LDS line buffer that mirrors the 128-byte line of the tile list
-// it is filling; a full line is written by 32 lanes at once, so global
-// stores are whole lines except at the ends of each lane's run.
+// Placing pass, 64 entries at a time (lane = entry).  For every tile of the
+// group that some entry covers, a ballot gives the covering lanes; each
+// writes at the tile's cursor plus its rank among them, so one store
+// instruction fills a contiguous run of that tile's list.  Lane t holds the
+// cursor of tile t.
 __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32_t* __restrict__ seg_start,
                                                    const uint2* __restrict__ granges,
                                                    const uint32_t* __restrict__ gval,
@@ -281,71 +342,46 @@ __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32
                                                    const uint32_t* __restrict__ cntB,
                                                    const uint2* __restrict__ ranges,
                                                    uint32_t* __restrict__ tval) {
-    __shared__ uint32_t sitem[64];
-    __shared__ uint2 srect[64];
-    __shared__ uint32_t lbuf_[64][kLine + 1];  // +1: lanes of one slot hit different banks
-    // Lanes read lines other lanes wrote: LDS operations of one wave complete
-    // in issue order, and volatile keeps the compiler from reordering them.
-    volatile uint32_t(*lbuf)[kLine + 1] = lbuf_;
     const Groups G = groups_of(P);
     const int K = P.F * G.ng;
     const uint32_t nseg = seg_start[K];
     const int lane = threadIdx.x;
     const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
-
-    // writes slots [lo, hi) of lane L's buffer to tval[base + slot]
-    auto flush = [&](uint32_t base, uint32_t lo, uint32_t hi, int L) {
-        const uint32_t k = (uint32_t)lane;
-        if (k >= lo && k < hi && base + k < cap) tval[base + k] = lbuf[L][k];
-    };
-
     for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
         const Segment sg = find_segment((int)b, seg_start, K, S, granges);
         const LaneTile lt = lane_tile(P, G, sg.fg, lane);
-        uint32_t c = 0;   // next list position of this lane's tile
-        if (lt.mine) c = ranges[(size_t)lt.f * P.n_tiles + lt.tile].x + cntB[(size_t)b * 64 + lane];
-        uint32_t base = c & ~(uint32_t)(kLine - 1);   // list position of buffer slot 0
-        uint32_t lo = c - base;                       // first slot this lane owns
+        const uint32_t ox = lt.tx - lane % kGroupW, oy = lt.ty - lane / kGroupW;
+        uint32_t cur = 0;   // next list position of this lane's tile
+        if (lt.mine) cur = ranges[(size_t)lt.f * P.n_tiles + lt.tile].x + cntB[(size_t)b * 64 + lane];
         for (uint32_t j0 = sg.beg; j0 < sg.end; j0 += 64) {
-            const int m = (int)min(64u, sg.end - j0);
-            __syncthreads();
-            if (lane < m) {
-                const uint32_t item = gval[j0 + lane];
-                sitem[lane] = item;
-                srect[lane] = rect[item];
+            const uint32_t j = j0 + lane;
+            uint32_t item = 0;
+            uint64_t mask = 0;
+            if (j < sg.end) {
+                item = gval[j];
+                mask = cover_mask(local_rect(rect[item], ox, oy));
             }
-            __syncthreads();
-            for (int i = 0; i < m; ++i) {
-                uint32_t xlo, xhi, ylo, yhi;
-                unpack_rect(srect[i], xlo, xhi, ylo, yhi);
-                const bool cov = lt.mine && lt.tx >= xlo && lt.tx <= xhi && lt.ty >= ylo && lt.ty <= yhi;
-                if (cov) {
-                    lbuf[lane][c - base] = sitem[i];
-                    ++c;
+            // tiles covered by any lane
+            uint32_t lo = (uint32_t)mask, hi = (uint32_t)(mask >> 32);
+            for (int d = 32; d > 0; d >>= 1) {
+                lo |= (uint32_t)__shfl_xor((int)lo, d, 64);
+                hi |= (uint32_t)__shfl_xor((int)hi, d, 64);
+            }
+            uint64_t todo = ((uint64_t)__builtin_amdgcn_readfirstlane(hi) << 32) |
+                            (uint64_t)__builtin_amdgcn_readfirstlane(lo);
+            while (todo) {
+                const int t = __builtin_ctzll(todo);
+                todo &= todo - 1;
+                const bool c = (mask >> t) & 1ull;
+                const uint64_t peers = __ballot(c);
+                const uint32_t base = __builtin_amdgcn_readlane(cur, t);
+                if (c) {
+                    const uint32_t pos = base + rank_below(peers);
+                    if (pos < cap) tval[pos] = item;
                 }
-                unsigned long long full = __ballot(c - base == (uint32_t)kLine);
-                while (full) {
-                    const int L = __builtin_ctzll(full);
-                    full &= full - 1;
-                    const uint32_t bL = __builtin_amdgcn_readlane(base, L);
-                    const uint32_t lL = __builtin_amdgcn_readlane(lo, L);
-                    flush(bL, lL, kLine, L);
-                }
-                if (c - base == (uint32_t)kLine) {
-                    base += kLine;
-                    lo = 0;
-                }
+                if (lane == t) cur += (uint32_t)__popcll(peers);
             }
         }
-        // partial last lines
-        unsigned long long rest = __ballot(c - base > lo);
-        while (rest) {
-            const int L = __builtin_ctzll(rest);
-            rest &= rest - 1;
-            flush(__builtin_amdgcn_readlane(base, L), __builtin_amdgcn_readlane(lo, L),
-                  __builtin_amdgcn_readlane(c - base, L), L);
-        }
-        __syncthreads();
     }
 }
 
@@ -450,7 +486,9 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     if (chunks) {
         ProfScope _p("k_group_place", s);
-        hipLaunchKernelGGL(k_group_place, dim3(chunks), dim3(64), 0, s, P, g.C, g.QC, w.dval[dbuf],
+        const int ngx = (P.ntx + kGroupW - 1) / kGroupW, ngy = (P.nty + kGroupH - 1) / kGroupH;
+        const size_t lds = 16 * (size_t)(ngx + ngy) + 4 * (size_t)g.ng;
+        hipLaunchKernelGGL(k_group_place, dim3(chunks), dim3(64), lds, s, P, g.C, g.QC, w.dval[dbuf],
                            w.cnt, w.rect, w.cntA, w.granges, w.gval);
     }
     // persistent level-B grid: every wave loops over segments
