@@ -29,17 +29,32 @@ namespace gft {
 
 namespace {
 
-// alpha of one (pixel, entry) pair.  One definition shared by the forward and
-// the backward kernels, with contraction pinned, so both take identical skip
-// / stop / clamp decisions.
-__device__ __forceinline__ float splat_alpha(const float4 r0, const float4 r1, float px, float py,
-                                             float amax, float& dx, float& dy, float& G) {
+// Base-2 exponent q of the 2-D Gaussian at (px, py): the conic is stored
+// prescaled by -log2(e) / 2 (-log2(e) for the cross term), so o G = o 2^q.
+// One definition shared by the forward and the backward kernels, with
+// contraction pinned, so both take identical skip / stop / clamp decisions.
+__device__ __forceinline__ float splat_q(const float4 c, const float4 r1, float px, float py, float& dx,
+                                         float& dy) {
 #pragma clang fp contract(off)
-    dx = (px - r0.x) - r0.z;
-    dy = (py - r0.y) - r0.w;
-    const float q = __builtin_fmaf(r1.x * dx, dx, __builtin_fmaf(r1.y * dx, dy, (r1.z * dy) * dy));
-    G = __builtin_amdgcn_exp2f(q);
-    return fminf(r1.w * G, amax);
+    dx = px - c.x;
+    dy = py - c.y;
+    return __builtin_fmaf(dx, __builtin_fmaf(r1.y, dy, r1.x * dx), (r1.z * dy) * dy);
+}
+
+// Below this exponent (log2 units) alpha < alpha_min with room to spare for
+// the rounding of exp2, the product and the threshold itself.
+constexpr float kSkipMargin = 1.0f / 64.0f;
+
+// The staged form of an entry's centre for one tile: the centre relative to
+// the tile origin (the hi + lo pair folded once per entry), and the exponent
+// threshold thr with q < thr  =>  min(o 2^q, alpha_max) < alpha_min, which
+// lets the backward skip an entry that no pixel of the tile can take without
+// changing any decision.
+// lamin = log2(alpha_min), or -inf when alpha_min = 0 (nothing skipped).
+__device__ __forceinline__ float4 stage_centre(const float4 r0, float o, float ox, float oy, float lamin) {
+    const float cu = (r0.x - ox) + r0.z;
+    const float cv = (r0.y - oy) + r0.w;
+    return make_float4(cu, cv, (lamin - __log2f(o)) - kSkipMargin, 0.f);
 }
 
 // Sum over the 64 lanes of a wave: DPP within rows of 16, then 4 readlanes.
@@ -100,7 +115,7 @@ __device__ __forceinline__ float allreduce_from(float r) {
 
 // Field whose wave total lane `lane` holds after wave_reduce_fields<NP>.
 template <int NP>
-__device__ __forceinline__ int field_of_lane(int lane) {
+__host__ __device__ constexpr int field_of_lane(int lane) {
     int f = 0;
 #pragma unroll
     for (int D = 1; D < NP; D *= 2)
@@ -133,9 +148,12 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
     const int tid = threadIdx.x;
     const int x = tx * TW + (tid % TW), y = ty * TH + (tid / TW);
     const bool inside = x < P.W && y < P.H;
-    const float fpx = (float)x + 0.5f, fpy = (float)y + 0.5f;
+    // pixel centre relative to the tile origin (exact small values)
+    const float fpx = (float)(tid % TW) + 0.5f, fpy = (float)(tid / TW) + 0.5f;
+    const float ox = (float)(tx * TW), oy = (float)(ty * TH);
     const uint2 rg = ranges[w];
     const float amin = P.alpha_min, amax = P.alpha_max, tmin = P.T_min;
+    const float lamin = amin > 0.f ? __log2f(amin) : -INFINITY;
 
     float T = 1.0f;
     float cr = 0.f, cg = 0.f, cb = 0.f, dep = 0.f;
@@ -144,27 +162,34 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
     for (int i = 0; i < NF; ++i) S[i] = C[i] = 0.f;
     bool done = !inside;
     uint32_t last = 0;
-    uint32_t n_eval = 0, n_comp = 0;
+    uint32_t n_eval = 0, n_comp = 0;   // evaluated / composited (pixel, entry) pairs
 
     for (uint32_t b0 = rg.x; b0 < rg.y; b0 += BS) {
         if (__syncthreads_count(!done) == 0) break;
         const uint32_t j = b0 + tid;
         if (j < rg.y) {
             const float4* r = rec + (size_t)tval[j] * RS4;
+            const float4 r1 = r[1];
+            srec[0][tid] = stage_centre(r[0], r1.w, ox, oy, lamin);
+            srec[1][tid] = r1;
 #pragma unroll
-            for (int q = 0; q < RS4; ++q) srec[q][tid] = r[q];
+            for (int q = 2; q < RS4; ++q) srec[q][tid] = r[q];
         }
         __syncthreads();
-        const int cnt = (int)min((uint32_t)BS, rg.y - b0);
+        const int cnt = __builtin_amdgcn_readfirstlane((int)min((uint32_t)BS, rg.y - b0));
+        // Divergent per pixel (a lane that is done or skips an entry simply
+        // idles): measured faster here than branch-free selects with
+        // wave-uniform ballot exits.
         for (int k = 0; k < cnt; ++k) {
             if (done) continue;
             ++n_eval;
-            const float4 r0 = srec[0][k], r1 = srec[1][k];
-            float dx, dy, G;
-            const float a = splat_alpha(r0, r1, fpx, fpy, amax, dx, dy, G);
+            const float4 c = srec[0][k], r1 = srec[1][k];
+            float dx, dy;
+            const float qe = splat_q(c, r1, fpx, fpy, dx, dy);
+            const float a = fminf(r1.w * __builtin_amdgcn_exp2f(qe), amax);
             if (a < amin) continue;
             const float nT = T * (1.0f - a);
-            if (nT < tmin) {
+            if (nT < tmin) {   // stop before compositing
                 done = true;
                 continue;
             }
@@ -178,10 +203,8 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
 #pragma unroll
             for (int i = 0; i < NF; ++i) {
                 const float4 rp = srec[3 + i / 2][k];
-                const float as = (i & 1) ? rp.z : rp.x;
-                const float ac = (i & 1) ? rp.w : rp.y;
-                S[i] += as * w2;
-                C[i] += ac * w2;
+                S[i] += ((i & 1) ? rp.z : rp.x) * w2;
+                C[i] += ((i & 1) ? rp.w : rp.y) * w2;
             }
             T = nT;
             ++n_comp;
@@ -283,6 +306,8 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
     constexpr int GS = grad_floats(NF);
     constexpr int NG = 10 + 2 * NF;            // gradient fields per entry
     constexpr int NGP = NG <= 16 ? 16 : 32;    // padded to a power of two
+    static_assert(field_of_lane<NGP>(0) == 0 && field_of_lane<NGP>(NGP / 2) == 1,
+                  "lanes 0 and NGP / 2 hold the totals of fields 0 and 1");
     __shared__ float4 srec[RS4][B];
     __shared__ uint32_t sitem[B];
 
@@ -293,6 +318,8 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
     const int lane = threadIdx.x;
     const uint2 rg = ranges[w];
     const float amin = P.alpha_min, amax = P.alpha_max;
+    const float lamin = amin > 0.f ? __log2f(amin) : -INFINITY;
+    const float ox = (float)(tx * TW), oy = (float)(ty * TH);
     const gftorf_frame& fr = frames[f];
     const size_t HW = (size_t)P.H * P.W;
 
@@ -308,8 +335,8 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
         const int pidx = lane + 64 * i;
         const int x = tx * TW + pidx % TW, y = ty * TH + pidx / TW;
         const bool inside = x < P.W && y < P.H;
-        fpx[i] = (float)x + 0.5f;
-        fpy[i] = (float)y + 0.5f;
+        fpx[i] = (float)(pidx % TW) + 0.5f;   // relative to the tile origin
+        fpy[i] = (float)(pidx / TW) + 0.5f;
         const size_t pix = (size_t)y * P.W + x;
         float Tf = 1.f, Tp = 1.f, brd = 0.f, bqd = 0.f;
         last[i] = 0;
@@ -366,13 +393,30 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
             const uint32_t item = tval[hi - 1 - lane];
             sitem[lane] = item;
             const float4* r = rec + (size_t)item * RS4;
+            const float4 r1 = r[1];
+            srec[0][lane] = stage_centre(r[0], r1.w, ox, oy, lamin);
+            srec[1][lane] = r1;
 #pragma unroll
-            for (int q = 0; q < RS4; ++q) srec[q][lane] = r[q];
+            for (int q = 2; q < RS4; ++q) srec[q][lane] = r[q];
         }
         __syncthreads();
         for (int s = 0; s < cnt; ++s) {
             const uint32_t kidx = hi - 1 - (uint32_t)s - rg.x;   // position in the tile list
-            const float4 r0 = srec[0][s], r1 = srec[1][s], r2 = srec[2][s];
+            const float4 c = srec[0][s], r1 = srec[1][s];
+            // phase 1: which pixels can composite this entry (the forward's
+            // decisions: not past the pixel's last entry, exponent above the
+            // certain-skip threshold); an entry no pixel takes costs no more
+            float dx[PPT], dy[PPT], qe[PPT];
+            bool pass[PPT];
+            bool anyp = false;
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                qe[i] = splat_q(c, r1, fpx[i], fpy[i], dx[i], dy[i]);
+                pass[i] = kidx < last[i] && !(qe[i] < c.z);
+                anyp |= pass[i];
+            }
+            if (__ballot(anyp) == 0ull) continue;
+            const float4 r2 = srec[2][s];
             float as[NF], ac[NF];
 #pragma unroll
             for (int k = 0; k < NF; ++k) {
@@ -389,11 +433,15 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
             // registers are never copied at control-flow joins).
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
-                float dx, dy, G;
-                const float a = splat_alpha(r0, r1, fpx[i], fpy[i], amax, dx, dy, G);
-                const bool act = kidx < last[i] && a >= amin;
+                const float G = __builtin_amdgcn_exp2f(qe[i]);
+                const float oG = r1.w * G;
+                const float a = fminf(oG, amax);
+                const bool act = pass[i] && a >= amin;
                 any |= act;
-                const float om = 1.0f - a;
+                // ae = alpha of a composited entry, 0 otherwise: with ae = 0
+                // every state update below is the identity (rcp(1) = 1)
+                const float ae = act ? a : 0.0f;
+                const float om = 1.0f - ae;
                 const float rom = __builtin_amdgcn_rcpf(om);
                 const float Ti = T[i] * rom;
                 const float T2 = Ti * Ti;
@@ -402,11 +450,11 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
 #pragma unroll
                 for (int k = 0; k < NF; ++k) v += gS[i][k] * as[k] + gC[i][k] * ac[k];
                 const float dA = Ti * (u - s1[i]) + T2 * (v + 2.0f * (a - 1.0f) * s2[i]) - bgT[i] * rom;
-                T[i] = act ? Ti : T[i];
-                s1[i] = act ? a * u + om * s1[i] : s1[i];
-                s2[i] = act ? a * v + (om * om) * s2[i] : s2[i];
-                const float w1 = act ? a * Ti : 0.0f;
-                const float w2 = act ? a * T2 : 0.0f;
+                T[i] = Ti;
+                s1[i] = __builtin_fmaf(ae, u - s1[i], s1[i]);        // alpha u + (1 - alpha) s1
+                s2[i] = __builtin_fmaf(ae, v, (om * om) * s2[i]);    // alpha v + (1 - alpha)^2 s2
+                const float w1 = ae * Ti;
+                const float w2 = ae * T2;
                 g[6] += w1 * gr[i][0];
                 g[7] += w1 * gr[i][1];
                 g[8] += w1 * gr[i][2];
@@ -416,22 +464,32 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
                     g[10 + 2 * k] += w2 * gS[i][k];
                     g[11 + 2 * k] += w2 * gC[i][k];
                 }
-                // alpha = o 2^q unless clamped (then alpha has no gradient)
-                const float dAe = (act && r1.w * G <= amax) ? dA : 0.0f;
-                const float gq = dAe * a * LN2;
-                const float gx = gq * dx, gy = gq * dy;
+                // alpha = o 2^q unless clamped (then alpha has no gradient).
+                // gq = dL/dq / ln 2; the factor ln 2 of fields 0..4 and the
+                // conic of the centre gradient are applied once per entry.
+                const float dAe = (act && oG <= amax) ? dA : 0.0f;
+                const float gq = dAe * a;
+                const float gx = gq * dx[i], gy = gq * dy[i];
                 g[5] += G * dAe;                                 // d/do
-                g[2] += gx * dx;                                 // d/dcA
-                g[3] += gx * dy;                                 // d/dcB
-                g[4] += gy * dy;                                 // d/dcC
-                g[0] -= 2.0f * r1.x * gx + r1.y * gy;            // d/du
-                g[1] -= 2.0f * r1.z * gy + r1.y * gx;            // d/dv
+                g[2] += gx * dx[i];                              // d/dcA
+                g[3] += gx * dy[i];                              // d/dcB
+                g[4] += gy * dy[i];                              // d/dcC
+                g[0] += gx;                                      // sum gx
+                g[1] += gy;                                      // sum gy
             }
             if (__ballot(any) == 0ull) continue;
             // one reduce-scatter over the wave, then one atomic instruction whose
             // lanes add consecutive fields of the entry's gradient record
-            const float tot = wave_reduce_fields<NGP>(g, lane);
+            float tot = wave_reduce_fields<NGP>(g, lane);
             const int fld = field_of_lane<NGP>(lane);
+            // fields 0 and 1 hold sum gx and sum gy (lanes 0 and NGP / 2):
+            // d/du = -(2 cA sum gx + cB sum gy), d/dv = -(2 cC sum gy + cB sum gx)
+            const float sgx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tot), 0));
+            const float sgy =
+                __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tot), NGP / 2));
+            if (fld == 0) tot = -(2.0f * r1.x * sgx + r1.y * sgy);
+            if (fld == 1) tot = -(2.0f * r1.z * sgy + r1.y * sgx);
+            if (fld < 5) tot *= LN2;
             if (lane < NGP && fld < NG && tot != 0.f)
                 atomicAdd(grec + (size_t)sitem[s] * GS + fld, tot);
         }
