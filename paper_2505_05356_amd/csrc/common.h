@@ -13,8 +13,8 @@ constexpr float kLog2e = 1.4426950408889634f;
 
 // Radix sort geometry: 256 threads (4 wave64), 16 keys per thread.
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per tile
 constexpr int kSortBuckets = 256;                       // <= 8 digit bits per pass
 
 // Tile binning works on chunks of depth-sorted items of one frame, first into
@@ -73,8 +73,8 @@ struct Workspace {
     uint32_t* cnt;          // [M] tiles covered
     uint32_t* dkey[2];      // [M] depth keys (double buffer)
     uint32_t* dval[2];      // [M] item ids
-    uint32_t* counts;       // [256][max_sort_tiles] per-tile digit counts of the depth sort
-    uint32_t* totals;       // [256]
+    uint32_t* counts;       // [F][256][max_sort_tiles] per-tile digit counts of the depth sort
+    uint32_t* totals;       // [F][256] digit totals per frame
     uint32_t* cntA;         // [F][QC][ng] per-chunk group counts, then column prefixes
     uint32_t* lenA;         // [F * ng] group-list lengths
     uint2* granges;         // [F * ng] group-list ranges in gval
@@ -105,7 +105,7 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nt
     const int64_t M = n * F;
     const BinGeom g = bin_geometry(n, F, ntx, nty, cap);
     w.M = M;
-    w.max_sort_tiles = (M + kSortTile - 1) / kSortTile;
+    w.max_sort_tiles = (n + kSortTile - 1) / kSortTile;   // sort tiles per frame
     if (w.max_sort_tiles < 1) w.max_sort_tiles = 1;
     const int64_t K = (int64_t)F * n_tiles;
     w.status = reinterpret_cast<Status*>(take(sizeof(Status)));
@@ -114,8 +114,8 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nt
     w.cnt = reinterpret_cast<uint32_t*>(take(4 * M));
     for (int i = 0; i < 2; ++i) w.dkey[i] = reinterpret_cast<uint32_t*>(take(4 * M));
     for (int i = 0; i < 2; ++i) w.dval[i] = reinterpret_cast<uint32_t*>(take(4 * M));
-    w.counts = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets * w.max_sort_tiles));
-    w.totals = reinterpret_cast<uint32_t*>(take(4 * kSortBuckets));
+    w.counts = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * kSortBuckets * w.max_sort_tiles));
+    w.totals = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * kSortBuckets));
     const int64_t KG = (int64_t)F * g.ng;
     w.cntA = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * g.QC * g.ng));
     w.lenA = reinterpret_cast<uint32_t*>(take(4 * KG));

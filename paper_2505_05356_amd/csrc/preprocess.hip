@@ -218,181 +218,225 @@ __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g
 
 // ---------------------------------------------------------------------------
 // Backward: screen-space gradient records -> parameter gradients.
+//
+// FP32 throughout (the gradients carry no binning decision).  One thread per
+// (Gaussian, frame) item: the GS lanes of a group are the frames of one
+// Gaussian (frames f0, f0 + GS, ... when there are more than GS), and the
+// per-frame contributions are summed inside the group with DPP in a fixed
+// order, so the result is deterministic and needs no atomics.  The 2-D
+// covariance gradient comes from the stored conic Q (computed in binary64):
+// dL/dSigma' = -Q (dL/dQ) Q, with no determinant to lose precision in.
 // ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
+}
+
+// Sum over the GS consecutive lanes of a group (GS a power of two <= 64).
+template <int GS>
+__device__ __forceinline__ float group_sum(float v) {
+    if constexpr (GS >= 2) v += dpp_f<0xb1>(v);    // quad_perm [1,0,3,2]
+    if constexpr (GS >= 4) v += dpp_f<0x4e>(v);    // quad_perm [2,3,0,1]
+    if constexpr (GS >= 8) v += dpp_f<0x141>(v);   // row_half_mirror: the other quad of the 8
+    if constexpr (GS >= 16) v += dpp_f<0x140>(v);  // row_mirror: the other 8 of the row
+    if constexpr (GS >= 32) v += __shfl_xor(v, 16, 64);
+    if constexpr (GS >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+constexpr int kNG = 25;   // gradient values per Gaussian
+
+template <int GS>
 __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussians g,
                                                         const gftorf_frame* __restrict__ frames,
                                                         const uint32_t* __restrict__ cnt,
+                                                        const float4* __restrict__ rec,
                                                         const float* __restrict__ grec,
                                                         gftorf_gaussians_grad out) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= P.n) return;
-    const Gauss G = load_gauss(g, k);
-    const int GS = grad_floats(P.nf);
-    double gx0[3] = {0, 0, 0}, gv[3] = {0, 0, 0}, ga[3] = {0, 0, 0}, gs[3] = {0, 0, 0};
-    double gq0[4] = {0, 0, 0, 0}, gom[3] = {0, 0, 0}, grgb[3] = {0, 0, 0};
-    double glogit = 0, galb = 0;
-    const double o = 1.0 / (1.0 + exp(-G.logit));
-    const double L2E = 1.4426950408889634;
-
-    for (int f = 0; f < P.F; ++f) {
-        const int64_t item = (int64_t)f * P.n + k;
-        if (cnt[item] == 0) continue;
-        const gftorf_frame& fr = frames[f];
-        const float* gr = grec + item * GS;
-        const double gu = gr[0], gvv = gr[1];
-        const double gA = -0.5 * L2E * gr[2], gB = -L2E * gr[3], gC = -0.5 * L2E * gr[4];
-        const double go = gr[5];
-        const double gd_direct = gr[9];
-        const Binned b = bin(G, fr, P);
-        const double t = (double)fr.time;
-
-        // colour, opacity
-        for (int c = 0; c < 3; ++c) grgb[c] += gr[6 + c];
-        glogit += go * o * (1.0 - o);
-
-        // ---- range d: depth channel + C-ToF amplitude and phase -----------
-        double cc[3];
-        optical_centre(fr, cc);
-        const double e[3] = {b.m[0] - cc[0], b.m[1] - cc[1], b.m[2] - cc[2]};
-        const double d = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-        const double amp = (double)P.s_int * G.albedo / (d * d);
-        double gd = gd_direct;
-        for (int fi = 0; fi < P.nf; ++fi) {
-            double cyc = 2.0 * P.freq[fi] * d / kSpeedOfLight;
-            cyc -= floor(cyc);
-            double sn, cs;
-            sincos(2.0 * M_PI * cyc, &sn, &cs);
-            const double gas = gr[10 + 2 * fi], gac = gr[11 + 2 * fi];
-            const double dpsi = 4.0 * M_PI * P.freq[fi] / kSpeedOfLight;
-            // a sin psi, a cos psi with a = s r / d^2, psi = 4 pi f d / c
-            gd += gas * (-2.0 * amp / d * sn + amp * cs * dpsi) +
-                  gac * (-2.0 * amp / d * cs - amp * sn * dpsi);
-            galb += (gas * sn + gac * cs) * (double)P.s_int / (d * d);
-        }
-        double gm[3];
-        for (int c = 0; c < 3; ++c) gm[c] = gd * e[c] / d;
-
-        // ---- conic -> 2D covariance ---------------------------------------
-        const double a = b.S00, bb = b.S01, c2 = b.S11;
-        const double id2 = 1.0 / (b.det * b.det);
-        const double g_a = (gA * (-c2 * c2) + gB * (bb * c2) + gC * (-bb * bb)) * id2;
-        const double g_b = (gA * (2.0 * bb * c2) + gB * (-(a * c2 + bb * bb)) + gC * (2.0 * a * bb)) * id2;
-        const double g_c = (gA * (-bb * bb) + gB * (a * bb) + gC * (-a * a)) * id2;
-        const double Gp[2][2] = {{g_a, 0.5 * g_b}, {0.5 * g_b, g_c}};
-
-        // ---- rebuild T = J W and Sigma3 = Rq S^2 Rq^T ----------------------
-        const double px = b.p[0], py = b.p[1], pz = b.p[2];
-        const double fx = fr.fx, fy = fr.fy;
-        const double iz = 1.0 / pz, iz2 = iz * iz;
-        double Wc[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) Wc[i][j] = fr.R[3 * i + j];
-        const double J[2][3] = {{fx * iz, 0.0, -fx * px * iz2}, {0.0, fy * iz, -fy * py * iz2}};
-        double T[2][3];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 3; ++j)
-                T[i][j] = J[i][0] * Wc[0][j] + J[i][1] * Wc[1][j] + J[i][2] * Wc[2][j];
-        const double qw = b.q[0], qx = b.q[1], qy = b.q[2], qz = b.q[3];
-        const double nq = qw * qw + qx * qx + qy * qy + qz * qz;
-        double M[3][3] = {{qw * qw + qx * qx - qy * qy - qz * qz, 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
-                          {2 * (qx * qy + qw * qz), qw * qw - qx * qx + qy * qy - qz * qz, 2 * (qy * qz - qw * qx)},
-                          {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), qw * qw - qx * qx - qy * qy + qz * qz}};
-        double R[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) R[i][j] = M[i][j] / nq;
-        const double s2[3] = {G.s[0] * G.s[0], G.s[1] * G.s[1], G.s[2] * G.s[2]};
-        double Sig[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j)
-                Sig[i][j] = R[i][0] * s2[0] * R[j][0] + R[i][1] * s2[1] * R[j][1] + R[i][2] * s2[2] * R[j][2];
-
-        // dL/dSigma3 = T^T G' T ; dL/dT = 2 G' T Sigma3
-        double GT[2][3];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 3; ++j) GT[i][j] = Gp[i][0] * T[0][j] + Gp[i][1] * T[1][j];
-        double G3[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) G3[i][j] = T[0][i] * GT[0][j] + T[1][i] * GT[1][j];
-        double gT[2][3];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 3; ++j)
-                gT[i][j] = 2.0 * (GT[i][0] * Sig[0][j] + GT[i][1] * Sig[1][j] + GT[i][2] * Sig[2][j]);
-        // dL/dJ = dL/dT W^T
-        double gJ[2][3];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 3; ++j)
-                gJ[i][j] = gT[i][0] * Wc[j][0] + gT[i][1] * Wc[j][1] + gT[i][2] * Wc[j][2];
-        // camera-space position gradient: J and the pixel centre
-        double gp[3];
-        gp[0] = gJ[0][2] * (-fx * iz2) + gu * fx * iz;
-        gp[1] = gJ[1][2] * (-fy * iz2) + gvv * fy * iz;
-        gp[2] = gJ[0][0] * (-fx * iz2) + gJ[0][2] * (2.0 * fx * px * iz2 * iz) +
-                gJ[1][1] * (-fy * iz2) + gJ[1][2] * (2.0 * fy * py * iz2 * iz) -
-                gu * fx * px * iz2 - gvv * fy * py * iz2;
-        for (int c = 0; c < 3; ++c) gm[c] += Wc[0][c] * gp[0] + Wc[1][c] * gp[1] + Wc[2][c] * gp[2];
-
-        // ---- Sigma3 -> scale, rotation -------------------------------------
-        // dL/ds_k = 2 s_k (R^T G3 R)_kk ; dL/dR = 2 G3 R S^2
-        for (int kk = 0; kk < 3; ++kk) {
-            double acc = 0;
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) acc += R[i][kk] * G3[i][j] * R[j][kk];
-            gs[kk] += 2.0 * G.s[kk] * acc;
-        }
-        double gR[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j)
-                gR[i][j] = 2.0 * (G3[i][0] * R[0][j] + G3[i][1] * R[1][j] + G3[i][2] * R[2][j]) * s2[j];
-        // R = M / n
-        double gn = 0;
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) gn -= gR[i][j] * M[i][j];
-        gn /= nq * nq;
-        double gM[3][3];
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) gM[i][j] = gR[i][j] / nq;
-        double gq[4];
-        gq[0] = 2 * (qw * gM[0][0] - qz * gM[0][1] + qy * gM[0][2] + qz * gM[1][0] + qw * gM[1][1] -
-                     qx * gM[1][2] - qy * gM[2][0] + qx * gM[2][1] + qw * gM[2][2]) + 2 * qw * gn;
-        gq[1] = 2 * (qx * gM[0][0] + qy * gM[0][1] + qz * gM[0][2] + qy * gM[1][0] - qx * gM[1][1] -
-                     qw * gM[1][2] + qz * gM[2][0] + qw * gM[2][1] - qx * gM[2][2]) + 2 * qx * gn;
-        gq[2] = 2 * (-qy * gM[0][0] + qx * gM[0][1] + qw * gM[0][2] + qx * gM[1][0] + qy * gM[1][1] +
-                     qz * gM[1][2] - qw * gM[2][0] + qz * gM[2][1] - qy * gM[2][2]) + 2 * qy * gn;
-        gq[3] = 2 * (-qz * gM[0][0] - qw * gM[0][1] + qx * gM[0][2] + qw * gM[1][0] - qz * gM[1][1] +
-                     qy * gM[1][2] + qx * gM[2][0] + qy * gM[2][1] + qz * gM[2][2]) + 2 * qz * gn;
-
-        // q = q0 + (t/2) D(omega) q0 with D the left product by (0, omega)
-        const double ht = 0.5 * t;
-        const double ox = G.om[0], oy = G.om[1], oz = G.om[2];
-        const double w0 = G.q0[0], x0 = G.q0[1], y0 = G.q0[2], z0 = G.q0[3];
-        gq0[0] += gq[0] + ht * (gq[1] * ox + gq[2] * oy + gq[3] * oz);
-        gq0[1] += gq[1] + ht * (-gq[0] * ox + gq[2] * oz - gq[3] * oy);
-        gq0[2] += gq[2] + ht * (-gq[0] * oy - gq[1] * oz + gq[3] * ox);
-        gq0[3] += gq[3] + ht * (-gq[0] * oz + gq[1] * oy - gq[2] * ox);
-        gom[0] += ht * (-gq[0] * x0 + gq[1] * w0 - gq[2] * z0 + gq[3] * y0);
-        gom[1] += ht * (-gq[0] * y0 + gq[1] * z0 + gq[2] * w0 - gq[3] * x0);
-        gom[2] += ht * (-gq[0] * z0 - gq[1] * y0 + gq[2] * x0 + gq[3] * w0);
-
-        // ---- trajectory ----------------------------------------------------
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = tid / GS;
+    const int f0 = (int)(tid - k * GS);
+    const int64_t n = P.n;
+    const bool have = k < n;
+    // acc: mean 0-2, vel 3-5, acc 6-8, scale 9-11, quat 12-15, omega 16-18,
+    //      rgb 19-21, opacity logit 22, albedo 23 (24 unused)
+    float acc[kNG];
+#pragma unroll
+    for (int i = 0; i < kNG; ++i) acc[i] = 0.f;
+    if (have) {
+        auto ld = [&](const float* p, int64_t i) { return p ? p[i] : 0.0f; };
+        float x0[3], vv[3], aa[3], sc[3], q0[4], om[3];
         for (int c = 0; c < 3; ++c) {
-            gx0[c] += gm[c];
-            gv[c] += gm[c] * t;
-            ga[c] += gm[c] * 0.5 * t * t;
+            x0[c] = ld(g.mean, c * n + k);
+            vv[c] = ld(g.vel, c * n + k);
+            aa[c] = ld(g.acc, c * n + k);
+            sc[c] = ld(g.scale, c * n + k);
+            om[c] = ld(g.omega, c * n + k);
+        }
+        for (int c = 0; c < 4; ++c) q0[c] = ld(g.quat, c * n + k);
+        const float albedo = ld(g.albedo, k);
+        const int RS4 = record_float4s(P.nf);
+        const int GF = grad_floats(P.nf);
+        const float L2E = 1.4426950408889634f;
+        for (int f = f0; f < P.F; f += GS) {
+            const int64_t item = (int64_t)f * n + k;
+            if (cnt[item] == 0) continue;
+            const gftorf_frame& fr = frames[f];
+            const float* gr = grec + item * GF;
+            const float4 r1 = rec[item * RS4 + 1];
+            const float t = fr.time;
+
+            // trajectory and rotation at the frame time (as in the forward)
+            float m[3];
+            for (int c = 0; c < 3; ++c) m[c] = x0[c] + vv[c] * t + 0.5f * aa[c] * t * t;
+            const float ht = 0.5f * t;
+            const float qw = q0[0] - ht * (om[0] * q0[1] + om[1] * q0[2] + om[2] * q0[3]);
+            const float qx = q0[1] + ht * (q0[0] * om[0] + om[1] * q0[3] - om[2] * q0[2]);
+            const float qy = q0[2] + ht * (q0[0] * om[1] + om[2] * q0[1] - om[0] * q0[3]);
+            const float qz = q0[3] + ht * (q0[0] * om[2] + om[0] * q0[2] - om[1] * q0[1]);
+            float Wc[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) Wc[i][j] = fr.R[3 * i + j];
+            float p[3];
+            for (int i = 0; i < 3; ++i) p[i] = Wc[i][0] * m[0] + Wc[i][1] * m[1] + Wc[i][2] * m[2] + fr.t[i];
+
+            // colour, opacity (o from the record)
+            for (int c = 0; c < 3; ++c) acc[19 + c] += gr[6 + c];
+            acc[22] += gr[5] * r1.w * (1.0f - r1.w);
+
+            // range d: depth channel + C-ToF amplitude and phase
+            float e[3];
+            for (int i = 0; i < 3; ++i)
+                e[i] = m[i] + (Wc[0][i] * fr.t[0] + Wc[1][i] * fr.t[1] + Wc[2][i] * fr.t[2]);
+            const float d2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+            const float d = sqrtf(d2);
+            const float id = 1.0f / d;
+            const float amp = P.s_int * albedo / d2;
+            float gd = gr[9];
+            for (int fi = 0; fi < P.nf; ++fi) {
+                float cyc = (float)(2.0 * P.freq[fi] / kSpeedOfLight) * d;
+                cyc -= floorf(cyc);
+                const float sn = __builtin_amdgcn_sinf(cyc), cs = __builtin_amdgcn_cosf(cyc);   // of 2 pi cyc
+                const float gas = gr[10 + 2 * fi], gac = gr[11 + 2 * fi];
+                const float dpsi = (float)(4.0 * M_PI * P.freq[fi] / kSpeedOfLight);
+                // a sin psi, a cos psi with a = s r / d^2, psi = 4 pi f d / c
+                gd += gas * (-2.0f * amp * id * sn + amp * cs * dpsi) +
+                      gac * (-2.0f * amp * id * cs - amp * sn * dpsi);
+                acc[23] += (gas * sn + gac * cs) * P.s_int / d2;
+            }
+            float gm[3];
+            for (int c = 0; c < 3; ++c) gm[c] = gd * e[c] * id;
+
+            // conic gradient -> 2-D covariance gradient: -Q (dL/dQ) Q
+            const float A = r1.x * (-2.0f / L2E), B = r1.y * (-1.0f / L2E), C = r1.z * (-2.0f / L2E);
+            const float gA = -0.5f * L2E * gr[2], gB = -L2E * gr[3], gC = -0.5f * L2E * gr[4];
+            const float h00 = A * gA + B * (0.5f * gB), h01 = A * (0.5f * gB) + B * gC;
+            const float h10 = B * gA + C * (0.5f * gB), h11 = B * (0.5f * gB) + C * gC;
+            const float Gp[2][2] = {{-(h00 * A + h01 * B), -(h00 * B + h01 * C)},
+                                    {-(h00 * B + h01 * C), -(h10 * B + h11 * C)}};
+
+            // T = J W and Sigma3 = R S^2 R^T
+            const float px = p[0], py = p[1], pz = p[2];
+            const float fx = fr.fx, fy = fr.fy;
+            const float iz = 1.0f / pz, iz2 = iz * iz;
+            const float J[2][3] = {{fx * iz, 0.0f, -fx * px * iz2}, {0.0f, fy * iz, -fy * py * iz2}};
+            float T[2][3];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 3; ++j) T[i][j] = J[i][0] * Wc[0][j] + J[i][1] * Wc[1][j] + J[i][2] * Wc[2][j];
+            const float nq = qw * qw + qx * qx + qy * qy + qz * qz;
+            const float M[3][3] = {{qw * qw + qx * qx - qy * qy - qz * qz, 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
+                                   {2 * (qx * qy + qw * qz), qw * qw - qx * qx + qy * qy - qz * qz, 2 * (qy * qz - qw * qx)},
+                                   {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), qw * qw - qx * qx - qy * qy + qz * qz}};
+            const float inq = 1.0f / nq;
+            float R[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) R[i][j] = M[i][j] * inq;
+            const float s2[3] = {sc[0] * sc[0], sc[1] * sc[1], sc[2] * sc[2]};
+            float Sig[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    Sig[i][j] = R[i][0] * s2[0] * R[j][0] + R[i][1] * s2[1] * R[j][1] + R[i][2] * s2[2] * R[j][2];
+
+            // dL/dSigma3 = T^T G' T ; dL/dT = 2 G' T Sigma3 ; dL/dJ = dL/dT W^T
+            float GT[2][3];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 3; ++j) GT[i][j] = Gp[i][0] * T[0][j] + Gp[i][1] * T[1][j];
+            float G3[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) G3[i][j] = T[0][i] * GT[0][j] + T[1][i] * GT[1][j];
+            float gT[2][3];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 3; ++j)
+                    gT[i][j] = 2.0f * (GT[i][0] * Sig[0][j] + GT[i][1] * Sig[1][j] + GT[i][2] * Sig[2][j]);
+            float gJ[2][3];
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 3; ++j)
+                    gJ[i][j] = gT[i][0] * Wc[j][0] + gT[i][1] * Wc[j][1] + gT[i][2] * Wc[j][2];
+            // camera-space position: J and the pixel centre u = fx px / pz + cx
+            const float gu = gr[0], gv = gr[1];
+            float gp[3];
+            gp[0] = gJ[0][2] * (-fx * iz2) + gu * fx * iz;
+            gp[1] = gJ[1][2] * (-fy * iz2) + gv * fy * iz;
+            gp[2] = gJ[0][0] * (-fx * iz2) + gJ[0][2] * (2.0f * fx * px * iz2 * iz) + gJ[1][1] * (-fy * iz2) +
+                    gJ[1][2] * (2.0f * fy * py * iz2 * iz) - gu * fx * px * iz2 - gv * fy * py * iz2;
+            for (int c = 0; c < 3; ++c) gm[c] += Wc[0][c] * gp[0] + Wc[1][c] * gp[1] + Wc[2][c] * gp[2];
+
+            // Sigma3 -> scale: dL/ds_k = 2 s_k (R^T G3 R)_kk ; rotation: dL/dR = 2 G3 R S^2
+            for (int kk = 0; kk < 3; ++kk) {
+                float a3 = 0.f;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) a3 += R[i][kk] * G3[i][j] * R[j][kk];
+                acc[9 + kk] += 2.0f * sc[kk] * a3;
+            }
+            float gn = 0.f, gM[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    const float gR = 2.0f * (G3[i][0] * R[0][j] + G3[i][1] * R[1][j] + G3[i][2] * R[2][j]) * s2[j];
+                    gn -= gR * M[i][j];
+                    gM[i][j] = gR * inq;
+                }
+            gn *= inq * inq;   // R = M / n
+            float gq[4];
+            gq[0] = 2 * (qw * gM[0][0] - qz * gM[0][1] + qy * gM[0][2] + qz * gM[1][0] + qw * gM[1][1] -
+                         qx * gM[1][2] - qy * gM[2][0] + qx * gM[2][1] + qw * gM[2][2]) + 2 * qw * gn;
+            gq[1] = 2 * (qx * gM[0][0] + qy * gM[0][1] + qz * gM[0][2] + qy * gM[1][0] - qx * gM[1][1] -
+                         qw * gM[1][2] + qz * gM[2][0] + qw * gM[2][1] - qx * gM[2][2]) + 2 * qx * gn;
+            gq[2] = 2 * (-qy * gM[0][0] + qx * gM[0][1] + qw * gM[0][2] + qx * gM[1][0] + qy * gM[1][1] +
+                         qz * gM[1][2] - qw * gM[2][0] + qz * gM[2][1] - qy * gM[2][2]) + 2 * qy * gn;
+            gq[3] = 2 * (-qz * gM[0][0] - qw * gM[0][1] + qx * gM[0][2] + qw * gM[1][0] - qz * gM[1][1] +
+                         qy * gM[1][2] + qx * gM[2][0] + qy * gM[2][1] + qz * gM[2][2]) + 2 * qz * gn;
+            // q = q0 + (t/2) D(omega) q0 with D the left product by (0, omega)
+            acc[12] += gq[0] + ht * (gq[1] * om[0] + gq[2] * om[1] + gq[3] * om[2]);
+            acc[13] += gq[1] + ht * (-gq[0] * om[0] + gq[2] * om[2] - gq[3] * om[1]);
+            acc[14] += gq[2] + ht * (-gq[0] * om[1] - gq[1] * om[2] + gq[3] * om[0]);
+            acc[15] += gq[3] + ht * (-gq[0] * om[2] + gq[1] * om[1] - gq[2] * om[0]);
+            acc[16] += ht * (-gq[0] * q0[1] + gq[1] * q0[0] - gq[2] * q0[3] + gq[3] * q0[2]);
+            acc[17] += ht * (-gq[0] * q0[2] + gq[1] * q0[3] + gq[2] * q0[0] - gq[3] * q0[1]);
+            acc[18] += ht * (-gq[0] * q0[3] - gq[1] * q0[2] + gq[2] * q0[1] + gq[3] * q0[0]);
+
+            // trajectory
+            for (int c = 0; c < 3; ++c) {
+                acc[c] += gm[c];
+                acc[3 + c] += gm[c] * t;
+                acc[6 + c] += gm[c] * (0.5f * t * t);
+            }
         }
     }
-    const int64_t n = P.n;
+#pragma unroll
+    for (int i = 0; i < kNG - 1; ++i) acc[i] = group_sum<GS>(acc[i]);
+    if (!have || f0 != 0) return;
     for (int c = 0; c < 3; ++c) {
-        if (out.mean) out.mean[c * n + k] = (float)gx0[c];
-        if (out.vel) out.vel[c * n + k] = (float)gv[c];
-        if (out.acc) out.acc[c * n + k] = (float)ga[c];
-        if (out.scale) out.scale[c * n + k] = (float)gs[c];
-        if (out.omega) out.omega[c * n + k] = (float)gom[c];
-        if (out.rgb) out.rgb[c * n + k] = (float)grgb[c];
+        if (out.mean) out.mean[c * n + k] = acc[c];
+        if (out.vel) out.vel[c * n + k] = acc[3 + c];
+        if (out.acc) out.acc[c * n + k] = acc[6 + c];
+        if (out.scale) out.scale[c * n + k] = acc[9 + c];
+        if (out.omega) out.omega[c * n + k] = acc[16 + c];
+        if (out.rgb) out.rgb[c * n + k] = acc[19 + c];
     }
     for (int c = 0; c < 4; ++c)
-        if (out.quat) out.quat[c * n + k] = (float)gq0[c];
-    if (out.opacity_logit) out.opacity_logit[k] = (float)glogit;
-    if (out.albedo) out.albedo[k] = (float)galb;
+        if (out.quat) out.quat[c * n + k] = acc[12 + c];
+    if (out.opacity_logit) out.opacity_logit[k] = acc[22];
+    if (out.albedo) out.albedo[k] = acc[23];
 }
 
 }  // namespace
@@ -410,13 +454,26 @@ void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_
 
 void launch_preprocess_bwd(const Params& P, const gftorf_gaussians& g, const gftorf_frame* frames,
                            const Workspace& w, const gftorf_gaussians_grad& grad, hipStream_t s) {
+    // GS lanes per Gaussian: the smallest power of two >= frames, at most 64
+    int gs = 1;
+    while (gs < P.F && gs < 64) gs *= 2;
     const int threads = 256;
-    const unsigned blocks = (unsigned)((P.n + threads - 1) / threads);
+    const unsigned blocks = (unsigned)((P.n * gs + threads - 1) / threads);
     if (blocks == 0) return;
-    { ProfScope _p("k_preprocess_bwd", s);
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.cnt,
-                       w.grec, grad);
+    ProfScope _p("k_preprocess_bwd", s);
+#define GFT_PRE_BWD(G)                                                                                    \
+    hipLaunchKernelGGL(k_preprocess_bwd<G>, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.cnt, w.rec, \
+                       w.grec, grad)
+    switch (gs) {
+        case 1: GFT_PRE_BWD(1); break;
+        case 2: GFT_PRE_BWD(2); break;
+        case 4: GFT_PRE_BWD(4); break;
+        case 8: GFT_PRE_BWD(8); break;
+        case 16: GFT_PRE_BWD(16); break;
+        case 32: GFT_PRE_BWD(32); break;
+        default: GFT_PRE_BWD(64); break;
     }
+#undef GFT_PRE_BWD
 }
 
 }  // namespace gft

@@ -3,17 +3,16 @@
 // Every pixel composites the Gaussians of its tile front to back (paper §3),
 // in ascending (depth key, Gaussian index) order per frame.  The M = F * N
 // items start in (frame, index) order; a stable LSD radix sort over their
-// 32-bit depth keys (4 passes of 8 bits) followed by one pass on the frame
-// index (8 bits of frame per pass, the digit taken from the item id) leaves
-// them frame-major and depth-ordered inside each frame, ties in index order.
-// The tile lists are then built from this order by the binning kernels
-// (bin.hip) without sorting any (tile, Gaussian) pairs.
+// 32-bit depth keys (4 passes of 8 bits), run segment by segment (one segment
+// per frame), leaves them frame-major and depth-ordered inside each frame,
+// ties in index order.  The tile lists are then built from this order by the
+// binning kernels (bin.hip) without sorting any (tile, Gaussian) pairs.
 //
-// Radix passes are reduce-then-scan (upsweep tile histograms, per-digit
-// column scan, downsweep rank-and-scatter) with no inter-workgroup waiting.
-// Ranking inside a 4096-key tile is stable: wave-level peer matching with
-// ballots, wave-private digit counters in LDS, then an LDS reorder so that
-// each digit run is written contiguously.
+// Radix passes are reduce-then-scan (upsweep tile histograms, per-(frame,
+// digit) column scan, downsweep rank-and-scatter) with no inter-workgroup
+// waiting.  Sort tiles never straddle a frame.  Ranking inside a tile is
+// stable: wave-level peer matching with ballots, wave-private digit counters
+// in LDS, then an LDS reorder so that each digit run is written contiguously.
 #include "block_scan.h"
 #include "common.h"
 
@@ -21,58 +20,58 @@ namespace gft {
 
 namespace {
 
-// Digit of an element: bits [shift, shift + nbits) of the key, or, when
-// vdiv != 0, of the frame index value / vdiv.
-__device__ __forceinline__ uint32_t digit_of(uint32_t k, uint32_t v, int shift, uint32_t mask,
-                                             uint32_t vdiv) {
-    const uint32_t src = vdiv ? v / vdiv : k;
-    return (src >> shift) & mask;
+// Sort tile `g` of the segmented layout: frame and element range.
+struct SortTile {
+    long long f, t, beg, end;
+};
+
+__device__ __forceinline__ SortTile sort_tile(long long g, long long n, long long tpf) {
+    SortTile r;
+    r.f = g / tpf;
+    r.t = g - r.f * tpf;
+    r.beg = r.f * n + r.t * kSortTile;
+    r.end = min(r.beg + kSortTile, (r.f + 1) * n);
+    return r;
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_sort_upsweep(const uint32_t* __restrict__ keys,
-                                                               const uint32_t* __restrict__ vals,
-                                                               long long n, int shift, int nbits,
-                                                               uint32_t vdiv,
-                                                               uint32_t* __restrict__ counts,
-                                                               long long stride) {
+// counts[(f * 256 + d) * tpf + t] = keys of digit d in tile t of frame f.
+__global__ void __launch_bounds__(kSortThreads) k_sort_upsweep(const uint32_t* __restrict__ keys, long long n,
+                                                               int F, long long tpf, int shift,
+                                                               uint32_t* __restrict__ counts) {
     __shared__ uint32_t hist[4][kSortBuckets];
-    const long long ntiles = (n + kSortTile - 1) / kSortTile;
-    const uint32_t mask = (1u << nbits) - 1u;
+    const long long ntiles = (long long)F * tpf;
     const int wave = threadIdx.x / 64;
-    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (long long g = blockIdx.x; g < ntiles; g += gridDim.x) {
+        const SortTile st = sort_tile(g, n, tpf);
         for (int i = threadIdx.x; i < 4 * kSortBuckets; i += kSortThreads) (&hist[0][0])[i] = 0;
         __syncthreads();
-        const long long base = tile * kSortTile;
 #pragma unroll 4
         for (int it = 0; it < kSortItems; ++it) {
-            const long long idx = base + it * kSortThreads + threadIdx.x;
-            if (idx < n) {
-                const uint32_t d = vdiv ? digit_of(0u, vals[idx], shift, mask, vdiv)
-                                        : digit_of(keys[idx], 0u, shift, mask, 0u);
-                atomicAdd(&hist[wave][d], 1u);
-            }
+            const long long idx = st.beg + it * kSortThreads + threadIdx.x;
+            if (idx < st.end) atomicAdd(&hist[wave][(keys[idx] >> shift) & 0xffu], 1u);
         }
         __syncthreads();
         const int d = threadIdx.x;
-        counts[(long long)d * stride + tile] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
+        counts[(st.f * kSortBuckets + d) * tpf + st.t] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
         __syncthreads();
     }
 }
 
-// One workgroup per digit: exclusive scan of that digit's per-tile counts.
-__global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ counts, long long n,
-                                                   long long stride, uint32_t* __restrict__ totals) {
+// One workgroup per (digit, frame): exclusive scan of that row of per-tile
+// counts; the row total goes to totals[f * 256 + d].
+__global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ counts, long long tpf,
+                                                   uint32_t* __restrict__ totals) {
     __shared__ uint32_t scratch[8];
-    const long long ntiles = (n + kSortTile - 1) / kSortTile;
-    uint32_t* row = counts + (long long)blockIdx.x * stride;
+    const long long rowi = (long long)blockIdx.y * kSortBuckets + blockIdx.x;
+    uint32_t* row = counts + rowi * tpf;
     uint32_t carry = 0;
-    for (long long base = 0; base < ntiles; base += 256 * 4) {
+    for (long long base = 0; base < tpf; base += 256 * 4) {
         uint32_t v[4];
         uint32_t s = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const long long i = base + threadIdx.x * 4 + j;
-            v[j] = i < ntiles ? row[i] : 0u;
+            v[j] = i < tpf ? row[i] : 0u;
             s += v[j];
         }
         uint32_t tot;
@@ -81,18 +80,18 @@ __global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ counts
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const long long i = base + threadIdx.x * 4 + j;
-            if (i < ntiles) row[i] = run;
+            if (i < tpf) row[i] = run;
             run += v[j];
         }
         carry += tot;
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+    if (threadIdx.x == 0) totals[rowi] = carry;
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, long long n, int shift, int nbits, uint32_t vdiv,
-    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, long long stride) {
+    uint32_t* __restrict__ vout, long long n, int F, long long tpf, int shift,
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals) {
     __shared__ uint32_t digit_base[kSortBuckets];
     __shared__ uint32_t whist[4][kSortBuckets];
     __shared__ uint32_t tile_start[kSortBuckets];
@@ -100,41 +99,40 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
     __shared__ uint32_t sval[kSortTile];
     __shared__ uint32_t scratch[8];
 
-    const long long ntiles = (n + kSortTile - 1) / kSortTile;
-    const uint32_t mask = (1u << nbits) - 1u;
-    const int nb = 1 << nbits;
+    const long long ntiles = (long long)F * tpf;
     const int tid = threadIdx.x;
     const int wave = tid / 64;
     const int lane = tid % 64;
+    long long cur_f = -1;
 
-    {   // exclusive scan of the digit totals -> global base of each digit
-        uint32_t tot;
-        uint32_t v = tid < nb ? totals[tid] : 0u;
-        uint32_t ex = block_exclusive_scan<uint32_t, kSortThreads>(v, scratch, &tot);
-        digit_base[tid] = ex;
-    }
-    __syncthreads();
-
-    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const long long base = tile * kSortTile;
+    for (long long g = blockIdx.x; g < ntiles; g += gridDim.x) {
+        const SortTile st = sort_tile(g, n, tpf);
+        if (st.f != cur_f) {   // start of each digit inside this frame's segment
+            __syncthreads();
+            uint32_t tot;
+            const uint32_t ex = block_exclusive_scan<uint32_t, kSortThreads>(
+                totals[st.f * kSortBuckets + tid], scratch, &tot);
+            digit_base[tid] = ex;
+            cur_f = st.f;
+        }
         for (int i = lane; i < kSortBuckets; i += 64) whist[wave][i] = 0;
         uint32_t k[kSortItems], v[kSortItems], rank[kSortItems];
-        const long long wbase = base + (long long)wave * (kSortItems * 64);
+        const long long wbase = st.beg + (long long)wave * (kSortItems * 64);
 #pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
             const long long idx = wbase + it * 64 + lane;
-            const bool ok = idx < n;
+            const bool ok = idx < st.end;
             k[it] = ok ? kin[idx] : 0u;
             v[it] = ok ? vin[idx] : 0u;
-            // digit, with bit `nbits` flagging an out-of-range lane
-            rank[it] = ok ? digit_of(k[it], v[it], shift, mask, vdiv) : (1u << nbits);
+            // digit, with bit 8 flagging an out-of-range lane
+            rank[it] = ok ? ((k[it] >> shift) & 0xffu) : 0x100u;
         }
-        __syncthreads();  // whist cleared
+        __syncthreads();  // whist cleared, digit_base written
 #pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
             const uint32_t d = rank[it];
             unsigned long long peers = ~0ull;
-            for (int b = 0; b <= nbits; ++b) {
+            for (int b = 0; b <= 8; ++b) {
                 const bool bit = (d >> b) & 1u;
                 const unsigned long long bal = __ballot(bit);
                 peers &= bit ? bal : ~bal;
@@ -148,7 +146,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
             // keep the compiler from reordering them across iterations.
             volatile uint32_t* wh = whist[wave];
             uint32_t prev = 0;
-            const bool valid = d < (uint32_t)nb;
+            const bool valid = d < (uint32_t)kSortBuckets;
             if (valid) prev = wh[d];
             if (valid && below == cnt - 1) wh[d] = prev + cnt;
             rank[it] = valid ? prev + below : 0xffffffffu;
@@ -170,23 +168,23 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
 #pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
             if (rank[it] != 0xffffffffu) {
-                const uint32_t d = digit_of(k[it], v[it], shift, mask, vdiv);
+                const uint32_t d = (k[it] >> shift) & 0xffu;
                 const uint32_t pos = tile_start[d] + whist[wave][d] + rank[it];
                 skey[pos] = k[it];
                 sval[pos] = v[it];
             }
         }
         __syncthreads();
-        const long long rem = n - base;
-        const int valid_n = rem < (long long)kSortTile ? (int)rem : kSortTile;
+        const int valid_n = (int)(st.end - st.beg);
+        const long long fbase = st.f * n;
         for (int j = tid; j < valid_n; j += kSortThreads) {
             const uint32_t key = skey[j];
             const uint32_t val = sval[j];
-            const uint32_t d = digit_of(key, val, shift, mask, vdiv);
-            const unsigned long long g = (unsigned long long)digit_base[d] +
-                                         counts[(long long)d * stride + tile] + (j - tile_start[d]);
-            kout[g] = key;
-            vout[g] = val;
+            const uint32_t d = (key >> shift) & 0xffu;
+            const long long gpos = fbase + (long long)digit_base[d] +
+                                   counts[(st.f * kSortBuckets + d) * tpf + st.t] + (j - tile_start[d]);
+            kout[gpos] = key;
+            vout[gpos] = val;
         }
         __syncthreads();
     }
@@ -211,25 +209,25 @@ unsigned grid_for(long long items, long long per_block, unsigned cap_blocks) {
     return (unsigned)b;
 }
 
-// One stable LSD pass over n elements; ping-pong is managed by the caller.
-void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                long long n, int shift, int nbits, uint32_t vdiv, const Workspace& w, hipStream_t s) {
-    const long long stride = w.max_sort_tiles;
-    const unsigned g = grid_for(n, kSortTile, 2048);
+// One stable LSD pass over the F segments of n elements; ping-pong is
+// managed by the caller.
+void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, long long n,
+                int F, int shift, const Workspace& w, hipStream_t s) {
+    const long long tpf = w.max_sort_tiles;
+    const unsigned g = grid_for((long long)F * tpf, 1, 4096);
     {
         ProfScope _p("k_sort_upsweep", s);
-        hipLaunchKernelGGL(k_sort_upsweep, dim3(g), dim3(kSortThreads), 0, s, kin, vin, n, shift, nbits,
-                           vdiv, w.counts, stride);
+        hipLaunchKernelGGL(k_sort_upsweep, dim3(g), dim3(kSortThreads), 0, s, kin, n, F, tpf, shift,
+                           w.counts);
     }
     {
         ProfScope _p("k_sort_scan", s);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1u << nbits), dim3(256), 0, s, w.counts, n, stride,
-                           w.totals);
+        hipLaunchKernelGGL(k_sort_scan, dim3(kSortBuckets, F), dim3(256), 0, s, w.counts, tpf, w.totals);
     }
     {
         ProfScope _p("k_sort_downsweep", s);
-        hipLaunchKernelGGL(k_sort_downsweep, dim3(g), dim3(kSortThreads), 0, s, kin, vin, kout, vout,
-                           n, shift, nbits, vdiv, w.counts, w.totals, stride);
+        hipLaunchKernelGGL(k_sort_downsweep, dim3(g), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n, F,
+                           tpf, shift, w.counts, w.totals);
     }
 }
 
@@ -249,27 +247,14 @@ void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
                        (long long)n);
 }
 
-int depth_sort_passes(int n_frames) {
-    int frame_bits = 0;
-    while ((1 << frame_bits) < n_frames) ++frame_bits;
-    return 4 + (frame_bits + 7) / 8;
-}
+int depth_sort_passes(int) { return 4; }
 
 // Frame-major depth sort of the M items; returns the buffer holding the result.
 int launch_depth_sort(const Params& P, const Workspace& w, hipStream_t s) {
-    const long long M = w.M;
     int cur = 0;
-    if (M == 0) return 0;
-    for (int pass = 0; pass < 4; ++pass) {
-        radix_pass(w.dkey[cur], w.dval[cur], w.dkey[cur ^ 1], w.dval[cur ^ 1], M, 8 * pass, 8, 0u, w, s);
-        cur ^= 1;
-    }
-    int frame_bits = 0;
-    while ((1 << frame_bits) < P.F) ++frame_bits;
-    for (int shift = 0; shift < frame_bits; shift += 8) {
-        const int nb = frame_bits - shift < 8 ? frame_bits - shift : 8;
-        radix_pass(w.dkey[cur], w.dval[cur], w.dkey[cur ^ 1], w.dval[cur ^ 1], M, shift, nb,
-                   (uint32_t)P.n, w, s);
+    if (w.M == 0) return 0;
+    for (int pass = 0; pass < depth_sort_passes(P.F); ++pass) {
+        radix_pass(w.dkey[cur], w.dval[cur], w.dkey[cur ^ 1], w.dval[cur ^ 1], P.n, P.F, 8 * pass, w, s);
         cur ^= 1;
     }
     return cur;
