@@ -50,9 +50,8 @@ __device__ __forceinline__ Groups groups_of(const Params& P) {
 // ---- level A: items -> groups ----------------------------------------------
 
 __global__ void __launch_bounds__(256) k_group_count(Params P, int C, int QC,
-                                                     const uint32_t* __restrict__ dval,
-                                                     const uint32_t* __restrict__ cnt,
-                                                     const uint2* __restrict__ rect,
+                                                     const uint32_t* __restrict__ dkey,
+                                                     const uint2* __restrict__ drect,
                                                      uint32_t* __restrict__ cntA) {
     __shared__ uint32_t lcnt[kMaxGroupsPerFrame];
     const Groups G = groups_of(P);
@@ -63,10 +62,9 @@ __global__ void __launch_bounds__(256) k_group_count(Params P, int C, int QC,
     const long long beg = (long long)f * P.n + (long long)q * C;
     const long long end = min(beg + C, (long long)(f + 1) * P.n);
     for (long long j = beg + threadIdx.x; j < end; j += 256) {
-        const uint32_t item = dval[j];
-        if (cnt[item] == 0) continue;
+        if (dkey[j] == kCulledKey) continue;
         uint32_t xlo, xhi, ylo, yhi;
-        unpack_rect(rect[item], xlo, xhi, ylo, yhi);
+        unpack_rect(drect[j], xlo, xhi, ylo, yhi);
         for (uint32_t gy = ylo / kGroupH; gy <= yhi / kGroupH; ++gy)
             for (uint32_t gx = xlo / kGroupW; gx <= xhi / kGroupW; ++gx)
                 atomicAdd(&lcnt[gy * G.ngx + gx], 1u);
@@ -151,11 +149,12 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t peers) {
 // list is kept.  The leaders (lowest lane per group) then advance the cursors.
 __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
                                                     const uint32_t* __restrict__ dval,
-                                                    const uint32_t* __restrict__ cnt,
-                                                    const uint2* __restrict__ rect,
+                                                    const uint32_t* __restrict__ dkey,
+                                                    const uint2* __restrict__ drect,
                                                     const uint32_t* __restrict__ cntA,
                                                     const uint2* __restrict__ granges,
-                                                    uint32_t* __restrict__ gval) {
+                                                    uint32_t* __restrict__ gval,
+                                                    uint16_t* __restrict__ gloc) {
     extern __shared__ uint64_t dyn_[];
     const Groups G = groups_of(P);
     uint64_t* x_lo = dyn_;             // [ngx] lanes whose first group column <= v
@@ -174,17 +173,14 @@ __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
     const int nv = max(G.ngx, G.ngy);
     for (long long j0 = beg; j0 < end; j0 += 64) {
         int gx0 = 1, gx1 = 0, gy0 = 1, gy1 = 0;   // empty: never in a ballot
-        uint32_t item = 0;
-        if (j0 + lane < end) {
+        uint32_t item = 0, xlo = 0, xhi = 0, ylo = 0, yhi = 0;
+        if (j0 + lane < end && dkey[j0 + lane] != kCulledKey) {
             item = dval[j0 + lane];
-            if (cnt[item] != 0) {
-                uint32_t xlo, xhi, ylo, yhi;
-                unpack_rect(rect[item], xlo, xhi, ylo, yhi);
-                gx0 = (int)(xlo / kGroupW);
-                gx1 = (int)(xhi / kGroupW);
-                gy0 = (int)(ylo / kGroupH);
-                gy1 = (int)(yhi / kGroupH);
-            }
+            unpack_rect(drect[j0 + lane], xlo, xhi, ylo, yhi);
+            gx0 = (int)(xlo / kGroupW);
+            gx1 = (int)(xhi / kGroupW);
+            gy0 = (int)(ylo / kGroupH);
+            gy1 = (int)(yhi / kGroupH);
         }
         __syncthreads();   // the previous round's table and cursor reads are done
         for (int v = 0; v < nv; ++v) {
@@ -203,7 +199,14 @@ __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
             for (int k = 0; k < area; ++k) {
                 const uint64_t peers = x_lo[gx] & x_hi[gx] & y_lo[gy] & y_hi[gy];
                 const uint32_t pos = cursor[gy * G.ngx + gx] + rank_below(peers);
-                if (pos < cap) gval[pos] = item;
+                if (pos < cap) {
+                    // the rectangle clipped to this group's 8x8 tiles
+                    const uint32_t ox = (uint32_t)gx * kGroupW, oy = (uint32_t)gy * kGroupH;
+                    const uint32_t x0 = max(xlo, ox) - ox, x1 = min(xhi, ox + kGroupW - 1) - ox;
+                    const uint32_t y0 = max(ylo, oy) - oy, y1 = min(yhi, oy + kGroupH - 1) - oy;
+                    gval[pos] = item;
+                    gloc[pos] = (uint16_t)(x0 | (x1 << 3) | (y0 << 6) | (y1 << 9));
+                }
                 if (++gx > gx1) { gx = gx0; ++gy; }
             }
         }
@@ -264,19 +267,17 @@ __device__ __forceinline__ LaneTile lane_tile(const Params& P, const Groups& G, 
 }
 
 // An entry's tile rectangle clipped to the 8x8 tiles of its group, in group
-// coordinates (the entry is in the group's list, so the clip is not empty).
+// coordinates, as stored by the level-A placement (3 bits per bound).
 struct LocalRect {
     uint32_t x0, x1, y0, y1;
 };
 
-__device__ __forceinline__ LocalRect local_rect(uint2 rc, uint32_t ox, uint32_t oy) {
-    uint32_t xlo, xhi, ylo, yhi;
-    unpack_rect(rc, xlo, xhi, ylo, yhi);
+__device__ __forceinline__ LocalRect local_rect(uint32_t packed) {
     LocalRect r;
-    r.x0 = max(xlo, ox) - ox;
-    r.x1 = min(xhi, ox + kGroupW - 1) - ox;
-    r.y0 = max(ylo, oy) - oy;
-    r.y1 = min(yhi, oy + kGroupH - 1) - oy;
+    r.x0 = packed & 7u;
+    r.x1 = (packed >> 3) & 7u;
+    r.y0 = (packed >> 6) & 7u;
+    r.y1 = (packed >> 9) & 7u;
     return r;
 }
 
@@ -293,8 +294,7 @@ __device__ __forceinline__ uint64_t cover_mask(const LocalRect& r) {
 // in LDS; a 2-D prefix sum across the lanes turns it into per-tile counts.
 __global__ void __launch_bounds__(64) k_tile_count(Params P, int S, const uint32_t* __restrict__ seg_start,
                                                    const uint2* __restrict__ granges,
-                                                   const uint32_t* __restrict__ gval,
-                                                   const uint2* __restrict__ rect,
+                                                   const uint16_t* __restrict__ gloc,
                                                    uint32_t* __restrict__ cntB) {
     __shared__ int diff[64];
     const Groups G = groups_of(P);
@@ -303,12 +303,10 @@ __global__ void __launch_bounds__(64) k_tile_count(Params P, int S, const uint32
     const int lane = threadIdx.x;
     for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
         const Segment sg = find_segment((int)b, seg_start, K, S, granges);
-        const LaneTile lt = lane_tile(P, G, sg.fg, lane);
-        const uint32_t ox = lt.tx - lane % kGroupW, oy = lt.ty - lane / kGroupW;
         diff[lane] = 0;
         __syncthreads();
         for (uint32_t j = sg.beg + lane; j < sg.end; j += 64) {
-            const LocalRect r = local_rect(rect[gval[j]], ox, oy);
+            const LocalRect r = local_rect(gloc[j]);
             const bool xin = r.x1 + 1 < (uint32_t)kGroupW, yin = r.y1 + 1 < (uint32_t)kGroupH;
             atomicAdd(&diff[r.y0 * kGroupW + r.x0], 1);
             if (xin) atomicAdd(&diff[r.y0 * kGroupW + r.x1 + 1], -1);
@@ -338,7 +336,7 @@ __global__ void __launch_bounds__(64) k_tile_count(Params P, int S, const uint32
 __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32_t* __restrict__ seg_start,
                                                    const uint2* __restrict__ granges,
                                                    const uint32_t* __restrict__ gval,
-                                                   const uint2* __restrict__ rect,
+                                                   const uint16_t* __restrict__ gloc,
                                                    const uint32_t* __restrict__ cntB,
                                                    const uint2* __restrict__ ranges,
                                                    uint32_t* __restrict__ tval) {
@@ -350,7 +348,6 @@ __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32
     for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
         const Segment sg = find_segment((int)b, seg_start, K, S, granges);
         const LaneTile lt = lane_tile(P, G, sg.fg, lane);
-        const uint32_t ox = lt.tx - lane % kGroupW, oy = lt.ty - lane / kGroupW;
         uint32_t cur = 0;   // next list position of this lane's tile
         if (lt.mine) cur = ranges[(size_t)lt.f * P.n_tiles + lt.tile].x + cntB[(size_t)b * 64 + lane];
         for (uint32_t j0 = sg.beg; j0 < sg.end; j0 += 64) {
@@ -359,7 +356,7 @@ __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32
             uint64_t mask = 0;
             if (j < sg.end) {
                 item = gval[j];
-                mask = cover_mask(local_rect(rect[item], ox, oy));
+                mask = cover_mask(local_rect(gloc[j]));
             }
             // tiles covered by any lane
             uint32_t lo = (uint32_t)mask, hi = (uint32_t)(mask >> 32);
@@ -432,6 +429,14 @@ __global__ void __launch_bounds__(1024) k_tile_keyscan(const uint32_t* __restric
     }
 }
 
+// Introspection: the sorted rectangles back in item order.
+__global__ void k_item_rects(const uint32_t* __restrict__ dval, const uint2* __restrict__ drect, long long M,
+                             uint2* __restrict__ out) {
+    for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < M;
+         j += (long long)gridDim.x * blockDim.x)
+        out[dval[j]] = drect[j];
+}
+
 // Introspection: expands the ranges into per-pair (frame, tile) keys.
 __global__ void k_keys_from_ranges(const uint2* __restrict__ ranges, long long K,
                                    unsigned long long limit, uint32_t* __restrict__ keys) {
@@ -469,8 +474,8 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     const unsigned chunks = (unsigned)(P.F * g.QC);
     if (chunks) {
         ProfScope _p("k_group_count", s);
-        hipLaunchKernelGGL(k_group_count, dim3(chunks), dim3(256), 0, s, P, g.C, g.QC, w.dval[dbuf],
-                           w.cnt, w.rect, w.cntA);
+        hipLaunchKernelGGL(k_group_count, dim3(chunks), dim3(256), 0, s, P, g.C, g.QC, w.dkey[dbuf],
+                           w.drect[dbuf], w.cntA);
     }
     if (chunks) {
         ProfScope _p("k_group_colscan", s);
@@ -489,14 +494,14 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
         const int ngx = (P.ntx + kGroupW - 1) / kGroupW, ngy = (P.nty + kGroupH - 1) / kGroupH;
         const size_t lds = 16 * (size_t)(ngx + ngy) + 4 * (size_t)g.ng;
         hipLaunchKernelGGL(k_group_place, dim3(chunks), dim3(64), lds, s, P, g.C, g.QC, w.dval[dbuf],
-                           w.cnt, w.rect, w.cntA, w.granges, w.gval);
+                           w.dkey[dbuf], w.drect[dbuf], w.cntA, w.granges, w.gval, w.gloc);
     }
     // persistent level-B grid: every wave loops over segments
     const unsigned segs = (unsigned)(g.max_segments < 16384 ? g.max_segments : 16384);
     {
         ProfScope _p("k_tile_count", s);
         hipLaunchKernelGGL(k_tile_count, dim3(segs), dim3(64), 0, s, P, g.S, w.seg_start, w.granges,
-                           w.gval, w.rect, w.cntB);
+                           w.gloc, w.cntB);
     }
     {
         ProfScope _p("k_tile_colscan", s);
@@ -510,9 +515,16 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     {
         ProfScope _p("k_tile_place", s);
         hipLaunchKernelGGL(k_tile_place, dim3(segs), dim3(64), 0, s, P, g.S, w.seg_start, w.granges,
-                           w.gval, w.rect, w.cntB, w.ranges, w.tval);
+                           w.gval, w.gloc, w.cntB, w.ranges, w.tval);
     }
     return hipGetLastError();
+}
+
+void launch_item_rects(const Workspace& w, int dbuf, uint2* out, hipStream_t s) {
+    if (w.M == 0) return;
+    const long long blocks = (w.M + 255) / 256;
+    hipLaunchKernelGGL(k_item_rects, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s,
+                       w.dval[dbuf], w.drect[dbuf], (long long)w.M, out);
 }
 
 void launch_keys_from_ranges(const Params& P, const Workspace& w, uint32_t* keys,

@@ -295,7 +295,10 @@ int gftorf_copy_lists(const void* ws, int64_t n, int32_t n_frames, const gftorf_
     cp(depth_key, w.dkey[db], 4 * (size_t)w.M);
     cp(depth_item, w.dval[db], 4 * (size_t)w.M);
     cp(item_count, w.cnt, 4 * (size_t)w.M);
-    cp(item_rect, w.rect, 8 * (size_t)w.M);
+    if (item_rect && e == hipSuccess) {
+        gft::launch_item_rects(w, db, reinterpret_cast<uint2*>(item_rect), s);
+        e = hipGetLastError();
+    }
     cp(tile_ranges, w.ranges, 8 * (size_t)P.F * P.n_tiles);
     if (e != hipSuccess) return hip_fail(e, "gftorf_copy_lists");
     return GFTORF_OK;

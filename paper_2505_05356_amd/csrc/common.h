@@ -12,6 +12,7 @@ constexpr double kSpeedOfLight = 299792458.0;   // m/s
 constexpr float kLog2e = 1.4426950408889634f;
 
 // Radix sort geometry: 256 threads (4 wave64), 16 keys per thread.
+constexpr uint32_t kCulledKey = 0xffffffffu;   // depth key of a culled item
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per tile
@@ -69,10 +70,10 @@ struct Params {
 struct Workspace {
     Status* status;
     float4* rec;            // [M][record_float4s]
-    uint2* rect;            // [M] packed (x_lo | x_hi << 16, y_lo | y_hi << 16)
     uint32_t* cnt;          // [M] tiles covered
     uint32_t* dkey[2];      // [M] depth keys (double buffer)
     uint32_t* dval[2];      // [M] item ids
+    uint2* drect[2];        // [M] tile rectangles (x_lo | x_hi << 16, y_lo | y_hi << 16), sort payload
     uint32_t* counts;       // [F][256][max_sort_tiles] per-tile digit counts of the depth sort
     uint32_t* totals;       // [F][256] digit totals per frame
     uint32_t* cntA;         // [F][QC][ng] per-chunk group counts, then column prefixes
@@ -80,6 +81,7 @@ struct Workspace {
     uint2* granges;         // [F * ng] group-list ranges in gval
     uint32_t* seg_start;    // [F * ng + 1] first level-B segment of each group
     uint32_t* gval;         // [cap] item ids of the group lists
+    uint16_t* gloc;         // [cap] their rectangles clipped to the group, 3 bits per bound
     uint32_t* cntB;         // [max_segments][64] per-segment tile counts, then prefixes
     uint32_t* tcount;       // [F * n_tiles] pairs per (frame, tile)
     uint2* ranges;          // [F * n_tiles] [start, end) of each tile list in tval
@@ -110,10 +112,10 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nt
     const int64_t K = (int64_t)F * n_tiles;
     w.status = reinterpret_cast<Status*>(take(sizeof(Status)));
     w.rec = reinterpret_cast<float4*>(take(sizeof(float4) * record_float4s(nf) * M));
-    w.rect = reinterpret_cast<uint2*>(take(sizeof(uint2) * M));
     w.cnt = reinterpret_cast<uint32_t*>(take(4 * M));
     for (int i = 0; i < 2; ++i) w.dkey[i] = reinterpret_cast<uint32_t*>(take(4 * M));
     for (int i = 0; i < 2; ++i) w.dval[i] = reinterpret_cast<uint32_t*>(take(4 * M));
+    for (int i = 0; i < 2; ++i) w.drect[i] = reinterpret_cast<uint2*>(take(sizeof(uint2) * M));
     w.counts = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * kSortBuckets * w.max_sort_tiles));
     w.totals = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * kSortBuckets));
     const int64_t KG = (int64_t)F * g.ng;
@@ -122,6 +124,7 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nt
     w.granges = reinterpret_cast<uint2*>(take(sizeof(uint2) * KG));
     w.seg_start = reinterpret_cast<uint32_t*>(take(4 * (KG + 1)));
     w.gval = reinterpret_cast<uint32_t*>(take(4 * cap));
+    w.gloc = reinterpret_cast<uint16_t*>(take(2 * cap));
     w.cntB = reinterpret_cast<uint32_t*>(take(4 * 64 * (size_t)g.max_segments));
     w.tcount = reinterpret_cast<uint32_t*>(take(4 * K));
     w.ranges = reinterpret_cast<uint2*>(take(sizeof(uint2) * K));
@@ -160,6 +163,7 @@ void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_
 int depth_sort_passes(int n_frames);
 int launch_depth_sort(const Params& P, const Workspace& w, hipStream_t s);
 hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStream_t s);
+void launch_item_rects(const Workspace& w, int dbuf, uint2* out, hipStream_t s);
 void launch_keys_from_ranges(const Params& P, const Workspace& w, uint32_t* keys,
                              unsigned long long limit, hipStream_t s);
 hipError_t launch_composite_fwd(const Params& P, const gftorf_frame* frames, const Workspace& w,

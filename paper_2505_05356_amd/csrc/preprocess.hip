@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g
         cnt[item] = c;
         rect[item] = make_uint2((uint32_t)b.xlo | ((uint32_t)(b.xhi & 0xffff) << 16),
                                 (uint32_t)b.ylo | ((uint32_t)(b.yhi & 0xffff) << 16));
-        dkey[item] = b.valid ? __float_as_uint((float)b.p[2]) : 0xffffffffu;
+        dkey[item] = b.valid ? __float_as_uint((float)b.p[2]) : kCulledKey;
         dval[item] = (uint32_t)item;
         if (!b.valid) continue;
 
@@ -447,7 +447,7 @@ void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_
     const unsigned blocks = (unsigned)((P.n + threads - 1) / threads);
     if (blocks == 0) return;
     { ProfScope _p("k_preprocess", s);
-    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec, w.rect,
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec, w.drect[0],
                        w.cnt, w.dkey[0], w.dval[0], w.status);
     }
 }

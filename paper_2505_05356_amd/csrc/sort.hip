@@ -10,7 +10,9 @@
 //
 // Radix passes are reduce-then-scan (upsweep tile histograms, per-(frame,
 // digit) column scan, downsweep rank-and-scatter) with no inter-workgroup
-// waiting.  Sort tiles never straddle a frame.  Ranking inside a tile is
+// waiting.  Sort tiles never straddle a frame.  Each item's tile rectangle
+// rides along as payload, so the binning kernels read it in depth order
+// without gathering it by item id.  Ranking inside a tile is
 // stable: wave-level peer matching with ballots, wave-private digit counters
 // in LDS, then an LDS reorder so that each digit run is written contiguously.
 #include "block_scan.h"
@@ -89,14 +91,16 @@ __global__ void __launch_bounds__(256) k_sort_scan(uint32_t* __restrict__ counts
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, long long n, int F, long long tpf, int shift,
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, const uint2* __restrict__ rin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, uint2* __restrict__ rout, long long n, int F,
+    long long tpf, int shift,
     const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals) {
     __shared__ uint32_t digit_base[kSortBuckets];
     __shared__ uint32_t whist[4][kSortBuckets];
     __shared__ uint32_t tile_start[kSortBuckets];
     __shared__ uint32_t skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
+    __shared__ uint2 srect[kSortTile];
     __shared__ uint32_t scratch[8];
 
     const long long ntiles = (long long)F * tpf;
@@ -117,6 +121,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
         }
         for (int i = lane; i < kSortBuckets; i += 64) whist[wave][i] = 0;
         uint32_t k[kSortItems], v[kSortItems], rank[kSortItems];
+        uint2 rc[kSortItems];
         const long long wbase = st.beg + (long long)wave * (kSortItems * 64);
 #pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
@@ -124,6 +129,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
             const bool ok = idx < st.end;
             k[it] = ok ? kin[idx] : 0u;
             v[it] = ok ? vin[idx] : 0u;
+            rc[it] = ok ? rin[idx] : make_uint2(0u, 0u);
             // digit, with bit 8 flagging an out-of-range lane
             rank[it] = ok ? ((k[it] >> shift) & 0xffu) : 0x100u;
         }
@@ -172,6 +178,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
                 const uint32_t pos = tile_start[d] + whist[wave][d] + rank[it];
                 skey[pos] = k[it];
                 sval[pos] = v[it];
+                srect[pos] = rc[it];
             }
         }
         __syncthreads();
@@ -185,6 +192,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
                                    counts[(st.f * kSortBuckets + d) * tpf + st.t] + (j - tile_start[d]);
             kout[gpos] = key;
             vout[gpos] = val;
+            rout[gpos] = srect[j];
         }
         __syncthreads();
     }
@@ -211,8 +219,8 @@ unsigned grid_for(long long items, long long per_block, unsigned cap_blocks) {
 
 // One stable LSD pass over the F segments of n elements; ping-pong is
 // managed by the caller.
-void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, long long n,
-                int F, int shift, const Workspace& w, hipStream_t s) {
+void radix_pass(const uint32_t* kin, const uint32_t* vin, const uint2* rin, uint32_t* kout, uint32_t* vout,
+                uint2* rout, long long n, int F, int shift, const Workspace& w, hipStream_t s) {
     const long long tpf = w.max_sort_tiles;
     const unsigned g = grid_for((long long)F * tpf, 1, 4096);
     {
@@ -226,8 +234,8 @@ void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32
     }
     {
         ProfScope _p("k_sort_downsweep", s);
-        hipLaunchKernelGGL(k_sort_downsweep, dim3(g), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n, F,
-                           tpf, shift, w.counts, w.totals);
+        hipLaunchKernelGGL(k_sort_downsweep, dim3(g), dim3(kSortThreads), 0, s, kin, vin, rin, kout, vout, rout,
+                           n, F, tpf, shift, w.counts, w.totals);
     }
 }
 
@@ -254,7 +262,8 @@ int launch_depth_sort(const Params& P, const Workspace& w, hipStream_t s) {
     int cur = 0;
     if (w.M == 0) return 0;
     for (int pass = 0; pass < depth_sort_passes(P.F); ++pass) {
-        radix_pass(w.dkey[cur], w.dval[cur], w.dkey[cur ^ 1], w.dval[cur ^ 1], P.n, P.F, 8 * pass, w, s);
+        radix_pass(w.dkey[cur], w.dval[cur], w.drect[cur], w.dkey[cur ^ 1], w.dval[cur ^ 1], w.drect[cur ^ 1],
+                   P.n, P.F, 8 * pass, w, s);
         cur ^= 1;
     }
     return cur;
