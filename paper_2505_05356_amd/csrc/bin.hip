@@ -328,6 +328,26 @@ __global__ void __launch_bounds__(64) k_tile_count(Params P, int S, const uint32
     }
 }
 
+// Tiles t0 .. t0 + 31 of the group for one batch of 64 entries: `bits` holds
+// this lane's coverage of those tiles, lane t of `cur` the cursor of tile t.
+__device__ __forceinline__ void place_half(uint64_t tiles, int t0, uint32_t bits, uint32_t item, uint32_t& cur,
+                                           uint32_t cap, uint32_t* __restrict__ tval) {
+    uint32_t todo = (uint32_t)(tiles >> t0);
+    while (todo) {
+        const int i = __builtin_ctz(todo);
+        todo &= todo - 1;
+        const uint64_t peers = __ballot((bits >> i) & 1u);
+        if (peers == 0ull) continue;
+        const int t = t0 + i;
+        const uint32_t base = __builtin_amdgcn_readlane(cur, t);
+        if ((peers >> __lane_id()) & 1ull) {
+            const uint32_t pos = base + rank_below(peers);
+            if (pos < cap) tval[pos] = item;
+        }
+        if ((int)__lane_id() == t) cur = base + (uint32_t)__popcll(peers);
+    }
+}
+
 // Placing pass, 64 entries at a time (lane = entry).  For every tile of the
 // group that some entry covers, a ballot gives the covering lanes; each
 // writes at the tile's cursor plus its rank among them, so one store
@@ -350,34 +370,26 @@ __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32
         const LaneTile lt = lane_tile(P, G, sg.fg, lane);
         uint32_t cur = 0;   // next list position of this lane's tile
         if (lt.mine) cur = ranges[(size_t)lt.f * P.n_tiles + lt.tile].x + cntB[(size_t)b * 64 + lane];
+        // tiles of this group inside the frame (wave-uniform)
+        const uint64_t tiles = __ballot(lt.mine);
+        // the next batch's entries are loaded while this batch is placed
+        uint32_t nitem = 0, nloc = 0;
+        bool nvalid = sg.beg + lane < sg.end;
+        if (nvalid) {
+            nitem = gval[sg.beg + lane];
+            nloc = gloc[sg.beg + lane];
+        }
         for (uint32_t j0 = sg.beg; j0 < sg.end; j0 += 64) {
-            const uint32_t j = j0 + lane;
-            uint32_t item = 0;
-            uint64_t mask = 0;
-            if (j < sg.end) {
-                item = gval[j];
-                mask = cover_mask(local_rect(gloc[j]));
+            const uint32_t item = nitem;
+            const uint64_t mask = nvalid ? cover_mask(local_rect(nloc)) : 0ull;
+            const uint32_t jn = j0 + 64 + lane;
+            nvalid = jn < sg.end;
+            if (nvalid) {
+                nitem = gval[jn];
+                nloc = gloc[jn];
             }
-            // tiles covered by any lane
-            uint32_t lo = (uint32_t)mask, hi = (uint32_t)(mask >> 32);
-            for (int d = 32; d > 0; d >>= 1) {
-                lo |= (uint32_t)__shfl_xor((int)lo, d, 64);
-                hi |= (uint32_t)__shfl_xor((int)hi, d, 64);
-            }
-            uint64_t todo = ((uint64_t)__builtin_amdgcn_readfirstlane(hi) << 32) |
-                            (uint64_t)__builtin_amdgcn_readfirstlane(lo);
-            while (todo) {
-                const int t = __builtin_ctzll(todo);
-                todo &= todo - 1;
-                const bool c = (mask >> t) & 1ull;
-                const uint64_t peers = __ballot(c);
-                const uint32_t base = __builtin_amdgcn_readlane(cur, t);
-                if (c) {
-                    const uint32_t pos = base + rank_below(peers);
-                    if (pos < cap) tval[pos] = item;
-                }
-                if (lane == t) cur += (uint32_t)__popcll(peers);
-            }
+            place_half(tiles, 0, (uint32_t)mask, item, cur, cap, tval);
+            place_half(tiles, 32, (uint32_t)(mask >> 32), item, cur, cap, tval);
         }
     }
 }
@@ -394,7 +406,20 @@ __global__ void __launch_bounds__(64) k_tile_colscan(Params P, const uint32_t* _
     const uint32_t gy = gi / G.ngx, gx = gi - gy * G.ngx;
     const uint32_t tx = gx * kGroupW + lane % kGroupW, ty = gy * kGroupH + lane / kGroupW;
     uint32_t run = 0;
-    for (uint32_t b = seg_start[fg]; b < seg_start[fg + 1]; ++b) {
+    const uint32_t b1 = seg_start[fg + 1];
+    uint32_t b = seg_start[fg];
+    // 8 segments per step: independent loads in flight together
+    for (; b + 8 <= b1; b += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = cntB[(size_t)(b + i) * 64 + lane];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            cntB[(size_t)(b + i) * 64 + lane] = run;
+            run += v[i];
+        }
+    }
+    for (; b < b1; ++b) {
         const uint32_t v = cntB[(size_t)b * 64 + lane];
         cntB[(size_t)b * 64 + lane] = run;
         run += v;
@@ -458,8 +483,9 @@ BinGeom bin_geometry(int64_t n, int32_t n_frames, int ntx, int nty, uint64_t cap
     g.C = C;
     g.QC = n > 0 ? (int)((n + C - 1) / C) : 0;
     g.ng = ((ntx + kGroupW - 1) / kGroupW) * ((nty + kGroupH - 1) / kGroupH);
-    // level-B segment: long runs per lane for large batches, more waves for small ones
-    g.S = M >= (1 << 20) ? 512 : 128;
+    // level-B segment: 128 entries (two batches of 64) -- short segments give
+    // enough waves to hide the load latency of the placing pass
+    g.S = 128;
     // every segment but the last of each group list holds S entries, and the
     // group lists hold at most min(cap, M * groups) entries
     uint64_t entries = cap;
