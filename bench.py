@@ -43,6 +43,16 @@ FWD_FLOP_PER_COMP = 16
 BWD_FLOP_PER_COMP = 87
 SORT_BYTES_PER_KEY_PASS = 16  # read key + value, write key + value (4 B each)
 
+# HBM traffic per launch of the composite kernels from rocprofv3 counter runs
+# of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled
+# by what the same counter reads for a plain device copy of known size
+# (--calibration-copy-mib).  A figure holds only for the kernel source it was
+# measured on: the sha256 of the listed files must match, else traffic is null.
+FETCH_SCALE, WRITE_SCALE = 1048576 / 524322, 1048576 / 1048576   # 1 GiB copy: FETCH 524322 KiB, WRITE 1048576 KiB
+TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
+TRAFFIC_SHA256 = "8015e44aa9b5bc58660269fe8d95593ec57e36a50a2422a54ae5a253f6b42ccd"
+TRAFFIC_KIB = {"k_composite_bwd": (52027, 51901), "k_composite_fwd": (6745, 96089)}   # KiB per launch
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -56,7 +66,25 @@ def parse():
                     help="seconds of oracle tile work in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="after timing, one device-to-device copy of this many MiB (for counter runs)")
     return ap.parse_args()
+
+
+def traffic_bytes(name):
+    """Counter-measured HBM bytes per launch of `name`, or None when there is
+    no measurement for the kernel source as it is now."""
+    import hashlib
+    if name not in TRAFFIC_KIB or TRAFFIC_SHA256 is None or FETCH_SCALE is None:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_FILES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC_SHA256:
+        return None
+    fetch, write = TRAFFIC_KIB[name]
+    return int(round((fetch * FETCH_SCALE + write * WRITE_SCALE) * 1024))
 
 
 def main():
@@ -171,9 +199,17 @@ def main():
     work = dict(P=P, E_fwd=st["n_evaluated"], C=st["n_composited"],
                 E_bwd=int(out["n_contrib"].sum().item()))   # backward walks up to n_contrib
     roof = roofline(dominant, kern[dominant]["avg_ms"], **work)
+    roof["traffic"] = traffic_bytes(dominant)
     print("# kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f}ms x{v['launches'] // args.steps}"
                                     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["total_ms"])),
           file=sys.stderr, flush=True)
+
+    if args.calibration_copy_mib > 0:   # a plain copy of known size for counter scaling
+        src = torch.ones(args.calibration_copy_mib * 262144, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:
