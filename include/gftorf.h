@@ -80,7 +80,21 @@ typedef struct gftorf_gaussians_grad {
 } gftorf_gaussians_grad;
 
 /* One rendered frame; an ARRAY of these lives in DEVICE memory, so a graph
- * replay can change times, poses and backgrounds between launches. */
+ * replay can change times, poses and backgrounds between launches.
+ *
+ * Asynchronous raw quartets (paper §4, Eq. 7): a camera captures the raw
+ * quads of one quartet at different times.  A frame with t_hi > t_lo places
+ * every Gaussian centre on the straight line between its trajectory
+ * positions at the two integer timesteps t_lo and t_hi:
+ *   x = ((t_hi - time) x(t_lo) + (time - t_lo) x(t_hi)) / (t_hi - t_lo),
+ * which for t_hi - t_lo = 1 is Eq. 7 literally.  The rotation is evaluated
+ * at `time` (the unnormalised quaternion is affine in time, so the same
+ * interpolation leaves it unchanged).  With t_hi <= t_lo the trajectory is
+ * evaluated at `time` directly.
+ * quad_mask selects the quad channels (bit freq * n_phase + phase) the frame
+ * renders: the forward writes only those channels of `quad`, the backward
+ * reads only those channels of d_quad (the others count as zero) and gives
+ * zero background gradient to the others.  0 means every channel. */
 typedef struct gftorf_frame {
     float R[9];                       /* world -> camera rotation, row-major      */
     float t[3];                       /* world -> camera translation              */
@@ -88,6 +102,9 @@ typedef struct gftorf_frame {
     float time;                       /* s, evaluates the Gaussian trajectories   */
     float bg_rgb[3];                  /* c_bg (Eq. 2)                             */
     float bg_quad[GFTORF_MAX_QUAD];   /* q_bg [n_freq][n_phase] (Eq. 4)           */
+    float t_lo, t_hi;                 /* s, Eq. 7 interpolation anchors           */
+    uint32_t quad_mask;               /* rendered quad channels, 0 = all          */
+    uint32_t reserved;                /* must be 0                                */
 } gftorf_frame;
 
 /* Per-call constants (host memory).  The paper states neither the rasterizer

@@ -16,6 +16,13 @@ builds on (§3, "GS image formation model"; §4 "Implementation details"):
   x(t) = x0 + v t + a t^2 / 2 and q(t) = q0 + (t/2) (0, omega) (x) q0, the
   first-order constant-rate quaternion step; q(t) is not renormalised because
   the rotation is formed as M(q) / |q|^2, which is exact for any q != 0.
+* asynchronous raw quads (§4, Eq. 7): a frame with anchors t_lo < t_hi takes
+  the centre on the line between its positions at the two integer timesteps,
+  x = w1 x(t_lo) + w2 x(t_hi), w1 = (t_hi - t) / (t_hi - t_lo),
+  w2 = (t - t_lo) / (t_hi - t_lo) (for unit spacing these are Eq. 7's
+  weights i2 - j and j - i1).  The deformation of the paper offsets positions
+  only; here the quaternion stays evaluated at t, which is the same thing as
+  interpolating it, because q(t) is affine in t.
 * camera space p = R x + t; culled unless p_z > near.
 * EWA projection: Sigma' = J R Rq S^2 Rq^T R^T J^T + dilation I, with the
   pinhole Jacobian J at p.
@@ -56,9 +63,21 @@ def project(g, frame, cfg):
         vx, vy, vz = _d(g.vel)
         ax, ay, az = _d(g.acc)
         tt = t * t
-        mx = (x0x + vx * t) + (0.5 * ax) * tt
-        my = (x0y + vy * t) + (0.5 * ay) * tt
-        mz = (x0z + vz * t) + (0.5 * az) * tt
+        tlo, thi = _d(getattr(frame, "t_lo", 0.0)), _d(getattr(frame, "t_hi", 0.0))
+        if thi > tlo:
+            # Eq. 7 between the anchors, one IEEE operation per statement
+            span = thi - tlo
+            w1 = (thi - t) / span
+            w2 = (t - tlo) / span
+            tl2 = tlo * tlo
+            th2 = thi * thi
+            mx = w1 * ((x0x + vx * tlo) + (0.5 * ax) * tl2) + w2 * ((x0x + vx * thi) + (0.5 * ax) * th2)
+            my = w1 * ((x0y + vy * tlo) + (0.5 * ay) * tl2) + w2 * ((x0y + vy * thi) + (0.5 * ay) * th2)
+            mz = w1 * ((x0z + vz * tlo) + (0.5 * az) * tl2) + w2 * ((x0z + vz * thi) + (0.5 * az) * th2)
+        else:
+            mx = (x0x + vx * t) + (0.5 * ax) * tt
+            my = (x0y + vy * t) + (0.5 * ay) * tt
+            mz = (x0z + vz * t) + (0.5 * az) * tt
 
         w0, qx0, qy0, qz0 = _d(g.quat)
         ox, oy, oz = _d(g.omega)

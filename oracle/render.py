@@ -86,7 +86,14 @@ def gaussian_quantities(p, frame, cfg):
     (s r / d^2), psi [n_freq, N], rgb [3, N].
     """
     t = _s(frame.time)
-    mu = p["mean"] + p["vel"] * t + 0.5 * p["acc"] * (t * t)            # [3,N]
+    tlo, thi = _s(getattr(frame, "t_lo", 0.0)), _s(getattr(frame, "t_hi", 0.0))
+    if thi > tlo:
+        # Eq. 7: straight line between the positions at the two anchors
+        w1, w2 = (thi - t) / (thi - tlo), (t - tlo) / (thi - tlo)
+        mu = (w1 * (p["mean"] + p["vel"] * tlo + 0.5 * p["acc"] * (tlo * tlo))
+              + w2 * (p["mean"] + p["vel"] * thi + 0.5 * p["acc"] * (thi * thi)))
+    else:
+        mu = p["mean"] + p["vel"] * t + 0.5 * p["acc"] * (t * t)        # [3,N]
     q0 = p["quat"]
     om = p["omega"]
     # (0, omega) (x) q0 = (-omega . v0, w0 omega + omega x v0)

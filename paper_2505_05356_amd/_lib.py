@@ -20,7 +20,7 @@ OPTIONAL = ("vel", "acc", "omega")
 MAX_FREQ = 4
 MAX_PHASE = 4
 MAX_QUAD = 16
-FRAME_FLOATS = 9 + 3 + 4 + 1 + 3 + MAX_QUAD   # 36
+FRAME_FLOATS = 9 + 3 + 4 + 1 + 3 + MAX_QUAD + 4   # 40: ... t_lo, t_hi, quad_mask, reserved
 
 OK, EINVAL, ENOWS, EHIP, EOVERFLOW = 0, -1, -2, -3, -4
 

@@ -248,7 +248,8 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
         for (int i = 0; i < NF; ++i)
             for (int jj = 0; jj < P.nphi; ++jj) {
                 const int qc = i * P.nphi + jj;
-                o[qc * HW] = P.cphi[jj] * S[i] + P.sphi[jj] * C[i] + fr.bg_quad[qc] * Tp;
+                if (fr.quad_mask == 0u || ((fr.quad_mask >> qc) & 1u))
+                    o[qc * HW] = P.cphi[jj] * S[i] + P.sphi[jj] * C[i] + fr.bg_quad[qc] * Tp;
             }
     }
     if (out.phasor || out.d_tof || out.amplitude) {
@@ -359,6 +360,7 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
                 for (int k = 0; k < NF; ++k)
                     for (int jj = 0; jj < P.nphi; ++jj) {
                         const int qc = k * P.nphi + jj;
+                        if (fr.quad_mask != 0u && !((fr.quad_mask >> qc) & 1u)) continue;   // not rendered
                         const float g = d_quad[((size_t)f * P.nq + qc) * HW + pix];
                         gS[i][k] += P.cphi[jj] * g;
                         gC[i][k] += P.sphi[jj] * g;

@@ -69,7 +69,20 @@ __device__ Binned bin(const Gauss& G, const gftorf_frame& fr, const Params& P) {
     Binned b;
     const double t = (double)fr.time;
     const double tt = t * t;
-    for (int c = 0; c < 3; ++c) b.m[c] = (G.x0[c] + G.v[c] * t) + (0.5 * G.a[c]) * tt;
+    if (fr.t_hi > fr.t_lo) {
+        // Eq. 7: the straight line between the positions at the two anchors
+        const double tl = (double)fr.t_lo, th = (double)fr.t_hi;
+        const double span = th - tl;
+        const double w1 = (th - t) / span, w2 = (t - tl) / span;
+        const double tl2 = tl * tl, th2 = th * th;
+        for (int c = 0; c < 3; ++c) {
+            const double ml = (G.x0[c] + G.v[c] * tl) + (0.5 * G.a[c]) * tl2;
+            const double mh = (G.x0[c] + G.v[c] * th) + (0.5 * G.a[c]) * th2;
+            b.m[c] = w1 * ml + w2 * mh;
+        }
+    } else {
+        for (int c = 0; c < 3; ++c) b.m[c] = (G.x0[c] + G.v[c] * t) + (0.5 * G.a[c]) * tt;
+    }
 
     const double w0 = G.q0[0], qx0 = G.q0[1], qy0 = G.q0[2], qz0 = G.q0[3];
     const double ox = G.om[0], oy = G.om[1], oz = G.om[2];
@@ -286,9 +299,19 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
             const float4 r1 = rec[item * RS4 + 1];
             const float t = fr.time;
 
-            // trajectory and rotation at the frame time (as in the forward)
+            // trajectory and rotation at the frame time (as in the forward): the
+            // centre is cx0 x0 + cv v + ca a, with Eq. 7's weights when the
+            // frame interpolates between two anchors
+            float cx0 = 1.0f, cv = t, ca = 0.5f * t * t;
+            if (fr.t_hi > fr.t_lo) {
+                const float span = fr.t_hi - fr.t_lo;
+                const float w1 = (fr.t_hi - t) / span, w2 = (t - fr.t_lo) / span;
+                cx0 = w1 + w2;
+                cv = w1 * fr.t_lo + w2 * fr.t_hi;
+                ca = 0.5f * (w1 * fr.t_lo * fr.t_lo + w2 * fr.t_hi * fr.t_hi);
+            }
             float m[3];
-            for (int c = 0; c < 3; ++c) m[c] = x0[c] + vv[c] * t + 0.5f * aa[c] * t * t;
+            for (int c = 0; c < 3; ++c) m[c] = cx0 * x0[c] + cv * vv[c] + ca * aa[c];
             const float ht = 0.5f * t;
             const float qw = q0[0] - ht * (om[0] * q0[1] + om[1] * q0[2] + om[2] * q0[3]);
             const float qx = q0[1] + ht * (q0[0] * om[0] + om[1] * q0[3] - om[2] * q0[2]);
@@ -416,9 +439,9 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
 
             // trajectory
             for (int c = 0; c < 3; ++c) {
-                acc[c] += gm[c];
-                acc[3 + c] += gm[c] * t;
-                acc[6 + c] += gm[c] * (0.5f * t * t);
+                acc[c] += gm[c] * cx0;
+                acc[3 + c] += gm[c] * cv;
+                acc[6 + c] += gm[c] * ca;
             }
         }
     }

@@ -68,7 +68,7 @@ def n_quad(cfg) -> int:
 
 
 def pack_frames(frames, cfg, device="cuda") -> torch.Tensor:
-    """Frame descriptors -> float32 device tensor [F, 36] (struct gftorf_frame)."""
+    """Frame descriptors -> float32 device tensor [F, 40] (struct gftorf_frame)."""
     if isinstance(frames, torch.Tensor):
         return frames
     F = len(frames)
@@ -82,6 +82,9 @@ def pack_frames(frames, cfg, device="cuda") -> torch.Tensor:
         a[i, 17:20] = np.asarray(fr.bg_rgb, np.float32).reshape(3)
         if fr.bg_quad is not None:
             a[i, 20:20 + nq] = np.asarray(fr.bg_quad, np.float32).reshape(-1)[:nq]
+        a[i, 36] = getattr(fr, "t_lo", 0.0)
+        a[i, 37] = getattr(fr, "t_hi", 0.0)
+        a[i, 38:39].view(np.uint32)[0] = np.uint32(getattr(fr, "quad_mask", 0))
     return torch.from_numpy(a).to(device)
 
 

@@ -79,6 +79,11 @@ class Frame:
     time: float = 0.0
     bg_rgb: np.ndarray = field(default_factory=lambda: np.zeros(3, dtype=np.float32))
     bg_quad: Optional[np.ndarray] = None  # [n_freq, n_phase] float32, None = 0
+    # asynchronous raw quads: with t_hi > t_lo the Gaussian centres lie on the
+    # line between their positions at t_lo and t_hi (paper Eq. 7)
+    t_lo: float = 0.0
+    t_hi: float = 0.0
+    quad_mask: int = 0                    # rendered quad channels (bits), 0 = all
 
 
 @dataclass
@@ -296,6 +301,23 @@ def tiny_scene(n: int, width: int, height: int, seed: int, f: float = None,
     cfg = RenderConfig(width=width, height=height, freqs=(30e6,), tile_w=8, tile_h=8)
     return Workload(f"tiny-{n}-{width}x{height}", g,
                     identity_frames([0.0], width, height, f, f, 4), cfg)
+
+
+def async_quartet_frames(n_quartets: int, period: float, base: Frame, n_phase: int = 4,
+                         n_freq: int = 1) -> List[Frame]:
+    """Raw quads captured one at a time (paper §2, §4): raw frame k of quartet
+    i = k // n_phase, offset j = k % n_phase, is taken at time
+    (i + j / n_phase) * period and renders only its offset's channels (at
+    every frequency); its Gaussian centres are interpolated between the
+    integer timesteps i * period and (i + 1) * period (Eq. 7)."""
+    frames = []
+    for k in range(n_quartets * n_phase):
+        i, j = divmod(k, n_phase)
+        mask = sum(1 << (f * n_phase + j) for f in range(n_freq))
+        frames.append(dataclasses.replace(
+            base, time=float(np.float32((i + j / n_phase) * period)),
+            t_lo=float(np.float32(i * period)), t_hi=float(np.float32((i + 1) * period)), quad_mask=mask))
+    return frames
 
 
 def frames_for_times(times, wl: Workload) -> List[Frame]:

@@ -46,7 +46,7 @@ def test_struct_sizes_match_header(lib):
     from paper_2505_05356_amd import _lib
     assert ctypes.sizeof(_lib.ConfigC) == 112
     assert ctypes.sizeof(_lib.GaussiansC) == 8 * 10
-    assert _lib.FRAME_FLOATS * 4 == 144
+    assert _lib.FRAME_FLOATS * 4 == 160
 
 
 def _cfg(**kw):

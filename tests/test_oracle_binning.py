@@ -72,6 +72,51 @@ def test_trajectory_closed_form():
     assert p["pz"][0] == pytest.approx(z, rel=1e-15)
 
 
+def test_eq7_unit_spacing_is_the_literal_formula():
+    # Eq. 7 with integer timesteps i1, i2 = i1 + 1 and a fractional j between:
+    # x_j = (i2 - j) x_i1 + (j - i1) x_i2, with x from the trajectory closed form.
+    x0, v, a = (0.1, -0.2, 2.0), (0.5, 0.25, -1.0), (2.0, -3.0, 4.0)
+    g = _single(x0, (0.01, 0.01, 0.01), vel=v, acc=a)
+    cfg = scenes.RenderConfig(width=64, height=48)
+    f32 = lambda z: float(np.float32(z))
+    i1, j = 3.0, 3.25
+    fr = scenes.Frame(time=j, t_lo=i1, t_hi=i1 + 1.0)
+    p = binning.project(g, fr, cfg)
+    traj = lambda t: np.array([f32(x0[c]) + f32(v[c]) * t + 0.5 * f32(a[c]) * t * t for c in range(3)])
+    xj = (i1 + 1.0 - j) * traj(i1) + (j - i1) * traj(i1 + 1.0)
+    np.testing.assert_allclose([p["px"][0], p["py"][0], p["pz"][0]], xj, rtol=1e-14)
+    # ... which differs from the trajectory at j itself (the acceleration term)
+    assert abs(p["pz"][0] - traj(j)[2]) > 0.1
+
+
+def test_eq7_at_an_anchor_and_without_acceleration():
+    wl = scenes.cfg3(n=500, n_frames=1, seed=4)
+    g, cfg = wl.gaussians, wl.cfg
+    base = wl.frames[0]
+    # at t = t_lo the weights are exactly (1, 0): bit-identical to direct evaluation
+    a = binning.project(g, dataclasses.replace(base, time=0.2, t_lo=0.2, t_hi=0.3), cfg)
+    b = binning.project(g, dataclasses.replace(base, time=0.2), cfg)
+    for k in ("px", "py", "pz", "u", "v", "key", "count"):
+        np.testing.assert_array_equal(a[k], b[k])
+    np.testing.assert_array_equal(a["rect"], b["rect"])
+    # without acceleration the trajectory is affine: interpolation = evaluation
+    g0 = dataclasses.replace(g, acc=np.zeros_like(g.acc))
+    a = binning.project(g0, dataclasses.replace(base, time=0.23, t_lo=0.2, t_hi=0.3), cfg)
+    b = binning.project(g0, dataclasses.replace(base, time=0.23), cfg)
+    np.testing.assert_allclose(a["pz"], b["pz"], rtol=1e-14)
+    np.testing.assert_allclose(a["u"][a["valid"]], b["u"][a["valid"]], rtol=1e-12)
+
+
+def test_eq7_differentiable_form_matches():
+    wl = scenes.cfg3(n=800, n_frames=1, seed=6)
+    for fr in scenes.async_quartet_frames(1, 0.1, wl.frames[0]):
+        p = binning.project(wl.gaussians, fr, wl.cfg)
+        q = render.gaussian_quantities(render.params_to_torch(wl.gaussians), fr, wl.cfg)
+        v = p["valid"]
+        np.testing.assert_allclose(p["u"][v], q["u"].numpy()[v], rtol=1e-10)
+        np.testing.assert_allclose(p["v"][v], q["v"].numpy()[v], rtol=1e-10)
+
+
 def test_culling():
     g = _single((0, 0, 0.1), (0.01, 0.01, 0.01))           # behind the near plane
     cfg = scenes.RenderConfig(width=64, height=48)
