@@ -63,6 +63,17 @@ typedef struct gftorf_gaussians {
     const float* opacity_logit; /* [n]   o = sigmoid(logit)                        */
     const float* rgb;           /* [3][n] colour c_k (Eq. 2)                       */
     const float* albedo;        /* [n]   reflectivity r_k (Eq. 3/4)                */
+    /* View-dependent colour and reflectivity (paper §3): real spherical
+     * harmonics of degree sh_degree (0..3, K = (sh_degree + 1)^2
+     * coefficients) at the unit direction from the optical centre to the
+     * Gaussian centre, basis order (l, m) = (0,0), (1,-1), (1,0), (1,1), ...,
+     * Condon-Shortley phase.  c = max(0, 1/2 + sum_i Y_i k_i) per channel,
+     * r = max(0, 1/2 + sum_i Y_i k_i).  A non-NULL array replaces rgb or
+     * albedo (which may then be NULL); their gradient outputs are then zero. */
+    int32_t sh_degree;          /* 0..3; read only when an sh array is set       */
+    int32_t reserved;           /* must be 0                                       */
+    const float* sh_rgb;        /* [K][3][n] colour coefficients, or NULL          */
+    const float* sh_albedo;     /* [K][n] reflectivity coefficients, or NULL       */
 } gftorf_gaussians;
 
 /* Gradient outputs, same layout as gftorf_gaussians.  Each non-NULL array is
@@ -77,6 +88,8 @@ typedef struct gftorf_gaussians_grad {
     float* opacity_logit;
     float* rgb;
     float* albedo;
+    float* sh_rgb;              /* [K][3][n], used with gftorf_gaussians.sh_rgb    */
+    float* sh_albedo;           /* [K][n], used with gftorf_gaussians.sh_albedo    */
 } gftorf_gaussians_grad;
 
 /* One rendered frame; an ARRAY of these lives in DEVICE memory, so a graph

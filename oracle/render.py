@@ -40,10 +40,16 @@ import math
 import numpy as np
 import torch
 
-from . import binning
+from . import binning, sh
 
 C_LIGHT = 299_792_458.0
 FIELDS = ("mean", "vel", "acc", "scale", "quat", "omega", "opacity_logit", "rgb", "albedo")
+SH_FIELDS = ("sh_rgb", "sh_albedo")   # optional view-dependent colour / reflectivity (§3)
+
+
+def fields_of(g):
+    """The parameter fields a Gaussian set carries (SH ones only when present)."""
+    return FIELDS + tuple(k for k in SH_FIELDS if getattr(g, k, None) is not None)
 
 
 def _w(x):
@@ -64,7 +70,7 @@ def _t(x, requires_grad=False):
 
 
 def params_to_torch(g, requires_grad=False):
-    return {k: _t(getattr(g, k), requires_grad) for k in FIELDS}
+    return {k: _t(getattr(g, k), requires_grad) for k in fields_of(g)}
 
 
 def _quat_rotation(q):
@@ -129,10 +135,23 @@ def gaussian_quantities(p, frame, cfg):
     centre = -(W.T @ tc)                                                 # optical centre
     d = torch.linalg.norm(mu - centre[:, None], dim=0)
     o = torch.sigmoid(p["opacity_logit"])
+    rgb, albedo = p["rgb"], p["albedo"]
+    if p.get("sh_rgb") is not None or p.get("sh_albedo") is not None:
+        # view-dependent colour and reflectivity (§3): spherical harmonics at
+        # the direction from the optical centre to the Gaussian centre
+        direc = (mu - centre[:, None]) / d
+        if p.get("sh_rgb") is not None:
+            rgb = sh.colour(p["sh_rgb"], direc, _degree(p["sh_rgb"].shape[0]))
+        if p.get("sh_albedo") is not None:
+            albedo = sh.colour(p["sh_albedo"][:, None, :], direc, _degree(p["sh_albedo"].shape[0]))[0]
     s_int = _s(cfg.source_intensity)
-    amp = s_int * p["albedo"] / d ** 2
+    amp = s_int * albedo / d ** 2
     psi = torch.stack([4.0 * math.pi * _s(f) * d / C_LIGHT for f in cfg.freqs])
-    return dict(u=u, v=v, A=A, B=B, C=Cc, o=o, d=d, amp=amp, psi=psi, rgb=p["rgb"])
+    return dict(u=u, v=v, A=A, B=B, C=Cc, o=o, d=d, amp=amp, psi=psi, rgb=rgb)
+
+
+def _degree(n_coeffs):
+    return {v: k for k, v in sh.N_COEFFS.items()}[int(n_coeffs)]
 
 
 QKEYS = ("u", "v", "A", "B", "C", "o", "d", "amp", "psi", "rgb")
@@ -326,7 +345,7 @@ def render(g, frames, cfg, tiles=None, upstream=None, flag_rel=(1e-5, 1e-4),
         out["tile_data"] = tile_data
     if want_grad:
         out["grads"] = {k: (params[k].grad.numpy().copy() if params[k].grad is not None
-                            else np.zeros(params[k].shape)) for k in FIELDS}
+                            else np.zeros(params[k].shape)) for k in params}
         out["grad_bg_rgb"] = grad_bg_rgb
         out["grad_bg_quad"] = grad_bg_quad
         out["grad2d"] = grad2d

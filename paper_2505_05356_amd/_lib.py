@@ -25,12 +25,16 @@ FRAME_FLOATS = 9 + 3 + 4 + 1 + 3 + MAX_QUAD + 4   # 40: ... t_lo, t_hi, quad_mas
 OK, EINVAL, ENOWS, EHIP, EOVERFLOW = 0, -1, -2, -3, -4
 
 
+SH_FIELDS = ("sh_rgb", "sh_albedo")
+
+
 class GaussiansC(ctypes.Structure):
-    _fields_ = [("n", c_int64)] + [(k, c_void_p) for k in FIELDS]
+    _fields_ = ([("n", c_int64)] + [(k, c_void_p) for k in FIELDS] +
+                [("sh_degree", c_int32), ("reserved", c_int32)] + [(k, c_void_p) for k in SH_FIELDS])
 
 
 class GaussiansGradC(ctypes.Structure):
-    _fields_ = [(k, c_void_p) for k in FIELDS]
+    _fields_ = [(k, c_void_p) for k in FIELDS + SH_FIELDS]
 
 
 class ConfigC(ctypes.Structure):

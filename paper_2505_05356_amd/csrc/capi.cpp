@@ -91,8 +91,12 @@ int depth_buffer(const gft::Params& P) { return gft::depth_sort_passes(P.F) & 1;
 
 int check_gauss(const gftorf_gaussians* g) {
     if (!g) return fail(GFTORF_EINVAL, "gaussians is NULL");
-    if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity_logit || !g->rgb || !g->albedo))
-        return fail(GFTORF_EINVAL, "required Gaussian array is NULL (mean, scale, quat, opacity_logit, rgb, albedo)");
+    if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity_logit || (!g->rgb && !g->sh_rgb) ||
+                     (!g->albedo && !g->sh_albedo)))
+        return fail(GFTORF_EINVAL, "required Gaussian array is NULL (mean, scale, quat, opacity_logit, "
+                                   "rgb or sh_rgb, albedo or sh_albedo)");
+    if ((g->sh_rgb || g->sh_albedo) && (g->sh_degree < 0 || g->sh_degree > 3))
+        return fail(GFTORF_EINVAL, "sh_degree must be in [0, 3]");
     return GFTORF_OK;
 }
 

@@ -15,6 +15,7 @@
 // descriptors are wave-uniform (scalar loads).  Outputs are indexed by item
 // i = frame * n + gaussian, so consecutive threads write consecutive records.
 #include "common.h"
+#include "sh.h"
 
 namespace gft {
 
@@ -208,8 +209,33 @@ __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g
         optical_centre(fr, cc);
         const double e0 = b.m[0] - cc[0], e1 = b.m[1] - cc[1], e2 = b.m[2] - cc[2];
         const double d = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-        r[2] = make_float4((float)G.rgb[0], (float)G.rgb[1], (float)G.rgb[2], (float)d);
-        const double amp = (double)P.s_int * G.albedo / (d * d);
+        float rgb[3] = {(float)G.rgb[0], (float)G.rgb[1], (float)G.rgb[2]};
+        double albedo = G.albedo;
+        if (g.sh_rgb || g.sh_albedo) {
+            // view-dependent colour / reflectivity at the viewing direction
+            const float id = (float)(1.0 / d);
+            float Y[kMaxSH];
+            sh_basis((float)e0 * id, (float)e1 * id, (float)e2 * id, g.sh_degree, Y);
+            const int K = sh_count(g.sh_degree);
+            const int64_t n = P.n;
+            if (g.sh_rgb)
+                for (int c = 0; c < 3; ++c) {
+                    float acc = 0.5f;
+#pragma unroll
+                    for (int l = 0; l < kMaxSH; ++l)
+                        if (l < K) acc += Y[l] * g.sh_rgb[((int64_t)l * 3 + c) * n + k];
+                    rgb[c] = fmaxf(acc, 0.0f);
+                }
+            if (g.sh_albedo) {
+                float acc = 0.5f;
+#pragma unroll
+                for (int l = 0; l < kMaxSH; ++l)
+                    if (l < K) acc += Y[l] * g.sh_albedo[(int64_t)l * n + k];
+                albedo = (double)fmaxf(acc, 0.0f);
+            }
+        }
+        r[2] = make_float4(rgb[0], rgb[1], rgb[2], (float)d);
+        const double amp = (double)P.s_int * albedo / (d * d);
         float ph[2 * GFTORF_MAX_FREQ];
         for (int fi = 0; fi < P.nf; ++fi) {
             // psi = 4 pi f d / c = 2 pi * cycles; reduce to the fractional cycle first
@@ -259,7 +285,7 @@ __device__ __forceinline__ float group_sum(float v) {
 
 constexpr int kNG = 25;   // gradient values per Gaussian
 
-template <int GS>
+template <int GS, bool SH>
 __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussians g,
                                                         const gftorf_frame* __restrict__ frames,
                                                         const uint32_t* __restrict__ cnt,
@@ -276,6 +302,13 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
     float acc[kNG];
 #pragma unroll
     for (int i = 0; i < kNG; ++i) acc[i] = 0.f;
+    // spherical-harmonic coefficient gradients: colour [l][c] at 3 l + c,
+    // reflectivity [l] at 3 kMaxSH + l
+    constexpr int NSH = SH ? 4 * kMaxSH : 1;
+    float ash[NSH];
+#pragma unroll
+    for (int i = 0; i < NSH; ++i) ash[i] = 0.f;
+    const int K = sh_count(g.sh_degree);
     if (have) {
         auto ld = [&](const float* p, int64_t i) { return p ? p[i] : 0.0f; };
         float x0[3], vv[3], aa[3], sc[3], q0[4], om[3];
@@ -288,6 +321,9 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
         }
         for (int c = 0; c < 4; ++c) q0[c] = ld(g.quat, c * n + k);
         const float albedo = ld(g.albedo, k);
+        // SH coefficients of this Gaussian (re-read from cache where used)
+        auto kr = [&](int l, int c) { return (g.sh_rgb && l < K) ? g.sh_rgb[((int64_t)l * 3 + c) * n + k] : 0.f; };
+        auto ka = [&](int l) { return (g.sh_albedo && l < K) ? g.sh_albedo[(int64_t)l * n + k] : 0.f; };
         const int RS4 = record_float4s(P.nf);
         const int GF = grad_floats(P.nf);
         const float L2E = 1.4426950408889634f;
@@ -323,8 +359,9 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
             float p[3];
             for (int i = 0; i < 3; ++i) p[i] = Wc[i][0] * m[0] + Wc[i][1] * m[1] + Wc[i][2] * m[2] + fr.t[i];
 
-            // colour, opacity (o from the record)
-            for (int c = 0; c < 3; ++c) acc[19 + c] += gr[6 + c];
+            // colour (flat), opacity (o from the record)
+            if (!SH || !g.sh_rgb)
+                for (int c = 0; c < 3; ++c) acc[19 + c] += gr[6 + c];
             acc[22] += gr[5] * r1.w * (1.0f - r1.w);
 
             // range d: depth channel + C-ToF amplitude and phase
@@ -334,8 +371,25 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
             const float d2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
             const float d = sqrtf(d2);
             const float id = 1.0f / d;
-            const float amp = P.s_int * albedo / d2;
+            // view-dependent colour / reflectivity: basis at the viewing direction
+            float Y[SH ? kMaxSH : 1], act_c[3] = {1.f, 1.f, 1.f}, r_item = albedo, act_r = 1.f;
+            if constexpr (SH) {
+                sh_basis(e[0] * id, e[1] * id, e[2] * id, g.sh_degree, Y);
+                float cs3[3] = {0.5f, 0.5f, 0.5f}, rs = 0.5f;
+#pragma unroll
+                for (int l = 0; l < kMaxSH; ++l) {
+                    for (int c = 0; c < 3; ++c) cs3[c] += Y[l] * kr(l, c);
+                    rs += Y[l] * ka(l);
+                }
+                for (int c = 0; c < 3; ++c) act_c[c] = cs3[c] > 0.f ? 1.f : 0.f;   // clamp at 0
+                if (g.sh_albedo) {
+                    r_item = fmaxf(rs, 0.f);
+                    act_r = rs > 0.f ? 1.f : 0.f;
+                }
+            }
+            const float amp = P.s_int * r_item / d2;
             float gd = gr[9];
+            float galb = 0.f;   // dL/dr of this item
             for (int fi = 0; fi < P.nf; ++fi) {
                 float cyc = (float)(2.0 * P.freq[fi] / kSpeedOfLight) * d;
                 cyc -= floorf(cyc);
@@ -345,10 +399,39 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
                 // a sin psi, a cos psi with a = s r / d^2, psi = 4 pi f d / c
                 gd += gas * (-2.0f * amp * id * sn + amp * cs * dpsi) +
                       gac * (-2.0f * amp * id * cs - amp * sn * dpsi);
-                acc[23] += (gas * sn + gac * cs) * P.s_int / d2;
+                galb += (gas * sn + gac * cs) * P.s_int / d2;
             }
             float gm[3];
             for (int c = 0; c < 3; ++c) gm[c] = gd * e[c] * id;
+            if (SH && g.sh_albedo) {
+                // through r = max(0, 1/2 + sum Y k) and the viewing direction
+            } else {
+                acc[23] += galb;
+            }
+            if constexpr (SH) {
+                float w[kMaxSH];   // dL/dY_l
+#pragma unroll
+                for (int l = 0; l < kMaxSH; ++l) {
+                    w[l] = 0.f;
+                    if (g.sh_rgb)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const float tc = gr[6 + c] * act_c[c];
+                            ash[3 * l + c] += Y[l] * tc;
+                            w[l] += kr(l, c) * tc;
+                        }
+                    if (g.sh_albedo) {
+                        const float tr = galb * act_r;
+                        ash[3 * kMaxSH + l] += Y[l] * tr;
+                        w[l] += ka(l) * tr;
+                    }
+                }
+                // direction = e / d: dL/de = (I - dir dir^T) dL/ddir / d
+                float gdir[3];
+                sh_basis_grad(e[0] * id, e[1] * id, e[2] * id, g.sh_degree, w, gdir[0], gdir[1], gdir[2]);
+                const float dot = (gdir[0] * e[0] + gdir[1] * e[1] + gdir[2] * e[2]) * id;
+                for (int c = 0; c < 3; ++c) gm[c] += (gdir[c] - dot * e[c] * id) * id;
+            }
 
             // conic gradient -> 2-D covariance gradient: -Q (dL/dQ) Q
             const float A = r1.x * (-2.0f / L2E), B = r1.y * (-1.0f / L2E), C = r1.z * (-2.0f / L2E);
@@ -447,7 +530,20 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
     }
 #pragma unroll
     for (int i = 0; i < kNG - 1; ++i) acc[i] = group_sum<GS>(acc[i]);
+    if constexpr (SH) {
+#pragma unroll
+        for (int i = 0; i < NSH; ++i) ash[i] = group_sum<GS>(ash[i]);
+    }
     if (!have || f0 != 0) return;
+    if constexpr (SH) {
+#pragma unroll
+        for (int l = 0; l < kMaxSH; ++l) {
+            if (l >= K) continue;
+            if (out.sh_rgb)
+                for (int c = 0; c < 3; ++c) out.sh_rgb[((int64_t)l * 3 + c) * n + k] = ash[3 * l + c];
+            if (out.sh_albedo) out.sh_albedo[(int64_t)l * n + k] = ash[3 * kMaxSH + l];
+        }
+    }
     for (int c = 0; c < 3; ++c) {
         if (out.mean) out.mean[c * n + k] = acc[c];
         if (out.vel) out.vel[c * n + k] = acc[3 + c];
@@ -484,9 +580,14 @@ void launch_preprocess_bwd(const Params& P, const gftorf_gaussians& g, const gft
     const unsigned blocks = (unsigned)((P.n * gs + threads - 1) / threads);
     if (blocks == 0) return;
     ProfScope _p("k_preprocess_bwd", s);
-#define GFT_PRE_BWD(G)                                                                                    \
-    hipLaunchKernelGGL(k_preprocess_bwd<G>, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.cnt, w.rec, \
-                       w.grec, grad)
+    const bool sh = g.sh_rgb || g.sh_albedo;
+#define GFT_PRE_BWD(G)                                                                                      \
+    if (sh)                                                                                                  \
+        hipLaunchKernelGGL((k_preprocess_bwd<G, true>), dim3(blocks), dim3(threads), 0, s, P, g, frames,      \
+                           w.cnt, w.rec, w.grec, grad);                                                      \
+    else                                                                                                     \
+        hipLaunchKernelGGL((k_preprocess_bwd<G, false>), dim3(blocks), dim3(threads), 0, s, P, g, frames,     \
+                           w.cnt, w.rec, w.grec, grad)
     switch (gs) {
         case 1: GFT_PRE_BWD(1); break;
         case 2: GFT_PRE_BWD(2); break;

@@ -23,7 +23,10 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FIELDS, FRAME_FLOATS, MAX_QUAD
+from ._lib import FIELDS, FRAME_FLOATS, MAX_QUAD, SH_FIELDS
+
+ALL_FIELDS = FIELDS + SH_FIELDS
+_SH_DEGREE = {1: 0, 4: 1, 9: 2, 16: 3}
 
 
 @dataclasses.dataclass
@@ -101,10 +104,29 @@ def gaussians_struct(params: Dict[str, torch.Tensor]) -> _lib.GaussiansC:
     g = _lib.GaussiansC()
     n = params["opacity_logit"].shape[0]
     g.n = n
-    for k in FIELDS:
+    # spherical-harmonic colour [K, 3, n] / reflectivity [K, n] replace rgb / albedo
+    degree = None
+    for k in SH_FIELDS:
         t = params.get(k)
         if t is None:
-            if k not in _lib.OPTIONAL:
+            setattr(g, k, None)
+            continue
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError(f"parameter {k} must be a contiguous float32 CUDA tensor")
+        K = t.shape[0]
+        if K not in _SH_DEGREE or t.numel() != K * (3 if k == "sh_rgb" else 1) * n:
+            raise ValueError(f"parameter {k} must be [K{', 3' if k == 'sh_rgb' else ''}, n] with K in 1, 4, 9, 16")
+        if degree is not None and _SH_DEGREE[K] != degree:
+            raise ValueError("sh_rgb and sh_albedo must have the same degree")
+        degree = _SH_DEGREE[K]
+        setattr(g, k, t.data_ptr())
+    g.sh_degree = degree or 0
+    for k in FIELDS:
+        t = params.get(k)
+        replaced = (k == "rgb" and params.get("sh_rgb") is not None) or \
+                   (k == "albedo" and params.get("sh_albedo") is not None)
+        if t is None:
+            if k not in _lib.OPTIONAL and not replaced:
                 raise ValueError(f"parameter {k} is required")
             setattr(g, k, None)
             continue
@@ -211,9 +233,9 @@ def backward(params, frames_dev, cfg, ws: Workspace, saved, d_rgb=None, d_quad=N
     F = frames_dev.shape[0]
     if grads is None:
         grads = {k: (torch.empty_like(params[k]) if params.get(k) is not None else None)
-                 for k in FIELDS}
+                 for k in ALL_FIELDS}
     gg = _lib.GaussiansGradC()
-    for k in FIELDS:
+    for k in ALL_FIELDS:
         setattr(gg, k, grads[k].data_ptr() if grads.get(k) is not None else None)
     d_bg = torch.empty((F, 3 + n_quad(cfg)), device=frames_dev.device) if want_bg else None
     g = gaussians_struct(params)
@@ -238,7 +260,7 @@ class RasterizeCToF(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, ws, frames_dev, cfg, *plist):
-        params = {k: (p.contiguous() if p is not None else None) for k, p in zip(FIELDS, plist)}
+        params = {k: (p.contiguous() if p is not None else None) for k, p in zip(ALL_FIELDS, plist)}
         out = forward(params, frames_dev, cfg, ws)
         ctx.ws, ctx.cfg, ctx.frames = ws, cfg, frames_dev
         ctx.params = params
@@ -252,7 +274,7 @@ class RasterizeCToF(torch.autograd.Function):
         c = lambda t: None if t is None else t.contiguous()
         grads = backward(ctx.params, ctx.frames, ctx.cfg, ctx.ws, ctx.saved_out,
                          c(g_rgb), c(g_quad), c(g_depth))
-        res = [grads[k] if present else None for k, present in zip(FIELDS, ctx.present)]
+        res = [grads[k] if present else None for k, present in zip(ALL_FIELDS, ctx.present)]
         return (None, None, None, *res)
 
 
@@ -263,7 +285,7 @@ def render(params, frames, cfg, ws: Optional[Workspace] = None):
     n = params["opacity_logit"].shape[0]
     if ws is None:
         ws = Workspace(n, frames_dev.shape[0], cfg)
-    plist = [params.get(k) for k in FIELDS]
+    plist = [params.get(k) for k in ALL_FIELDS]
     rgb, quad, depth, Tf, nc = RasterizeCToF.apply(ws, frames_dev, cfg, *plist)
     return dict(rgb=rgb, quad=quad, depth=depth, T_final=Tf, n_contrib=nc, workspace=ws)
 
@@ -281,4 +303,8 @@ def to_device_params(g, device="cuda", static=None) -> Dict[str, torch.Tensor]:
             out[k] = None
         else:
             out[k] = torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    for k in SH_FIELDS:   # only when the Gaussians carry them
+        a = getattr(g, k, None)
+        if a is not None:
+            out[k] = torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
     return out

@@ -15,13 +15,14 @@ from typing import Dict, Optional
 import torch
 
 from . import _lib, raster
-from ._lib import FIELDS
+from ._lib import FIELDS, SH_FIELDS
 
 # Per-field learning rates.  The paper states the reflectivity (albedo) rate
 # 1.6e-4 (heuristic H1, §4); the others are not stated and follow common
 # Gaussian-splatting practice for these parameterisations.
 DEFAULT_LR = {"mean": 1.6e-4, "vel": 1.6e-4, "acc": 1.6e-4, "scale": 5e-4, "quat": 1e-3,
-              "omega": 1e-3, "opacity_logit": 5e-2, "rgb": 2.5e-3, "albedo": 1.6e-4}
+              "omega": 1e-3, "opacity_logit": 5e-2, "rgb": 2.5e-3, "albedo": 1.6e-4,
+              "sh_rgb": 2.5e-3, "sh_albedo": 1.6e-4}
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -29,8 +30,9 @@ def _p(t: Optional[torch.Tensor]):
 
 
 class TrainStep:
-    """params: trainable float32 device tensors (FIELDS; optional ones may be None)
-    seq_frames: packed frame descriptors of the sequence [S, 36] (device)
+    """params: trainable float32 device tensors (FIELDS and, if used, the
+    spherical-harmonic SH_FIELDS; optional ones may be None)
+    seq_frames: packed frame descriptors of the sequence [S, 40] (device)
     targets_rgb [S, 3, H, W], targets_quad [S, NQ, H, W] (device)
     bg_table: None or [n_bg, batch, 3 + NQ] backgrounds drawn per step (device)
     """
@@ -59,7 +61,7 @@ class TrainStep:
         self.m = {k: (torch.zeros_like(v) if v is not None else None) for k, v in params.items()}
         self.v = {k: (torch.zeros_like(v) if v is not None else None) for k, v in params.items()}
         lrs = dict(DEFAULT_LR, **(lrs or {}))
-        groups = [k for k in FIELDS if params.get(k) is not None]
+        groups = [k for k in FIELDS + SH_FIELDS if params.get(k) is not None]
         self.groups = (_lib.AdamGroupC * len(groups))()
         for i, k in enumerate(groups):
             g = self.groups[i]
@@ -69,7 +71,7 @@ class TrainStep:
         self.graph = None
         self._gs = raster.gaussians_struct(params)
         self._gg = _lib.GaussiansGradC()
-        for k in FIELDS:
+        for k in FIELDS + SH_FIELDS:
             setattr(self._gg, k, self.grads[k].data_ptr() if self.grads.get(k) is not None else None)
         self._o = raster.outputs_struct(self.out)
 

@@ -42,16 +42,24 @@ class Gaussians:
     opacity_logit: np.ndarray  # [N] o = sigmoid(logit)
     rgb: np.ndarray            # [3, N] colour c_k
     albedo: np.ndarray         # [N] reflectivity r_k
+    # optional view-dependent colour / reflectivity (paper §3): real spherical
+    # harmonic coefficients, [K, 3, N] and [K, N] with K = (degree + 1)^2;
+    # when present they replace rgb / albedo
+    sh_rgb: Optional[np.ndarray] = None
+    sh_albedo: Optional[np.ndarray] = None
 
     FIELDS = ("mean", "vel", "acc", "scale", "quat", "omega",
               "opacity_logit", "rgb", "albedo")
+    SH_FIELDS = ("sh_rgb", "sh_albedo")
 
     @property
     def n(self) -> int:
         return int(self.opacity_logit.shape[0])
 
     def arrays(self):
-        return {k: getattr(self, k) for k in self.FIELDS}
+        out = {k: getattr(self, k) for k in self.FIELDS}
+        out.update({k: getattr(self, k) for k in self.SH_FIELDS if getattr(self, k) is not None})
+        return out
 
     def copy(self) -> "Gaussians":
         return Gaussians(**{k: np.array(v, dtype=np.float32, copy=True)
@@ -301,6 +309,28 @@ def tiny_scene(n: int, width: int, height: int, seed: int, f: float = None,
     cfg = RenderConfig(width=width, height=height, freqs=(30e6,), tile_w=8, tile_h=8)
     return Workload(f"tiny-{n}-{width}x{height}", g,
                     identity_frames([0.0], width, height, f, f, 4), cfg)
+
+
+def with_sh(g: Gaussians, degree: int = 3, seed: int = 0, scale: float = 0.3,
+            rgb: bool = True, albedo: bool = True) -> Gaussians:
+    """A copy of `g` with spherical-harmonic colour and reflectivity: the DC
+    coefficient reproduces the flat colour / albedo (c = 1/2 + Y_00 k_0), the
+    higher ones are N(0, scale^2 / (l + 1)) (seeded PCG64, drawn after
+    everything else)."""
+    K = (degree + 1) ** 2
+    rng = np.random.Generator(np.random.PCG64(seed))
+    y00 = 0.5 / np.sqrt(np.pi)
+    lvl = np.concatenate([[l] * (2 * l + 1) for l in range(degree + 1)])
+    out = dataclasses.replace(g)
+    if rgb:
+        k = rng.normal(0.0, 1.0, (K, 3, g.n)) * (scale / (lvl + 1.0))[:, None, None]
+        k[0] = (g.rgb.astype(np.float64) - 0.5) / y00
+        out.sh_rgb = _f32(k)
+    if albedo:
+        k = rng.normal(0.0, 1.0, (K, g.n)) * (scale / (lvl + 1.0))[:, None]
+        k[0] = (g.albedo.astype(np.float64) - 0.5) / y00
+        out.sh_albedo = _f32(k)
+    return out
 
 
 def async_quartet_frames(n_quartets: int, period: float, base: Frame, n_phase: int = 4,

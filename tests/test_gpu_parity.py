@@ -241,3 +241,28 @@ def test_async_quartets_match_oracle():
         assert_grads_close(res_b["grads"][k], r, f"async/{k}")
     bg_ref = np.concatenate([ref_b["grad_bg_rgb"], ref_b["grad_bg_quad"]], 1)
     assert_grads_close(res_b["grad_bg"], bg_ref, "async/bg")
+
+
+@pytest.mark.parametrize("degree", [3, 1])
+def test_spherical_harmonics_match_oracle(degree):
+    # View-dependent colour (16 x 3 coefficients at degree 3) and reflectivity
+    # (16): forward against the oracle, and the gradients of every field
+    # including the coefficients (rgb and albedo are replaced: zero gradient).
+    g = scenes.with_sh(scenes.draw_gaussians(2000, 80, 64, 70.0, 70.0, seed=13, dynamic=True), degree,
+                       seed=5, scale=0.6)
+    frames = scenes.identity_frames([0.0, 0.15], 80, 64, 70.0, 70.0, 4, bg_seed=9)
+    cfg = scenes.RenderConfig(width=80, height=64)
+    ref = oref.render(g, frames, cfg)
+    ok = ~ref["flagged"]
+    res = run_gpu(g, frames, cfg)
+    for k in ("rgb", "quad", "depth", "T_final"):
+        assert_images_close(res[k], ref[k], ok, f"sh{degree}/{k}")
+    up = mask_upstream(scenes.upstream_grads(len(frames), cfg, seed=2), ok)
+    ref_b = oref.render(g, frames, cfg, upstream=up)
+    res_b = run_gpu(g, frames, cfg, upstream=up)
+    assert set(ref_b["grads"]) >= {"sh_rgb", "sh_albedo"}
+    for k, r in ref_b["grads"].items():
+        if k in ("rgb", "albedo"):
+            assert not np.any(res_b["grads"][k]), k
+            continue
+        assert_grads_close(res_b["grads"][k], r, f"sh{degree}/{k}")

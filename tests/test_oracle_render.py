@@ -241,6 +241,43 @@ def test_gradients_central_differences(dynamic):
     np.testing.assert_allclose(out["grad_bg_quad"][0], (up["quad"][0] * Tf).sum((1, 2)), rtol=1e-10)
 
 
+def test_sh_gradients_central_differences():
+    # view-dependent colour and reflectivity: the coefficients and, through
+    # the viewing direction, the centre
+    wl = _smooth_scene(5, False)
+    cfg = wl.cfg.strict()
+    fr = dataclasses.replace(wl.frames[0], bg_rgb=np.array([0.2, 0.1, -0.3], np.float32))
+    up = scenes.upstream_grads(1, cfg, seed=4)
+    g32 = scenes.with_sh(wl.gaussians, 3, seed=2)
+    g64 = scenes.Gaussians(**{k: v.astype(np.float64) for k, v in g32.arrays().items()})
+    out = render.render(g64, [fr], cfg, upstream=up)
+    assert not np.any(out["grads"]["rgb"]) and not np.any(out["grads"]["albedo"])   # replaced by SH
+    rng = np.random.default_rng(3)
+    for name in ("sh_rgb", "sh_albedo", "mean"):
+        arr = getattr(g64, name)
+        for _ in range(4):
+            idx = tuple(rng.integers(0, s) for s in arr.shape)
+            h = 1e-6 * max(1.0, abs(arr[idx]))
+            vals = []
+            for sgn in (1, -1):
+                gp = scenes.Gaussians(**{k: v.copy() for k, v in g64.arrays().items()})
+                getattr(gp, name)[idx] += sgn * h
+                vals.append(render.loss_of(render.render(gp, [fr], cfg), up))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = out["grads"][name][idx]
+            assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-2), (name, idx, fd, an)
+
+
+def test_sh_degree_zero_is_the_flat_colour():
+    # DC-only coefficients built from rgb / albedo reproduce the flat render
+    wl = scenes.cfg1()
+    g = scenes.with_sh(wl.gaussians, 0, seed=0)
+    a = render.render(g, wl.frames, wl.cfg)
+    b = render.render(wl.gaussians, wl.frames, wl.cfg)
+    for k in ("rgb", "quad", "depth"):
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-6, atol=1e-6)
+
+
 def test_dense_scene_statistics():
     # cfg-1 sanity: pairs, contributions and the stop rule all exercised.
     wl = scenes.cfg1()
