@@ -436,14 +436,23 @@ __global__ void __launch_bounds__(1024) k_tile_keyscan(const uint32_t* __restric
                                                        Status* status) {
     __shared__ unsigned long long scratch[17];
     unsigned long long carry = 0;
-    for (long long base = 0; base < K; base += 1024) {
-        const long long i = base + threadIdx.x;
-        const unsigned long long v = i < K ? tcount[i] : 0ull;
+    // 4 consecutive tiles per thread, 4096 per round
+    for (long long base = 0; base < K; base += 4096) {
+        const long long i0 = base + 4 * (long long)threadIdx.x;
+        uint32_t v[4];
+        unsigned long long sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = i0 + j < K ? tcount[i0 + j] : 0u;
+            sum += v[j];
+        }
         unsigned long long tot;
-        const unsigned long long ex = block_exclusive_scan<unsigned long long, 1024>(v, scratch, &tot);
-        if (i < K) {
-            const unsigned long long a = carry + ex, b = a + v;
-            ranges[i] = make_uint2((uint32_t)(a < cap ? a : cap), (uint32_t)(b < cap ? b : cap));
+        unsigned long long a = carry + block_exclusive_scan<unsigned long long, 1024>(sum, scratch, &tot);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const unsigned long long b = a + v[j];
+            if (i0 + j < K) ranges[i0 + j] = make_uint2((uint32_t)(a < cap ? a : cap), (uint32_t)(b < cap ? b : cap));
+            a = b;
         }
         carry += tot;
     }

@@ -11,9 +11,9 @@
 // FMA contraction off, so the lists are reproducible bit for bit.
 //
 // Layout: one thread per Gaussian; the thread loops over the frames so the
-// 24 parameter floats of a Gaussian are read from HBM once per batch; frame
-// descriptors are wave-uniform (scalar loads).  Outputs are indexed by item
-// i = frame * n + gaussian, so consecutive threads write consecutive records.
+// 24 parameter floats of a Gaussian are read from HBM once per batch.
+// Outputs are indexed by item i = frame * n + gaussian, so consecutive
+// threads write consecutive records.
 #include "common.h"
 #include "sh.h"
 
@@ -584,7 +584,7 @@ void launch_preprocess_bwd(const Params& P, const gftorf_gaussians& g, const gft
 #define GFT_PRE_BWD(G)                                                                                      \
     if (sh)                                                                                                  \
         hipLaunchKernelGGL((k_preprocess_bwd<G, true>), dim3(blocks), dim3(threads), 0, s, P, g, frames,      \
-                           w.cnt, w.rec, w.grec, grad);                                                      \
+                           w.cnt, w.rec, w.grec, grad);                                            \
     else                                                                                                     \
         hipLaunchKernelGGL((k_preprocess_bwd<G, false>), dim3(blocks), dim3(threads), 0, s, P, g, frames,     \
                            w.cnt, w.rec, w.grec, grad)

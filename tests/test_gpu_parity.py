@@ -266,3 +266,22 @@ def test_spherical_harmonics_match_oracle(degree):
             assert not np.any(res_b["grads"][k]), k
             continue
         assert_grads_close(res_b["grads"][k], r, f"sh{degree}/{k}")
+
+
+def test_backward_twice_after_one_forward():
+    # every backward starts from cleared gradient records, so a second
+    # backward after one forward repeats the first
+    wl = CASES["dynamic-3f-8x8-bg"]
+    up = scenes.upstream_grads(len(wl.frames), wl.cfg, seed=4)
+    res = run_gpu(wl.gaussians, wl.frames, wl.cfg, upstream=up)
+    d = {k: torch.from_numpy(np.ascontiguousarray(up[k], dtype=np.float32)).cuda()
+         for k in ("rgb", "quad", "depth")}
+    from paper_2505_05356_amd import raster
+    again = raster.backward(res["_params"], res["_frames"], wl.cfg, res["_ws"], res["_out"],
+                            d["rgb"], d["quad"], d["depth"])
+    torch.cuda.synchronize()
+    for k, v in again.items():
+        if v is None:
+            continue
+        # equal up to the float32 atomic summation order of the composite backward
+        assert_grads_close(v.cpu().numpy(), res["grads"][k], f"twice/{k}", rtol=1e-4)
