@@ -287,13 +287,16 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
 //
 // The upstream gradients are constant per pixel, so the recursions of Eq. S2
 // (RGB and depth, factor 1 - alpha) and Eq. S3 (quads, factor (1 - alpha)^2)
-// only enter dL/dalpha through two scalars per pixel:
-//   s1 = sum_c dL/dc_c acc_c + dL/dd acc_d,
-//   s2 = sum_f dL/dS_f acc_S,f + dL/dC_f acc_C,f,
-// which obey the same recursions with the per-entry values
-//   u = sum_c dL/dc_c c_k,c + dL/dd d_k and v = sum_f dL/dS_f a sin psi + dL/dC_f a cos psi:
-//   dL/dalpha_k = T_k (u - s1) + T_k^2 (v + 2 (alpha_k - 1) s2) - bg / (1 - alpha_k),
-//   s1 <- alpha_k u + (1 - alpha_k) s1,  s2 <- alpha_k v + (1 - alpha_k)^2 s2.
+// only enter dL/dalpha through the per-entry values
+//   u_k = sum_c dL/dc_c c_k,c + dL/dd d_k,  v_k = sum_f dL/dS_f a sin psi + dL/dC_f a cos psi
+// and their suffix sums behind entry k, kept un-normalised:
+//   A1 = sum_{j>k} u_j alpha_j T_j,  A2 = sum_{j>k} v_j alpha_j T_j^2.
+// (The normalised accumulators of S2 / S3 are A1 / T_{k+1} and
+// A2 / T_{k+1}^2.)  With the background term bg = c_bg . dL/dc T_final +
+// p q_bg . dL/dq T_final^p,
+//   dL/dalpha_k = T_k u_k + T_k^2 v_k - (A1 + 2 A2 + bg) / (1 - alpha_k),
+// so one running sum A = A1 + 2 A2 + bg per pixel suffices:
+//   A <- A + u_k alpha_k T_k + 2 v_k alpha_k T_k^2.
 template <int TW, int TH, int NF>
 __global__ void __launch_bounds__(64) k_composite_bwd(
     Params P, const gftorf_frame* __restrict__ frames, const uint2* __restrict__ ranges,
@@ -324,7 +327,7 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
     const gftorf_frame& fr = frames[f];
     const size_t HW = (size_t)P.H * P.W;
 
-    float fpx[PPT], fpy[PPT], T[PPT], bgT[PPT], s1[PPT], s2[PPT];
+    float fpx[PPT], fpy[PPT], T[PPT], A[PPT];
     uint32_t last[PPT];
     float gr[PPT][3], gd[PPT], gS[PPT][NF], gC[PPT][NF];
     float bg_acc[3 + GFTORF_MAX_QUAD];
@@ -369,11 +372,9 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
                     }
             }
         }
-        // background terms of dL/dalpha_k, before division by (1 - alpha_k):
-        // c_bg . dL/dc T_final + p q_bg . dL/dq T_final^p
-        bgT[i] = brd * Tf + (float)P.bg_pow * bqd * Tp;
+        // the suffix sum starts with the background term
+        A[i] = brd * Tf + (float)P.bg_pow * bqd * Tp;
         T[i] = Tf;
-        s1[i] = s2[i] = 0.f;
         maxl = max(maxl, last[i]);
     }
     // background gradients: dL/dc_bg = sum d_rgb T_final, dL/dq_bg = sum d_quad T_final^p
@@ -433,6 +434,9 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
             // Branch-free per pixel: inactive pixels contribute zero and keep
             // their state (selects instead of divergent blocks, so the field
             // registers are never copied at control-flow joins).
+            // The conic and centre gradients only need, per lane (one pixel
+            // column, so one dx), sum gq, sum gq dy and sum gq dy^2
+            float p0 = 0.f, p1 = 0.f, p2 = 0.f;
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 const float G = __builtin_amdgcn_exp2f(qe[i]);
@@ -443,20 +447,18 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
                 // ae = alpha of a composited entry, 0 otherwise: with ae = 0
                 // every state update below is the identity (rcp(1) = 1)
                 const float ae = act ? a : 0.0f;
-                const float om = 1.0f - ae;
-                const float rom = __builtin_amdgcn_rcpf(om);
+                const float rom = __builtin_amdgcn_rcpf(1.0f - ae);
                 const float Ti = T[i] * rom;
                 const float T2 = Ti * Ti;
                 const float u = gr[i][0] * r2.x + gr[i][1] * r2.y + gr[i][2] * r2.z + gd[i] * r2.w;
                 float v = 0.f;
 #pragma unroll
                 for (int k = 0; k < NF; ++k) v += gS[i][k] * as[k] + gC[i][k] * ac[k];
-                const float dA = Ti * (u - s1[i]) + T2 * (v + 2.0f * (a - 1.0f) * s2[i]) - bgT[i] * rom;
+                const float dA = Ti * u + T2 * v - rom * A[i];
                 T[i] = Ti;
-                s1[i] = __builtin_fmaf(ae, u - s1[i], s1[i]);        // alpha u + (1 - alpha) s1
-                s2[i] = __builtin_fmaf(ae, v, (om * om) * s2[i]);    // alpha v + (1 - alpha)^2 s2
                 const float w1 = ae * Ti;
                 const float w2 = ae * T2;
+                A[i] += w1 * u + w2 * (2.0f * v);
                 g[6] += w1 * gr[i][0];
                 g[7] += w1 * gr[i][1];
                 g[8] += w1 * gr[i][2];
@@ -466,18 +468,23 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
                     g[10 + 2 * k] += w2 * gS[i][k];
                     g[11 + 2 * k] += w2 * gC[i][k];
                 }
-                // alpha = o 2^q unless clamped (then alpha has no gradient).
-                // gq = dL/dq / ln 2; the factor ln 2 of fields 0..4 and the
-                // conic of the centre gradient are applied once per entry.
+                // alpha = o 2^q unless clamped (then alpha has no gradient);
+                // gq = dL/dq / ln 2
                 const float dAe = (act && oG <= amax) ? dA : 0.0f;
                 const float gq = dAe * a;
-                const float gx = gq * dx[i], gy = gq * dy[i];
                 g[5] += G * dAe;                                 // d/do
-                g[2] += gx * dx[i];                              // d/dcA
-                g[3] += gx * dy[i];                              // d/dcB
-                g[4] += gy * dy[i];                              // d/dcC
-                g[0] += gx;                                      // sum gx
-                g[1] += gy;                                      // sum gy
+                const float gy = gq * dy[i];
+                p0 += gq;
+                p1 += gy;
+                p2 += gy * dy[i];
+            }
+            {
+                const float dxl = dx[0];                         // the lane's column
+                g[0] += dxl * p0;                                // sum gx
+                g[1] += p1;                                      // sum gy
+                g[2] += (dxl * dxl) * p0;                        // d/dcA
+                g[3] += dxl * p1;                                // d/dcB
+                g[4] += p2;                                      // d/dcC
             }
             if (__ballot(any) == 0ull) continue;
             // one reduce-scatter over the wave, then one atomic instruction whose
