@@ -66,9 +66,71 @@ def parse():
                     help="seconds of oracle tile work in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
+    ap.add_argument("--workload", default="cfg3", choices=("cfg2", "cfg3", "cfg4", "cfg5"),
+                    help="cfg3 (default): the headline batched vs per-frame line; cfg2 / cfg4: the "
+                         "same measurement on the static 100k / 1M-Gaussian 16-frame workloads; "
+                         "cfg5: the graph-replayed optimisation step")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after timing, one device-to-device copy of this many MiB (for counter runs)")
     return ap.parse_args()
+
+
+def bench_train_step(args):
+    """Optimisation-step loop: 300k trainable Gaussians fitted to a 60-frame
+    sequence rendered by the forward from a seeded ground-truth scene, batch of
+    4 frames per step, RGB + quad L2 loss, Adam on every field, one captured
+    HIP graph replayed per step.  Prints one JSON line (steps/s)."""
+    import torch
+
+    import scenes
+    from paper_2505_05356_amd import raster, step as gstep
+
+    dev = "cuda:0"
+    gt, tr, cfg = scenes.cfg5_scenes()
+    S = 60
+    W, H, f = cfg.width, cfg.height, 525.0
+    seq = scenes.identity_frames([i / 30.0 for i in range(S)], W, H, f, f, cfg.n_quad)
+    seq_dev = raster.pack_frames(seq, cfg, dev)
+    # targets: the ground-truth scene rendered by the forward, 8 frames at a time
+    gt_params = raster.to_device_params(gt, dev)
+    tgt_rgb = torch.empty((S, 3, H, W), device=dev)
+    tgt_quad = torch.empty((S, cfg.n_quad, H, W), device=dev)
+    ws = raster.Workspace(gt.n, 8, cfg, device=dev)
+    for c0 in range(0, S, 8):
+        fr = seq_dev[c0:c0 + 8].contiguous()
+        out = raster.forward(gt_params, fr, cfg, ws, check=True)
+        tgt_rgb[c0:c0 + fr.shape[0]] = out["rgb"]
+        tgt_quad[c0:c0 + fr.shape[0]] = out["quad"]
+    del ws, gt_params
+    rng = np.random.default_rng(7)
+    bg = torch.from_numpy(rng.uniform(-1, 1, (64, 4, 3 + cfg.n_quad)).astype(np.float32)).to(dev)
+    params = raster.to_device_params(tr, dev, static=False)
+    ts = gstep.TrainStep(params, seq_dev, tgt_rgb, tgt_quad, cfg, batch=4, bg_table=bg)
+    ts.size_workspace()
+    ts.capture()
+    for _ in range(args.warmup):
+        ts.replay()
+    torch.cuda.synchronize()
+    l0 = ts.loss.item()
+    t0 = time.perf_counter()
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s_ev.record(ts.stream)
+    for _ in range(args.steps):
+        ts.replay()
+    e_ev.record(ts.stream)
+    torch.cuda.synchronize()
+    ms = s_ev.elapsed_time(e_ev)
+    line = {
+        "metric": "optimisation steps/s (4-frame batch: fwd + L2 loss + bwd + Adam, one HIP graph)",
+        "value": round(args.steps / (ms / 1e3), 2), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded ground-truth scene rendered as targets; no dataset)",
+        "config": {"workload": f"train-{tr.n // 1000}k-{S}f-{W}x{H}-batch4", "n_gaussians": tr.n,
+                   "sequence_frames": S, "batch": 4, "wall_s": round(time.perf_counter() - t0, 3),
+                   "loss_after_warmup": l0, "loss_last": ts.loss.item()},
+    }
+    print(json.dumps(line), flush=True)
 
 
 def traffic_bytes(name):
@@ -100,7 +162,14 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    wl = scenes.cfg3(n=args.n, n_frames=args.frames)
+    if args.workload == "cfg5":
+        return bench_train_step(args)
+    if args.workload == "cfg2":
+        wl = scenes.cfg2()
+    elif args.workload == "cfg4":
+        wl = scenes.cfg4()
+    else:
+        wl = scenes.cfg3(n=args.n, n_frames=args.frames)
     F = len(wl.frames)
     g = wl.gaussians
     params = raster.to_device_params(g, dev)
@@ -228,7 +297,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded dynamic Gaussian scene; no dataset)",
-        "config": {"workload": f"dynamic-{g.n // 1000}k-gaussians-{F}f-{cfg.width}x{cfg.height}",
+        "config": {"workload": wl.name if args.workload != "cfg3" else
+                   f"dynamic-{g.n // 1000}k-gaussians-{F}f-{cfg.width}x{cfg.height}",
                    "n_gaussians": g.n, "frames": F, "width": cfg.width, "height": cfg.height,
                    "tile": args.tile, "freqs_hz": list(cfg.freqs), "quads": cfg.n_quad,
                    "outputs": "rgb+quad+depth", "pairs": P, "evals_fwd": work["E_fwd"],
