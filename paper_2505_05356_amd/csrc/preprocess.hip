@@ -173,6 +173,7 @@ __device__ __forceinline__ void optical_centre(const gftorf_frame& fr, double c[
                  (double)fr.R[6 + i] * fr.t[2]);
 }
 
+template <bool SH>
 __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g,
                                                     const gftorf_frame* __restrict__ frames,
                                                     float4* __restrict__ rec, uint2* __restrict__ rect,
@@ -211,7 +212,7 @@ __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g
         const double d = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
         float rgb[3] = {(float)G.rgb[0], (float)G.rgb[1], (float)G.rgb[2]};
         double albedo = G.albedo;
-        if (g.sh_rgb || g.sh_albedo) {
+        if (SH) {
             // view-dependent colour / reflectivity at the viewing direction
             const float id = (float)(1.0 / d);
             float Y[kMaxSH];
@@ -566,8 +567,12 @@ void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_
     const unsigned blocks = (unsigned)((P.n + threads - 1) / threads);
     if (blocks == 0) return;
     { ProfScope _p("k_preprocess", s);
-    hipLaunchKernelGGL(k_preprocess, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec, w.drect[0],
-                       w.cnt, w.dkey[0], w.dval[0], w.status);
+    if (g.sh_rgb || g.sh_albedo)
+        hipLaunchKernelGGL(k_preprocess<true>, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec,
+                           w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.status);
+    else
+        hipLaunchKernelGGL(k_preprocess<false>, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec,
+                           w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.status);
     }
 }
 
