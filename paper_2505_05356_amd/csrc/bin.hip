@@ -74,37 +74,27 @@ __global__ void __launch_bounds__(256) k_group_count(Params P, int C, int QC,
     for (int t = threadIdx.x; t < G.ng; t += 256) out[t] = lcnt[t];
 }
 
-// grid (ceil(ng / 64), F), 1024 threads: lane = group within a block of 64,
-// wave = one sixteenth of the frame's chunk rows.  Exclusive scan of every
-// group's column over the chunks of its frame; totals per (frame, group).
-__global__ void __launch_bounds__(1024) k_group_colscan(Params P, int QC, uint32_t* __restrict__ cntA,
-                                                        uint32_t* __restrict__ lenA) {
-    __shared__ uint32_t part[16][64];
+// grid (ng, F), 256 threads: one workgroup per (frame, group) column.
+// Exclusive scan of the column over the chunks of its frame (each thread a
+// run of consecutive chunks), and the column total.
+__global__ void __launch_bounds__(256) k_group_colscan(Params P, int QC, uint32_t* __restrict__ cntA,
+                                                       uint32_t* __restrict__ lenA) {
+    __shared__ uint32_t scratch[8];
     const Groups G = groups_of(P);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int gi = blockIdx.x * 64 + lane;
-    const int f = blockIdx.y;
-    const int rows = (QC + 15) / 16;
-    const int q0 = wave * rows, q1 = min(q0 + rows, QC);
+    const int gi = blockIdx.x, f = blockIdx.y;
+    const int per = (QC + 255) / 256;
+    const int q0 = min((int)threadIdx.x * per, QC), q1 = min(q0 + per, QC);
     uint32_t* col = cntA + (size_t)f * QC * G.ng + gi;
     uint32_t s = 0;
-    if (gi < G.ng)
-        for (int q = q0; q < q1; ++q) s += col[(size_t)q * G.ng];
-    part[wave][lane] = s;
-    __syncthreads();
-    uint32_t run = 0, total = 0;
-    for (int w = 0; w < 16; ++w) {
-        if (w < wave) run += part[w][lane];
-        total += part[w][lane];
+    for (int q = q0; q < q1; ++q) s += col[(size_t)q * G.ng];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<uint32_t, 256>(s, scratch, &total);
+    for (int q = q0; q < q1; ++q) {
+        const uint32_t v = col[(size_t)q * G.ng];
+        col[(size_t)q * G.ng] = run;
+        run += v;
     }
-    if (gi < G.ng) {
-        for (int q = q0; q < q1; ++q) {
-            const uint32_t v = col[(size_t)q * G.ng];
-            col[(size_t)q * G.ng] = run;
-            run += v;
-        }
-        if (wave == 0) lenA[(size_t)f * G.ng + gi] = total;
-    }
+    if (threadIdx.x == 0) lenA[(size_t)f * G.ng + gi] = total;
 }
 
 // Single workgroup: group-list ranges (exclusive scan of the lengths) and the
@@ -488,7 +478,7 @@ BinGeom bin_geometry(int64_t n, int32_t n_frames, int ntx, int nty, uint64_t cap
     // level-A chunks: enough waves to fill the chip, at least 128 items each
     const int64_t M = n * (int64_t)n_frames;
     int C = 128;
-    while (C < 2048 && M / C > 4096) C *= 2;
+    while (C < 2048 && M / C > 16384) C *= 2;
     g.C = C;
     g.QC = n > 0 ? (int)((n + C - 1) / C) : 0;
     g.ng = ((ntx + kGroupW - 1) / kGroupW) * ((nty + kGroupH - 1) / kGroupH);
@@ -514,7 +504,7 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     if (chunks) {
         ProfScope _p("k_group_colscan", s);
-        hipLaunchKernelGGL(k_group_colscan, dim3((g.ng + 63) / 64, P.F), dim3(1024), 0, s, P, g.QC,
+        hipLaunchKernelGGL(k_group_colscan, dim3(g.ng, P.F), dim3(256), 0, s, P, g.QC,
                            w.cntA, w.lenA);
     } else {
         launch_fill_u32(w.lenA, 0u, K, s);
