@@ -384,22 +384,41 @@ __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32
     }
 }
 
-// One wave per (frame, group): exclusive scan of each lane's tile column over
-// the group's segments; per-tile totals.
-__global__ void __launch_bounds__(64) k_tile_colscan(Params P, const uint32_t* __restrict__ seg_start,
-                                                     uint32_t* __restrict__ cntB,
-                                                     uint32_t* __restrict__ tcount) {
+// One workgroup of 4 waves per (frame, group): exclusive scan of each lane's
+// tile column over the group's segments (each wave a quarter of them, then a
+// prefix over the waves); per-tile totals.
+__global__ void __launch_bounds__(256) k_tile_colscan(Params P, const uint32_t* __restrict__ seg_start,
+                                                      uint32_t* __restrict__ cntB,
+                                                      uint32_t* __restrict__ tcount) {
+    __shared__ uint32_t part[4][64];
     const Groups G = groups_of(P);
     const int fg = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int f = fg / G.ng, gi = fg - f * G.ng;
     const uint32_t gy = gi / G.ngx, gx = gi - gy * G.ngx;
     const uint32_t tx = gx * kGroupW + lane % kGroupW, ty = gy * kGroupH + lane / kGroupW;
-    uint32_t run = 0;
-    const uint32_t b1 = seg_start[fg + 1];
-    uint32_t b = seg_start[fg];
-    // 8 segments per step: independent loads in flight together
-    for (; b + 8 <= b1; b += 8) {
+    const uint32_t s0 = seg_start[fg], s1 = seg_start[fg + 1];
+    const uint32_t per = (s1 - s0 + 3) / 4;
+    const uint32_t b0 = min(s0 + wave * per, s1), b1 = min(b0 + per, s1);
+    uint32_t sum = 0;
+    uint32_t b = b0;
+    for (; b + 8 <= b1; b += 8) {   // 8 independent loads in flight
+        uint32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = cntB[(size_t)(b + i) * 64 + lane];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sum += v[i];
+    }
+    for (; b < b1; ++b) sum += cntB[(size_t)b * 64 + lane];
+    part[wave][lane] = sum;
+    __syncthreads();
+    uint32_t run = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        run += w < wave ? part[w][lane] : 0u;
+        total += part[w][lane];
+    }
+    for (b = b0; b + 8 <= b1; b += 8) {
         uint32_t v[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = cntB[(size_t)(b + i) * 64 + lane];
@@ -414,8 +433,8 @@ __global__ void __launch_bounds__(64) k_tile_colscan(Params P, const uint32_t* _
         cntB[(size_t)b * 64 + lane] = run;
         run += v;
     }
-    if (tx < (uint32_t)P.ntx && ty < (uint32_t)P.nty)
-        tcount[(size_t)f * P.n_tiles + ty * P.ntx + tx] = run;
+    if (wave == 0 && tx < (uint32_t)P.ntx && ty < (uint32_t)P.nty)
+        tcount[(size_t)f * P.n_tiles + ty * P.ntx + tx] = total;
 }
 
 // Single workgroup: tile-list ranges = exclusive scan of the per-(frame, tile)
@@ -423,6 +442,7 @@ __global__ void __launch_bounds__(64) k_tile_colscan(Params P, const uint32_t* _
 // are clamped to the capacity so that an overflowed forward stays in bounds.
 __global__ void __launch_bounds__(1024) k_tile_keyscan(const uint32_t* __restrict__ tcount, long long K,
                                                        unsigned long long cap, uint2* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ nf_block, int n_blocks,
                                                        Status* status) {
     __shared__ unsigned long long scratch[17];
     unsigned long long carry = 0;
@@ -446,10 +466,19 @@ __global__ void __launch_bounds__(1024) k_tile_keyscan(const uint32_t* __restric
         }
         carry += tot;
     }
+    uint32_t nf = 0;   // non-finite Gaussians counted by the preprocess blocks
+    for (int i = threadIdx.x; i < n_blocks; i += 1024) nf += nf_block[i];
+    nf = wave_reduce_sum(nf);
+    __shared__ uint32_t nf_sum;
+    if (threadIdx.x == 0) nf_sum = 0;
+    __syncthreads();
+    if (lane_id() == 0 && nf) atomicAdd(&nf_sum, nf);
+    __syncthreads();
     if (threadIdx.x == 0) {
         status->n_pairs = carry;
         status->cap = cap;
         status->overflow = carry > cap ? 1u : 0u;
+        status->nonfinite = nf_sum;
     }
 }
 
@@ -530,12 +559,13 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     {
         ProfScope _p("k_tile_colscan", s);
-        hipLaunchKernelGGL(k_tile_colscan, dim3(K), dim3(64), 0, s, P, w.seg_start, w.cntB, w.tcount);
+        hipLaunchKernelGGL(k_tile_colscan, dim3(K), dim3(256), 0, s, P, w.seg_start, w.cntB, w.tcount);
     }
     {
         ProfScope _p("k_tile_keyscan", s);
         hipLaunchKernelGGL(k_tile_keyscan, dim3(1), dim3(1024), 0, s, w.tcount,
-                           (long long)P.F * P.n_tiles, (unsigned long long)P.cap, w.ranges, w.status);
+                           (long long)P.F * P.n_tiles, (unsigned long long)P.cap, w.ranges, w.nf_block,
+                           (int)((P.n + 255) / 256), w.status);
     }
     {
         ProfScope _p("k_tile_place", s);

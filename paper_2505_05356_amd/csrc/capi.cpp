@@ -214,7 +214,7 @@ int gftorf_render_fwd(const gftorf_gaussians* g, const gftorf_frame* frames, int
     hipStream_t s = static_cast<hipStream_t>(stream);
     (void)hipGetLastError();
 
-    gft::launch_fill_u32(reinterpret_cast<uint32_t*>(w.status), 0u, sizeof(gft::Status) / 4, s);
+    // every Status field is written during the forward (no clearing launch)
     gft::launch_preprocess(P, *g, frames, w, s);
     const int dbuf = gft::launch_depth_sort(P, w, s);
     hipError_t e = gft::launch_binning(P, w, dbuf, s);

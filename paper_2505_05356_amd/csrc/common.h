@@ -71,6 +71,7 @@ struct Workspace {
     Status* status;
     float4* rec;            // [M][record_float4s]
     uint32_t* cnt;          // [M] tiles covered
+    uint32_t* nf_block;     // [ceil(n / 256)] non-finite Gaussians per preprocess block
     uint32_t* dkey[2];      // [M] depth keys (double buffer)
     uint32_t* dval[2];      // [M] item ids
     uint2* drect[2];        // [M] tile rectangles (x_lo | x_hi << 16, y_lo | y_hi << 16), sort payload
@@ -113,6 +114,7 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nt
     w.status = reinterpret_cast<Status*>(take(sizeof(Status)));
     w.rec = reinterpret_cast<float4*>(take(sizeof(float4) * record_float4s(nf) * M));
     w.cnt = reinterpret_cast<uint32_t*>(take(4 * M));
+    w.nf_block = reinterpret_cast<uint32_t*>(take(4 * (size_t)((n + 255) / 256 + 1)));
     for (int i = 0; i < 2; ++i) w.dkey[i] = reinterpret_cast<uint32_t*>(take(4 * M));
     for (int i = 0; i < 2; ++i) w.dval[i] = reinterpret_cast<uint32_t*>(take(4 * M));
     for (int i = 0; i < 2; ++i) w.drect[i] = reinterpret_cast<uint2*>(take(sizeof(uint2) * M));

@@ -510,6 +510,7 @@ __global__ void __launch_bounds__(1024) k_sum_counts(const uint2* __restrict__ w
                                                      Status* status) {
     __shared__ unsigned long long scratch[2][16];
     unsigned long long e = 0, c = 0;
+#pragma unroll 4
     for (int i = threadIdx.x; i < n; i += 1024) {
         e += wcount[i].x;
         c += wcount[i].y;

@@ -178,11 +178,13 @@ __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g
                                                     const gftorf_frame* __restrict__ frames,
                                                     float4* __restrict__ rec, uint2* __restrict__ rect,
                                                     uint32_t* __restrict__ cnt, uint32_t* __restrict__ dkey,
-                                                    uint32_t* __restrict__ dval, Status* status) {
+                                                    uint32_t* __restrict__ dval, uint32_t* __restrict__ nf_block) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Gauss G = load_gauss(g, k < P.n ? k : 0);
+    // non-finite Gaussians per block (summed by the tile-range scan)
+    const int bad = __syncthreads_count(k < P.n && !G.finite);
+    if (threadIdx.x == 0) nf_block[blockIdx.x] = (uint32_t)bad;
     if (k >= P.n) return;
-    const Gauss G = load_gauss(g, k);
-    if (!G.finite) atomicAdd(&status->nonfinite, 1u);
     const int RS4 = record_float4s(P.nf);
     const double o = 1.0 / (1.0 + exp(-G.logit));
     for (int f = 0; f < P.F; ++f) {
@@ -569,10 +571,10 @@ void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_
     { ProfScope _p("k_preprocess", s);
     if (g.sh_rgb || g.sh_albedo)
         hipLaunchKernelGGL(k_preprocess<true>, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec,
-                           w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.status);
+                           w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.nf_block);
     else
         hipLaunchKernelGGL(k_preprocess<false>, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec,
-                           w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.status);
+                           w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.nf_block);
     }
 }
 
