@@ -48,10 +48,10 @@ SORT_BYTES_PER_KEY_PASS = 16  # read key + value, write key + value (4 B each)
 # by what the same counter reads for a plain device copy of known size
 # (--calibration-copy-mib).  A figure holds only for the kernel source it was
 # measured on: the sha256 of the listed files must match, else traffic is null.
-FETCH_SCALE, WRITE_SCALE = 1048576 / 524322, 1048576 / 1048576   # 1 GiB copy: FETCH 524322 KiB, WRITE 1048576 KiB
+FETCH_SCALE, WRITE_SCALE = 1048576 / 524321, 1048576 / 1048576   # 1 GiB copy: FETCH 524321 KiB, WRITE 1048576 KiB
 TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
-TRAFFIC_SHA256 = "8015e44aa9b5bc58660269fe8d95593ec57e36a50a2422a54ae5a253f6b42ccd"
-TRAFFIC_KIB = {"k_composite_bwd": (52027, 51901), "k_composite_fwd": (6745, 96089)}   # KiB per launch
+TRAFFIC_SHA256 = "ba68fb3b7d35734a477eb9023b94c359c50bf874222101c608c1a0eaffd6dbbe"
+TRAFFIC_KIB = {"k_composite_bwd": (52022, 51901), "k_composite_fwd": (6743, 96090)}   # KiB per launch
 
 
 def parse():
