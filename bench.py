@@ -50,8 +50,8 @@ SORT_BYTES_PER_KEY_PASS = 16  # read key + value, write key + value (4 B each)
 # measured on: the sha256 of the listed files must match, else traffic is null.
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524321, 1048576 / 1048576   # 1 GiB copy: FETCH 524321 KiB, WRITE 1048576 KiB
 TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
-TRAFFIC_SHA256 = "ba68fb3b7d35734a477eb9023b94c359c50bf874222101c608c1a0eaffd6dbbe"
-TRAFFIC_KIB = {"k_composite_bwd": (52022, 51901), "k_composite_fwd": (6743, 96090)}   # KiB per launch
+TRAFFIC_SHA256 = "c95cf043e538bc4a4cb3f78e364ea03df3f983b17522ae13f24c65284a11ba62"
+TRAFFIC_KIB = {"k_composite_bwd": (52024, 51901), "k_composite_fwd": (4817, 96125)}   # KiB per launch
 
 
 def parse():

@@ -138,11 +138,14 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
                                                            const float4* __restrict__ rec,
                                                            gftorf_outputs out, uint2* __restrict__ wcount) {
     constexpr int BS = TW * TH;
-    // list entries staged per batch: most pixels stop after ~100-200 entries
-    // (T < T_min), so short batches waste fewer record loads past the stop
-    constexpr int SB = BS < 64 ? BS : 64;
+    static_assert(BS % 64 == 0, "a tile is a whole number of waves");
+    // Each wave stages 64 list entries at a time into its own LDS slice and
+    // walks them without a workgroup barrier, so a wave whose pixels are all
+    // done (T < T_min) stops while the others continue. Most pixels stop after
+    // ~100-200 entries, so short batches also waste few record loads.
+    constexpr int NWV = BS / 64;
     constexpr int RS4 = record_float4s(NF);
-    __shared__ float4 srec[RS4][SB];
+    __shared__ float4 srec_w[NWV][RS4][64];
 
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     const int f = w / P.n_tiles;
@@ -167,19 +170,25 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
     uint32_t last = 0;
     uint32_t n_eval = 0, n_comp = 0;   // evaluated / composited (pixel, entry) pairs
 
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += SB) {
-        if (__syncthreads_count(!done) == 0) break;
-        const uint32_t j = b0 + tid;
-        if (tid < SB && j < rg.y) {
+    float4 (*srec)[64] = srec_w[tid / 64];
+    const int lane = tid & 63;
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += 64) {
+        if (__ballot(!done) == 0ull) break;
+        const uint32_t j = b0 + lane;
+        // the previous batch's LDS reads of every lane precede these writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (j < rg.y) {
             const float4* r = rec + (size_t)tval[j] * RS4;
             const float4 r1 = r[1];
-            srec[0][tid] = stage_centre(r[0], r1.w, ox, oy, lamin);
-            srec[1][tid] = r1;
+            srec[0][lane] = stage_centre(r[0], r1.w, ox, oy, lamin);
+            srec[1][lane] = r1;
 #pragma unroll
-            for (int q = 2; q < RS4; ++q) srec[q][tid] = r[q];
+            for (int q = 2; q < RS4; ++q) srec[q][lane] = r[q];
         }
-        __syncthreads();
-        const int cnt = __builtin_amdgcn_readfirstlane((int)min((uint32_t)SB, rg.y - b0));
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int cnt = __builtin_amdgcn_readfirstlane((int)min(64u, rg.y - b0));
         // Divergent per pixel (a lane that is done or skips an entry simply
         // idles): measured faster here than branch-free selects with
         // wave-uniform ballot exits.
