@@ -16,6 +16,10 @@ recursion  -- the per-pixel opacity-gradient recursion of the supplement
               (Eqs. S2, S3) plus the background term, in numpy FP64.
 brute      -- per-pixel double loop in plain Python floats for tiny scenes.
 optim      -- L2 loss and Adam (paper §4 hyperparameters) in FP64.
+sh         -- real spherical harmonics up to degree 3 (view-dependent colour).
+tof        -- the time-of-flight epilogue: phasor, d_ToF and amplitude.
+mlp        -- the deformation network of §4: positional encoding, MLP,
+              per-(time, Gaussian) centre offsets and their gradients.
 
 Parity status: every function here is pinned by tests in tests/ against
 closed forms, brute force or finite differences; see each module header.

@@ -23,6 +23,9 @@ builds on (§3, "GS image formation model"; §4 "Implementation details"):
   weights i2 - j and j - i1).  The deformation of the paper offsets positions
   only; here the quaternion stays evaluated at t, which is the same thing as
   interpolating it, because q(t) is affine in t.
+* deformation offsets (§4): with per-frame offsets delta [F][3][N] (the
+  network's output at the frame's time), frame f's centre is the trajectory
+  position plus delta[f].
 * camera space p = R x + t; culled unless p_z > near.
 * EWA projection: Sigma' = J R Rq S^2 Rq^T R^T J^T + dilation I, with the
   pinhole Jacobian J at p.
@@ -50,8 +53,9 @@ def _d(x):
     return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
 
 
-def project(g, frame, cfg):
-    """Binning quantities of every Gaussian for one frame (float64 arrays).
+def project(g, frame, cfg, f=0):
+    """Binning quantities of every Gaussian for frame f of a batch (float64
+    arrays); f selects the frame's row of the optional centre offsets.
 
     Returns a dict with u, v (pixel centre), S00, S01, S11 (2D covariance incl.
     dilation), det, radius, rect (x_lo, x_hi, y_lo, y_hi as int64), count
@@ -78,6 +82,13 @@ def project(g, frame, cfg):
             mx = (x0x + vx * t) + (0.5 * ax) * tt
             my = (x0y + vy * t) + (0.5 * ay) * tt
             mz = (x0z + vz * t) + (0.5 * az) * tt
+        dl = getattr(g, "delta", None)
+        if dl is not None:
+            # the deformation network's offset of this frame (§4), added last
+            ox_, oy_, oz_ = _d(dl[f])
+            mx = mx + ox_
+            my = my + oy_
+            mz = mz + oz_
 
         w0, qx0, qy0, qz0 = _d(g.quat)
         ox, oy, oz = _d(g.omega)
@@ -195,7 +206,7 @@ def sorted_pairs(g, frames, cfg):
     Returns dict(frame, tile, key, index, P, projections)."""
     fr, tl, ky, ix, projs = [], [], [], [], []
     for f, frame in enumerate(frames):
-        p = project(g, frame, cfg)
+        p = project(g, frame, cfg, f)
         projs.append(p)
         t, k, i = frame_pairs(p, cfg)
         fr.append(np.full(t.size, f, np.int64))

@@ -45,11 +45,12 @@ from . import binning, sh
 C_LIGHT = 299_792_458.0
 FIELDS = ("mean", "vel", "acc", "scale", "quat", "omega", "opacity_logit", "rgb", "albedo")
 SH_FIELDS = ("sh_rgb", "sh_albedo")   # optional view-dependent colour / reflectivity (§3)
+OPTIONAL = SH_FIELDS + ("delta",)     # + per-frame centre offsets [F, 3, N] (§4 network)
 
 
 def fields_of(g):
-    """The parameter fields a Gaussian set carries (SH ones only when present)."""
-    return FIELDS + tuple(k for k in SH_FIELDS if getattr(g, k, None) is not None)
+    """The parameter fields a Gaussian set carries (optional ones when present)."""
+    return FIELDS + tuple(k for k in OPTIONAL if getattr(g, k, None) is not None)
 
 
 def _w(x):
@@ -83,7 +84,7 @@ def _quat_rotation(q):
     return r.reshape(-1, 3, 3)
 
 
-def gaussian_quantities(p, frame, cfg):
+def gaussian_quantities(p, frame, cfg, f=0):
     """Differentiable per-Gaussian screen-space quantities for one frame.
 
     p: dict of float64 tensors (FIELDS).  Returns a dict of tensors over N:
@@ -100,6 +101,8 @@ def gaussian_quantities(p, frame, cfg):
               + w2 * (p["mean"] + p["vel"] * thi + 0.5 * p["acc"] * (thi * thi)))
     else:
         mu = p["mean"] + p["vel"] * t + 0.5 * p["acc"] * (t * t)        # [3,N]
+    if "delta" in p:
+        mu = mu + p["delta"][f]        # deformation-network offset of frame f (§4)
     q0 = p["quat"]
     om = p["omega"]
     # (0, omega) (x) q0 = (-omega . v0, w0 omega + omega x v0)
@@ -283,7 +286,7 @@ def render(g, frames, cfg, tiles=None, upstream=None, flag_rel=(1e-5, 1e-4),
     ly, lx = np.meshgrid(np.arange(cfg.tile_h), np.arange(cfg.tile_w), indexing="ij")
     ly, lx = ly.ravel(), lx.ravel()
     for f, frame in enumerate(frames):
-        q_graph = gaussian_quantities(params, frame, cfg)
+        q_graph = gaussian_quantities(params, frame, cfg, f)
         leaves = {k: q_graph[k].detach().clone().requires_grad_(want_grad) for k in QKEYS}
         bgr = torch.tensor(_w(frame.bg_rgb), requires_grad=want_grad)
         bq_np = np.zeros(NQ) if frame.bg_quad is None else _w(frame.bg_quad).reshape(-1)
@@ -293,7 +296,7 @@ def render(g, frames, cfg, tiles=None, upstream=None, flag_rel=(1e-5, 1e-4),
             tile_ids = range(n_tiles)
         else:
             tile_ids = tiles[f]
-            lists = binning.lists_for_tiles(binning.project(g, frame, cfg), cfg, tile_ids)
+            lists = binning.lists_for_tiles(binning.project(g, frame, cfg, f), cfg, tile_ids)
         for tid in tile_ids:
             ty, tx = divmod(int(tid), ntx)
             gx = tx * cfg.tile_w + lx

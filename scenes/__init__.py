@@ -47,10 +47,15 @@ class Gaussians:
     # when present they replace rgb / albedo
     sh_rgb: Optional[np.ndarray] = None
     sh_albedo: Optional[np.ndarray] = None
+    # optional per-frame centre offsets [F, 3, N] (paper §4: the deformation
+    # network's delta x, evaluated at each rendered frame's time); frame f of
+    # a batch adds delta[f] to its centres
+    delta: Optional[np.ndarray] = None
 
     FIELDS = ("mean", "vel", "acc", "scale", "quat", "omega",
               "opacity_logit", "rgb", "albedo")
     SH_FIELDS = ("sh_rgb", "sh_albedo")
+    OPTIONAL = SH_FIELDS + ("delta",)
 
     @property
     def n(self) -> int:
@@ -58,7 +63,7 @@ class Gaussians:
 
     def arrays(self):
         out = {k: getattr(self, k) for k in self.FIELDS}
-        out.update({k: getattr(self, k) for k in self.SH_FIELDS if getattr(self, k) is not None})
+        out.update({k: getattr(self, k) for k in self.OPTIONAL if getattr(self, k) is not None})
         return out
 
     def copy(self) -> "Gaussians":
@@ -353,3 +358,33 @@ def async_quartet_frames(n_quartets: int, period: float, base: Frame, n_phase: i
 def frames_for_times(times, wl: Workload) -> List[Frame]:
     fr0 = wl.frames[0]
     return [dataclasses.replace(fr0, time=float(np.float32(t))) for t in times]
+
+
+def mlp_params(seed: int = 0, n_in: int = 84, width: int = 256, depth: int = 8, n_out: int = 3,
+               last_std: float = 1e-5, bias_std: float = 0.0, gain: float = 1.0) -> np.ndarray:
+    """Flat float32 parameters of the deformation network (paper §4, "MLP"):
+    for every linear layer in order, W [out][in] row-major then b [out].
+    Weights are Xavier-normal, std = gain sqrt(2 / (fan_in + fan_out)), except
+    the last layer's, N(0, last_std^2); biases are 0 (paper) or, for tests
+    that need every term exercised, N(0, bias_std^2).  Seeded PCG64, layer by
+    layer, weights before biases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = [(width, n_in)] + [(width, width)] * (depth - 1) + [(n_out, width)]
+    parts = []
+    for l, (o, i) in enumerate(shapes):
+        std = last_std if l == len(shapes) - 1 else gain * np.sqrt(2.0 / (i + o))
+        parts.append(rng.normal(0.0, std, o * i))
+        parts.append(rng.normal(0.0, bias_std, o) if bias_std > 0 else np.zeros(o))
+    return _f32(np.concatenate(parts))
+
+
+def mlp_rows(n: int, n_times: int, seed: int = 0, extent: float = 4.5, duration: float = 0.25):
+    """Canonical centres [3][n] (float32, uniform in a box of the given extent
+    in front of the camera, z in [0.5, extent]) and n_times time stamps spread
+    over [0, duration] for the deformation network."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x0 = np.stack([rng.uniform(-0.5 * extent, 0.5 * extent, n),
+                   rng.uniform(-0.5 * extent, 0.5 * extent, n),
+                   rng.uniform(0.5, extent, n)])
+    times = np.linspace(0.0, duration, n_times) if n_times > 1 else np.zeros(1)
+    return _f32(x0), _f32(times)

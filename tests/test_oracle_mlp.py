@@ -1,0 +1,169 @@
+"""Pins of the FP64 deformation-network oracle (paper §4, "MLP") against closed
+forms, a pure-Python loop and finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import mlp
+
+
+def test_encoding_closed_forms():
+    # p = 0: sin terms 0, cos terms 1; p = 1/4: sin(pi/4), sin(pi/2), sin(pi), ...;
+    # p = 1/2: sin(pi/2) = 1, cos(pi) = -1, then sin 0 / cos 1 for k >= 2
+    L = 4
+    r2 = math.sqrt(0.5)
+    exp = {0.0: [0.0, 0, 1, 0, 1, 0, 1, 0, 1],
+           0.25: [0.25, r2, r2, 1, 0, 0, -1, 0, 1],
+           0.5: [0.5, 1, 0, 0, -1, 0, 1, 0, 1]}
+    for p, e in exp.items():
+        np.testing.assert_allclose(mlp.encode(np.array([[p]]), L)[0], e, atol=1e-15)
+    # block layout for a 3-vector: feature (block k, coordinate c) at k * 3 + c
+    x = np.array([[0.0, 0.25, 0.5]])
+    enc = mlp.encode(x, L)
+    assert enc.shape == (1, 27)
+    for c, p in enumerate((0.0, 0.25, 0.5)):
+        np.testing.assert_allclose(enc[0, c::3], exp[p], atol=1e-15)
+    assert mlp.n_inputs(10, 10) == 84
+
+
+def test_encoding_derivative_by_differences():
+    rng = np.random.default_rng(0)
+    p = rng.uniform(0, 1, (4, 3))
+    h = 1e-7
+    fd = (mlp.encode(p + h, 5) - mlp.encode(p - h, 5)) / (2 * h)
+    np.testing.assert_allclose(mlp.encode_grad(p, 5), fd, rtol=1e-6, atol=1e-6)
+
+
+def _theta(rng, shapes, nonneg=False, b0=None):
+    parts = []
+    for l, (o, i) in enumerate(shapes):
+        w = rng.normal(0, 1.0 / math.sqrt(i), (o, i))
+        b = rng.normal(0, 0.1, o)
+        if nonneg:
+            w, b = np.abs(w), np.abs(b)
+        if l == 0 and b0 is not None:
+            b = np.full(o, b0)
+        parts += [w.ravel(), b]
+    return np.concatenate(parts)
+
+
+def test_all_active_network_is_affine():
+    # nonnegative weights and biases and a large first bias keep every unit
+    # active, so the network is the affine map x -> M enc + c with
+    # M = W_3 W_2 W_1 W_0 and c = sum_l (W_3 ... W_{l+1}) b_l
+    rng = np.random.default_rng(1)
+    lx, lt, width, depth = 2, 1, 6, 3
+    shapes = mlp.layer_shapes(mlp.n_inputs(lx, lt), width, depth)
+    theta = _theta(rng, shapes, nonneg=True, b0=100.0)
+    W, b = mlp.unpack(theta, shapes)
+    x_in, t_in = rng.uniform(0, 1, (7, 3)), rng.uniform(0, 1, 7)
+    out, cache = mlp.forward(theta, x_in, t_in, lx, lt, width, depth)
+    assert all((h[:, :] > 0).all() for h in cache["h"][1:])
+    M = np.linalg.multi_dot(W[::-1])
+    c = b[-1] + sum(np.linalg.multi_dot(W[l + 1:][::-1] + [b[l][:, None]])[:, 0]
+                    for l in range(depth))
+    enc = np.concatenate([mlp.encode(x_in, lx), mlp.encode(t_in[:, None], lt)], axis=1)
+    np.testing.assert_allclose(out, enc @ M.T + c, rtol=1e-12)
+
+
+def test_tiny_network_equals_python_loops():
+    rng = np.random.default_rng(2)
+    lx, lt, width, depth = 1, 1, 4, 2
+    shapes = mlp.layer_shapes(mlp.n_inputs(lx, lt), width, depth)
+    theta = _theta(rng, shapes)
+    W, b = mlp.unpack(theta, shapes)
+    x_in, t_in = rng.uniform(0, 1, (3, 3)), rng.uniform(0, 1, 3)
+    out, _ = mlp.forward(theta, x_in, t_in, lx, lt, width, depth)
+    for r in range(3):
+        x = [float(v) for v in x_in[r]]
+        t = float(t_in[r])
+        feat = x + [math.sin(math.pi * v) for v in x] + [math.cos(math.pi * v) for v in x]
+        feat += [t, math.sin(math.pi * t), math.cos(math.pi * t)]
+        h = feat
+        for l in range(depth + 1):
+            nxt = []
+            for o in range(len(b[l])):
+                s = float(b[l][o])
+                for i in range(len(h)):
+                    s += float(W[l][o][i]) * h[i]
+                nxt.append(max(0.0, s) if l < depth else s)
+            h = nxt
+        np.testing.assert_allclose(out[r], h, rtol=1e-13, atol=1e-15)
+
+
+def test_backward_central_differences():
+    rng = np.random.default_rng(3)
+    lx, lt, width, depth = 3, 2, 8, 3
+    shapes = mlp.layer_shapes(mlp.n_inputs(lx, lt), width, depth)
+    theta = _theta(rng, shapes)
+    x_in, t_in = rng.uniform(0, 1, (5, 3)), rng.uniform(0, 1, 5)
+    d_out = rng.normal(size=(5, 3))
+    out, cache = mlp.forward(theta, x_in, t_in, lx, lt, width, depth)
+    # smooth regime: every pre-activation well away from the relu kink
+    W, b = mlp.unpack(theta, shapes)
+    z = [cache["h"][l] @ W[l].T + b[l] for l in range(depth)]
+    assert min(np.abs(zz).min() for zz in z) > 1e-4
+    g_theta, g_x, g_t = mlp.backward(theta, cache, d_out)
+
+    def loss(th=theta, xi=x_in, ti=t_in):
+        return float((mlp.forward(th, xi, ti, lx, lt, width, depth)[0] * d_out).sum())
+
+    h = 1e-6
+    idx = np.concatenate([rng.choice(len(theta), 40, replace=False),
+                          np.cumsum([o * i + o for o, i in shapes]) - 1])   # + every last bias
+    for j in idx:
+        e = np.zeros_like(theta)
+        e[j] = h
+        fd = (loss(th=theta + e) - loss(th=theta - e)) / (2 * h)
+        assert g_theta[j] == pytest.approx(fd, rel=1e-6, abs=1e-9), j
+    for r in range(5):
+        for c in range(3):
+            e = np.zeros_like(x_in)
+            e[r, c] = h
+            fd = (loss(xi=x_in + e) - loss(xi=x_in - e)) / (2 * h)
+            assert g_x[r, c] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+        e = np.zeros_like(t_in)
+        e[r] = h
+        fd = (loss(ti=t_in + e) - loss(ti=t_in - e)) / (2 * h)
+        assert g_t[r] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_offsets_rows_and_centre_gradient():
+    rng = np.random.default_rng(4)
+    lx, lt, width, depth = 2, 2, 8, 2
+    shapes = mlp.layer_shapes(mlp.n_inputs(lx, lt), width, depth)
+    theta = _theta(rng, shapes)
+    x0 = rng.uniform(-1, 1, (3, 6))
+    times = np.array([0.0, 0.1, 0.3])
+    sx, st = 0.2, 4.0
+    d = mlp.offsets(theta, x0, times, sx, st, lx, lt, width, depth)
+    assert d.shape == (3, 3, 6)
+    for ti, t in enumerate(times):
+        o, _ = mlp.forward(theta, sx * x0.T, np.full(6, st * t), lx, lt, width, depth)
+        np.testing.assert_allclose(d[ti], o.T, rtol=1e-14)
+    up = rng.normal(size=d.shape)
+    _, g_x0 = mlp.offsets_backward(theta, x0, times, sx, st, up, lx, lt, width, depth)
+    h = 1e-6
+    for c in range(3):
+        for n in range(6):
+            e = np.zeros_like(x0)
+            e[c, n] = h
+            fd = ((mlp.offsets(theta, x0 + e, times, sx, st, lx, lt, width, depth) * up).sum()
+                  - (mlp.offsets(theta, x0 - e, times, sx, st, lx, lt, width, depth) * up).sum()) / (2 * h)
+            assert g_x0[c, n] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_initialisation_statistics():
+    # Xavier-normal hidden weights, N(0, 1e-5^2) last layer, zero biases (§4)
+    theta = scenes.mlp_params(seed=0).astype(np.float64)
+    shapes = mlp.layer_shapes()
+    assert theta.size == mlp.n_params(shapes) == 483_075
+    W, b = mlp.unpack(theta, shapes)
+    for l, (o, i) in enumerate(shapes[:-1]):
+        assert W[l].std() == pytest.approx(math.sqrt(2.0 / (o + i)), rel=0.03)
+        assert abs(W[l].mean()) < 0.01
+        assert not b[l].any()
+    assert W[-1].std() == pytest.approx(1e-5, rel=0.1)
+    assert not b[-1].any()

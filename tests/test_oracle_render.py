@@ -286,3 +286,55 @@ def test_dense_scene_statistics():
     assert out["n_contrib"].max() > 100
     assert np.isfinite(out["rgb"]).all() and np.isfinite(out["quad"]).all()
     assert out["flagged"].mean() < 0.05
+
+
+def test_frame_offsets_are_centre_shifts():
+    # deformation offsets (§4): with grid-exact values (multiples of 2^-10),
+    # x0 + delta is exact in float32, so a frame rendered with an offset equals
+    # the scene with that offset folded into the canonical centres, bit for bit
+    wl = scenes.tiny_scene(12, 24, 16, seed=3)
+    g = wl.gaussians
+    q = 2.0 ** -10
+    g.mean[:] = np.round(g.mean / q) * q
+    rng = np.random.default_rng(0)
+    delta = (rng.integers(-40, 40, (2, 3, g.n)) * q).astype(np.float32)
+    frames = [wl.frames[0], dataclasses.replace(wl.frames[0], time=0.0)]
+    cfg = wl.cfg
+    gd = dataclasses.replace(g, delta=delta)
+    out = render.render(gd, frames, cfg)
+    for f in range(2):
+        shifted = dataclasses.replace(g, mean=(g.mean + delta[f]).astype(np.float32))
+        ref = render.render(shifted, [frames[f]], cfg)
+        for k in ("rgb", "quad", "depth", "T_final", "n_contrib"):
+            np.testing.assert_array_equal(out[k][f], ref[k][0], err_msg=k)
+        a = binning.project(gd, frames[f], cfg, f)
+        b = binning.project(shifted, frames[f], cfg)
+        np.testing.assert_array_equal(a["rect"], b["rect"])
+        np.testing.assert_array_equal(a["key"], b["key"])
+
+
+def test_frame_offset_gradients_sum_to_the_centre_gradient():
+    # every frame's centre is mean + (trajectory terms) + delta[f], so
+    # dL/dmean = sum_f dL/ddelta[f]; plus central differences on delta itself
+    wl = _smooth_scene(6, True)
+    cfg = wl.cfg.strict()
+    rng = np.random.default_rng(2)
+    g64 = scenes.Gaussians(**{k: v.astype(np.float64) for k, v in wl.gaussians.arrays().items()})
+    g64.delta = rng.normal(0, 0.01, (2, 3, g64.n))
+    frames = [dataclasses.replace(wl.frames[0], time=0.1),
+              dataclasses.replace(wl.frames[0], time=0.3, t_lo=0.25, t_hi=0.5)]
+    up = scenes.upstream_grads(2, cfg, seed=4)
+    out = render.render(g64, frames, cfg, upstream=up)
+    np.testing.assert_allclose(out["grads"]["delta"].sum(0), out["grads"]["mean"], rtol=1e-12,
+                               atol=1e-14)
+    for _ in range(4):
+        idx = tuple(rng.integers(0, s) for s in g64.delta.shape)
+        h = 1e-6
+        vals = []
+        for sgn in (1, -1):
+            gp = scenes.Gaussians(**{k: v.copy() for k, v in g64.arrays().items()})
+            gp.delta[idx] += sgn * h
+            vals.append(render.loss_of(render.render(gp, frames, cfg), up))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        an = out["grads"]["delta"][idx]
+        assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-2), (idx, fd, an)
