@@ -66,10 +66,11 @@ def parse():
                     help="seconds of oracle tile work in the CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
-    ap.add_argument("--workload", default="cfg3", choices=("cfg2", "cfg3", "cfg4", "cfg5"),
+    ap.add_argument("--workload", default="cfg3", choices=("cfg2", "cfg3", "cfg4", "cfg5", "mlp"),
                     help="cfg3 (default): the headline batched vs per-frame line; cfg2 / cfg4: the "
                          "same measurement on the static 100k / 1M-Gaussian 16-frame workloads; "
-                         "cfg5: the graph-replayed optimisation step")
+                         "cfg5: the graph-replayed optimisation step; mlp: the deformation "
+                         "network's forward + backward over (Gaussian, time) rows")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after timing, one device-to-device copy of this many MiB (for counter runs)")
     return ap.parse_args()
@@ -149,6 +150,99 @@ def traffic_bytes(name):
     return int(round((fetch * FETCH_SCALE + write * WRITE_SCALE) * 1024))
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix peak
+
+
+def mlp_flop_per_row(n_in=84, width=256, depth=8, n_out=3):
+    """Multiply-adds x 2 of one row through every linear layer (unpadded)."""
+    return 2 * (n_in * width + (depth - 1) * width * width + width * n_out)
+
+
+def bench_mlp(args):
+    """Deformation network (paper §4): forward with saved activations, then the
+    backward to every parameter and to the canonical centres, for args.n
+    Gaussians at args.frames times.  Prints one JSON line (rows/s)."""
+    import torch
+
+    import scenes
+    from paper_2505_05356_amd import deform, profile
+
+    n, T = args.n, args.frames
+    theta = torch.from_numpy(scenes.mlp_params(seed=0)).cuda()
+    x0_np, times = scenes.mlp_rows(n, T, seed=1)
+    x0 = torch.from_numpy(x0_np).cuda()
+    times = [float(t) for t in times]
+    net = deform.DeformNet(n, T, time_scale=4.0)
+    delta = torch.empty((T, 3, n), device="cuda")
+    up = torch.randn((T, 3, n), device="cuda")
+    d_params = torch.empty(net.n_params, device="cuda")
+
+    def step():
+        net.forward(theta, x0, times, out=delta)
+        net.backward(theta, x0, times, up, d_params=d_params)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s_ev.record()
+    for _ in range(args.steps):
+        step()
+    e_ev.record()
+    torch.cuda.synchronize()
+    ms = s_ev.elapsed_time(e_ev) / args.steps
+    with profile.KernelTimer(max_launches=16 * args.steps + 16) as kt:
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+    kern = {k: v[1] / max(v[0], 1) for k, v in kt.totals.items()}
+    rows = n * T
+    flop = rows * mlp_flop_per_row()
+    per_kernel = {}
+    for k in ("k_mlp_fwd", "k_mlp_bwd", "k_mlp_dw"):
+        if k in kern:
+            tf = flop / (kern[k] / 1e3) / 1e12
+            per_kernel[k] = dict(avg_ms=round(kern[k], 4), tflops=round(tf, 1),
+                                 frac=round(tf / MFMA_BF16_PEAK_TFLOPS, 4))
+    dominant = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"])
+    a = per_kernel[dominant]["tflops"]
+    roof = dict(bound="mfma", achieved=a, peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=round(a / MFMA_BF16_PEAK_TFLOPS, 4), traffic=None, kernel=dominant,
+                avg_ms=per_kernel[dominant]["avg_ms"],
+                work=f"{flop:.4g} FLOP per launch = {rows} rows x {mlp_flop_per_row()} (bf16 products)")
+    print("# kernels: " + ", ".join(f"{k} {v * 1e3:.1f}us" for k, v in sorted(kern.items(), key=lambda kv: -kv[1])),
+          file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import mlp as omlp
+        R = 512
+        rng = np.random.default_rng(0)
+        xs, ts = rng.uniform(-0.5, 0.5, (R, 3)), rng.uniform(0, 1, R)
+        th = theta.cpu().numpy()
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < min(args.cpu_budget, 10.0) or reps == 0:
+            _, cache = omlp.forward(th, xs, ts)
+            omlp.backward(th, cache, rng.normal(size=(R, 3)))
+            reps += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(reps * R / dt, 1), "unit": "rows/s", "cores": torch.get_num_threads(),
+               "kind": "oracle", "sample": f"{reps} x {R} rows forward + backward (FP64 numpy)"}
+    line = {
+        "metric": "deformation MLP fwd+bwd rows/s (200k Gaussians x 8 times)",
+        "value": round(rows / (ms / 1e3), 1), "unit": "rows/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (seeded centres, paper initialisation; no dataset)",
+        "config": {"workload": f"deform-mlp-{n // 1000}k-x{T}-8x256-pe10", "rows": rows,
+                   "flop_per_step": 3 * flop, "step_tflops": round(3 * flop / (ms / 1e3) / 1e12, 1)},
+        "roofline": roof, "kernels": per_kernel,
+        "kernels_ms": {k: round(v, 4) for k, v in kern.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -164,6 +258,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "cfg5":
         return bench_train_step(args)
+    if args.workload == "mlp":
+        return bench_mlp(args)
     if args.workload == "cfg2":
         wl = scenes.cfg2()
     elif args.workload == "cfg4":

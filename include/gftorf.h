@@ -74,6 +74,12 @@ typedef struct gftorf_gaussians {
     int32_t reserved;           /* must be 0                                       */
     const float* sh_rgb;        /* [K][3][n] colour coefficients, or NULL          */
     const float* sh_albedo;     /* [K][n] reflectivity coefficients, or NULL       */
+    /* Per-frame centre offsets [n_frames][3][n] (paper §4: the deformation
+     * network moves every Gaussian from its canonical centre by delta x_k(t);
+     * gftorf_mlp_fwd produces them at the frames' times), or NULL.  Frame f
+     * adds delta[f] to the trajectory position, as the last binary64 step of
+     * the centre before projection. */
+    const float* delta;
 } gftorf_gaussians;
 
 /* Gradient outputs, same layout as gftorf_gaussians.  Each non-NULL array is
@@ -90,6 +96,8 @@ typedef struct gftorf_gaussians_grad {
     float* albedo;
     float* sh_rgb;              /* [K][3][n], used with gftorf_gaussians.sh_rgb    */
     float* sh_albedo;           /* [K][n], used with gftorf_gaussians.sh_albedo    */
+    float* delta;               /* [n_frames][3][n]: dL/d(frame f's centre); valid
+                                   with or without input offsets; 0 for culled items */
 } gftorf_gaussians_grad;
 
 /* One rendered frame; an ARRAY of these lives in DEVICE memory, so a graph
@@ -295,6 +303,58 @@ typedef struct gftorf_profile_entry {
 int gftorf_profile_begin(int32_t max_launches);
 int gftorf_profile_collect(void);
 int gftorf_profile_end(gftorf_profile_entry* out, int32_t max_entries, int32_t* n_entries);
+
+/* ---- Deformation network (paper §4, "MLP") ---------------------------------
+ * delta x = MLP(enc_Lx(s_x x0), enc_Lt(s_t t)) for every (time, Gaussian) row,
+ * rows in time-major order r = i_t n + k.
+ *   enc_L(p): the blocks p, sin(pi p), cos(pi p), sin(2 pi p), cos(2 pi p), ...,
+ *             sin(2^(L-1) pi p), cos(2^(L-1) pi p) of the coordinates of p;
+ *   network:  h_0 = the encoding (3 (1 + 2 L_x) + 1 + 2 L_t <= 96 features),
+ *             h_{l+1} = relu(W_l h_l + b_l) for l = 0 .. 7 (width 256),
+ *             delta x = W_8 h_8 + b_8;
+ *   params:   float32, for l = 0 .. 8 in order W_l [out][in] row-major, then
+ *             b_l [out] (gftorf_mlp_param_count floats).
+ * The products run on the matrix cores with bfloat16 operands (weights,
+ * encodings, activations and back-propagated gradients rounded to nearest
+ * even) and float32 accumulation; biases, outputs and gradients are float32.
+ * Every call enqueues on `stream`, allocates nothing and does not
+ * synchronise. */
+typedef struct gftorf_mlp_config {
+    int32_t n_freq_x;   /* L_x (paper: 10)                                        */
+    int32_t n_freq_t;   /* L_t (paper: 10)                                        */
+    int32_t width;      /* hidden units per layer: must be 256                    */
+    int32_t depth;      /* hidden layers: must be 8                               */
+    float pos_scale;    /* s_x (paper: 1 / unambiguous range = 2 f / c)           */
+    float time_scale;   /* s_t                                                    */
+} gftorf_mlp_config;
+
+#define GFTORF_MLP_MAX_TIMES 64
+
+/* Floats of the parameter vector of `cfg` (0 if cfg is invalid). */
+int64_t gftorf_mlp_param_count(const gftorf_mlp_config* cfg);
+
+/* Workspace bytes for n Gaussians at n_times times; with `training` it also
+ * holds the activations and gradients gftorf_mlp_bwd reads (about
+ * 9.2 KB per row).  0 if the arguments are invalid. */
+size_t gftorf_mlp_workspace_size(const gftorf_mlp_config* cfg, int64_t n, int32_t n_times,
+                                 int32_t training);
+
+/* delta [n_times][3][n] (overwritten) for canonical centres x0 [3][n] at the
+ * times `times` (host, n_times <= GFTORF_MLP_MAX_TIMES).  With `save` the
+ * activations stay in ws for gftorf_mlp_bwd (ws sized with training = 1). */
+int gftorf_mlp_fwd(const gftorf_mlp_config* cfg, const float* params, const float* x0, int64_t n,
+                   const float* times, int32_t n_times, float* delta, int32_t save,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of the last gftorf_mlp_fwd with save = 1 on the same ws and
+ * arguments: given d_delta [n_times][3][n], overwrites d_params (the
+ * parameter layout) and, if not NULL, d_x0 [3][n] (the canonical centres
+ * reach the network through s_x x0; summed over the times).  Deterministic:
+ * no atomics; the weight gradients are summed over fixed row chunks in a
+ * fixed order. */
+int gftorf_mlp_bwd(const gftorf_mlp_config* cfg, const float* params, const float* x0, int64_t n,
+                   const float* times, int32_t n_times, const float* d_delta, float* d_params,
+                   float* d_x0, void* ws, size_t ws_bytes, void* stream);
 
 const char* gftorf_strerror(int code);
 const char* gftorf_last_error(void);

@@ -29,6 +29,16 @@ design notes):
 Parameter vector layout (the C ABI uses the same): for l = 0..8 in order,
 W_l row-major [out][in], then b_l [out].
 
+Discrete decisions.  Which hidden units are active (z > 0) is an integer
+result of floating point.  A unit whose z is within rounding of 0 can be
+decided differently by two correct implementations, and its gradient then
+changes by a whole term.  forward(..., decide="bf16") takes those decisions
+in the precision of the matrix-core products (bfloat16 operands rounded to
+nearest even, wide accumulation), from a shadow evaluation; the values and
+gradients are still the FP64 definition with those decisions held fixed
+(h = [z_decided > 0] z), as the rasterizer oracle holds its visit decisions
+fixed.  decide="exact" takes them from the FP64 values themselves.
+
 Pins: tests/test_oracle_mlp.py (encoding closed forms at p = 0, 1/4, 1/2;
 an all-active network equals its affine closed form, a product of the weight
 matrices; a tiny network equals a pure-Python triple loop; central finite
@@ -94,16 +104,42 @@ def network_input(x_in, t_in, lx: int = 10, lt: int = 10):
                           axis=1)
 
 
-def forward(theta, x_in, t_in, lx: int = 10, lt: int = 10, width: int = 256, depth: int = 8):
-    """Offsets [R, 3] of R rows; also returns the per-layer values needed by
-    backward (the hidden activations h_0..h_depth)."""
+def round_bf16(x):
+    """Nearest bfloat16 (ties to even) of the float32 rounding of x, as float64."""
+    b = np.asarray(x, np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _decisions(W, b, x_in, t_in, lx, lt, depth):
+    """Active-unit masks of the hidden layers evaluated as the products are:
+    scaled inputs rounded to float32, bfloat16 operands."""
+    x32 = np.asarray(x_in, np.float64).astype(np.float32).astype(np.float64)
+    t32 = np.asarray(t_in, np.float64).astype(np.float32).astype(np.float64)
+    masks, h = [], round_bf16(network_input(x32, t32, lx, lt))
+    for l in range(depth):
+        z = h @ round_bf16(W[l]).T + b[l]
+        masks.append(z > 0.0)
+        h = round_bf16(np.maximum(z, 0.0))
+    return masks
+
+
+def forward(theta, x_in, t_in, lx: int = 10, lt: int = 10, width: int = 256, depth: int = 8,
+            decide: str = "exact"):
+    """Offsets [R, 3] of R rows; also returns what backward needs (the hidden
+    activations h_0..h_depth and the active-unit masks)."""
     shapes = layer_shapes(n_inputs(lx, lt), width, depth)
     W, b = unpack(theta, shapes)
     h = [network_input(x_in, t_in, lx, lt)]
+    masks = _decisions(W, b, x_in, t_in, lx, lt, depth) if decide == "bf16" else None
+    if decide not in ("exact", "bf16"):
+        raise ValueError(decide)
     for l in range(depth):
-        h.append(np.maximum(h[-1] @ W[l].T + b[l], 0.0))
+        z = h[-1] @ W[l].T + b[l]
+        m = masks[l] if masks is not None else z > 0.0
+        h.append(np.where(m, z, 0.0))
     out = h[-1] @ W[depth].T + b[depth]
-    return out, {"h": h, "x_in": np.asarray(x_in, np.float64),
+    return out, {"h": h, "masks": masks, "x_in": np.asarray(x_in, np.float64),
                  "t_in": np.asarray(t_in, np.float64), "lx": lx, "lt": lt,
                  "width": width, "depth": depth}
 
@@ -121,22 +157,28 @@ def backward(theta, cache, d_out):
         dW[l] = g.T @ h[l]
         db[l] = g.sum(axis=0)
         gh = g @ W[l]                                  # d/d h_l
-        if l > 0:
-            g = gh * (h[l] > 0.0)                      # relu' of layer l-1's output
+        if l > 0:                                      # relu' of layer l-1's output
+            active = cache["masks"][l - 1] if cache["masks"] is not None else h[l] > 0.0
+            g = gh * active
     d_enc = gh                                         # d/d h_0, the encoding
     nx = 3 * (1 + 2 * lx)
     gx = d_enc[:, :nx] * encode_grad(cache["x_in"], lx)
     gt = d_enc[:, nx:] * encode_grad(cache["t_in"][:, None], lt)
     d_x = gx.reshape(len(gx), 1 + 2 * lx, 3).sum(axis=1)
     d_t = gt.sum(axis=1)
+    # magnitude of the terms d_x sums (it cancels: the encoding's derivatives
+    # reach 2^(L-1) pi), the scale of its rounding errors in any precision
+    cache["d_x_terms"] = np.abs(gx).reshape(len(gx), 1 + 2 * lx, 3).sum(axis=1)
     flat = np.concatenate([np.concatenate([w.ravel(), c]) for w, c in zip(dW, db)])
     return flat, d_x, d_t
 
 
 def _rows(x0, times, s_x, s_t):
-    """Rows (t, n) in time-major order: x_in [T N, 3], t_in [T N]."""
+    """Rows (t, n) in time-major order: x_in [T N, 3], t_in [T N].  The scales
+    are float32 values (as the device receives them), widened exactly."""
     x0 = np.asarray(x0, dtype=np.float64)              # [3][N]
     times = np.asarray(times, dtype=np.float64)
+    s_x, s_t = float(np.float32(s_x)), float(np.float32(s_t))
     T, N = len(times), x0.shape[1]
     x_in = np.tile((s_x * x0).T, (T, 1))
     t_in = np.repeat(s_t * times, N)
@@ -144,21 +186,24 @@ def _rows(x0, times, s_x, s_t):
 
 
 def offsets(theta, x0, times, s_x, s_t, lx: int = 10, lt: int = 10, width: int = 256,
-            depth: int = 8):
+            depth: int = 8, decide: str = "exact"):
     """delta [T][3][N]: the network at every (time, Gaussian) row."""
     x_in, t_in, T, N = _rows(x0, times, s_x, s_t)
-    out, _ = forward(theta, x_in, t_in, lx, lt, width, depth)
+    out, _ = forward(theta, x_in, t_in, lx, lt, width, depth, decide)
     return out.reshape(T, N, 3).transpose(0, 2, 1)
 
 
 def offsets_backward(theta, x0, times, s_x, s_t, d_delta, lx: int = 10, lt: int = 10,
-                     width: int = 256, depth: int = 8):
+                     width: int = 256, depth: int = 8, decide: str = "exact", terms: bool = False):
     """Gradients of sum(d_delta * offsets(...)): the flat parameter gradient and
     d x0 [3][N] (the canonical centre reaches the network through s_x x0, summed
-    over the T times)."""
+    over the T times); with `terms` also the summed magnitudes of d x0's terms."""
     x_in, t_in, T, N = _rows(x0, times, s_x, s_t)
-    _, cache = forward(theta, x_in, t_in, lx, lt, width, depth)
+    _, cache = forward(theta, x_in, t_in, lx, lt, width, depth, decide)
     d_out = np.asarray(d_delta, np.float64).transpose(0, 2, 1).reshape(T * N, 3)
     flat, d_x, _ = backward(theta, cache, d_out)
+    s_x = float(np.float32(s_x))
     d_x0 = s_x * d_x.reshape(T, N, 3).sum(axis=0).T
+    if terms:
+        return flat, d_x0, s_x * cache["d_x_terms"].reshape(T, N, 3).sum(axis=0).T
     return flat, d_x0

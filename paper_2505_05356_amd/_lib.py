@@ -28,13 +28,23 @@ OK, EINVAL, ENOWS, EHIP, EOVERFLOW = 0, -1, -2, -3, -4
 SH_FIELDS = ("sh_rgb", "sh_albedo")
 
 
+# per-frame centre offsets [F][3][n] (the deformation network's output)
+OFFSET_FIELDS = ("delta",)
+
+
 class GaussiansC(ctypes.Structure):
     _fields_ = ([("n", c_int64)] + [(k, c_void_p) for k in FIELDS] +
-                [("sh_degree", c_int32), ("reserved", c_int32)] + [(k, c_void_p) for k in SH_FIELDS])
+                [("sh_degree", c_int32), ("reserved", c_int32)] +
+                [(k, c_void_p) for k in SH_FIELDS + OFFSET_FIELDS])
 
 
 class GaussiansGradC(ctypes.Structure):
-    _fields_ = [(k, c_void_p) for k in FIELDS + SH_FIELDS]
+    _fields_ = [(k, c_void_p) for k in FIELDS + SH_FIELDS + OFFSET_FIELDS]
+
+
+class MlpConfigC(ctypes.Structure):
+    _fields_ = [("n_freq_x", c_int32), ("n_freq_t", c_int32), ("width", c_int32),
+                ("depth", c_int32), ("pos_scale", c_float), ("time_scale", c_float)]
 
 
 class ConfigC(ctypes.Structure):
@@ -91,6 +101,12 @@ _SIGS = {
     "gftorf_profile_begin": (c_int32, [c_int32]),
     "gftorf_profile_collect": (c_int32, []),
     "gftorf_profile_end": (c_int32, [POINTER(ProfileEntryC), c_int32, POINTER(c_int32)]),
+    "gftorf_mlp_param_count": (c_int64, [POINTER(MlpConfigC)]),
+    "gftorf_mlp_workspace_size": (c_size_t, [POINTER(MlpConfigC), c_int64, c_int32, c_int32]),
+    "gftorf_mlp_fwd": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, POINTER(c_float),
+                                 c_int32, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
+    "gftorf_mlp_bwd": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, POINTER(c_float),
+                                 c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "gftorf_strerror": (c_char_p, [c_int32]),
     "gftorf_last_error": (c_char_p, []),
     "gftorf_version": (c_int32, []),

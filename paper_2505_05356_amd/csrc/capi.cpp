@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "common.h"
+#include "mlp.h"
 
 namespace {
 
@@ -342,6 +343,73 @@ int gftorf_select_frames(gftorf_frame* frames, int32_t n_batch, const gftorf_fra
                               static_cast<hipStream_t>(stream));
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_select_frames");
+}
+
+// ---- deformation network -------------------------------------------------
+
+namespace {
+bool mlp_layout(const gftorf_mlp_config* cfg, int64_t n, int32_t n_times, bool training,
+                gft::mlp::Layout* L) {
+    return cfg && gft::mlp::make_layout(cfg->n_freq_x, cfg->n_freq_t, cfg->width, cfg->depth, n,
+                                        n_times, training, L);
+}
+
+int mlp_call(const gftorf_mlp_config* cfg, const float* params, const float* x0, int64_t n,
+             const float* times, int32_t n_times, void* ws, size_t ws_bytes, bool training,
+             gft::mlp::Layout* L, gft::mlp::Call* c) {
+    if (!mlp_layout(cfg, n, n_times, training, L))
+        return fail(GFTORF_EINVAL, "unsupported network: width must be 256, depth 8, "
+                                   "3 (1 + 2 L_x) + 1 + 2 L_t <= 96, 1 <= n_times <= 64");
+    if (!params || !x0 || !times || !ws) return fail(GFTORF_EINVAL, "NULL pointer");
+    if (!std::isfinite(cfg->pos_scale) || !std::isfinite(cfg->time_scale))
+        return fail(GFTORF_EINVAL, "non-finite input scale");
+    if (ws_bytes < L->bytes) return fail(GFTORF_ENOWS, "workspace too small for the network");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GFTORF_EINVAL, "workspace must be 256-byte aligned");
+    c->params = params;
+    c->x0 = x0;
+    c->sx = cfg->pos_scale;
+    c->st = cfg->time_scale;
+    for (int t = 0; t < gft::mlp::kMaxTimes; ++t) c->times[t] = t < n_times ? times[t] : 0.f;
+    c->ws = static_cast<char*>(ws);
+    return GFTORF_OK;
+}
+}  // namespace
+
+int64_t gftorf_mlp_param_count(const gftorf_mlp_config* cfg) {
+    gft::mlp::Layout L;
+    return mlp_layout(cfg, 1, 1, false, &L) ? L.n_params : 0;
+}
+
+size_t gftorf_mlp_workspace_size(const gftorf_mlp_config* cfg, int64_t n, int32_t n_times,
+                                 int32_t training) {
+    gft::mlp::Layout L;
+    return mlp_layout(cfg, n, n_times, training != 0, &L) ? L.bytes : 0;
+}
+
+int gftorf_mlp_fwd(const gftorf_mlp_config* cfg, const float* params, const float* x0, int64_t n,
+                   const float* times, int32_t n_times, float* delta, int32_t save, void* ws,
+                   size_t ws_bytes, void* stream) {
+    gft::mlp::Layout L;
+    gft::mlp::Call c;
+    const int rc = mlp_call(cfg, params, x0, n, times, n_times, ws, ws_bytes, save != 0, &L, &c);
+    if (rc != GFTORF_OK) return rc;
+    if (!delta) return fail(GFTORF_EINVAL, "NULL pointer");
+    (void)hipGetLastError();
+    const hipError_t e = gft::mlp::launch_fwd(L, c, delta, save != 0, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_mlp_fwd");
+}
+
+int gftorf_mlp_bwd(const gftorf_mlp_config* cfg, const float* params, const float* x0, int64_t n,
+                   const float* times, int32_t n_times, const float* d_delta, float* d_params,
+                   float* d_x0, void* ws, size_t ws_bytes, void* stream) {
+    gft::mlp::Layout L;
+    gft::mlp::Call c;
+    const int rc = mlp_call(cfg, params, x0, n, times, n_times, ws, ws_bytes, true, &L, &c);
+    if (rc != GFTORF_OK) return rc;
+    if (!d_delta || !d_params) return fail(GFTORF_EINVAL, "NULL pointer");
+    (void)hipGetLastError();
+    const hipError_t e = gft::mlp::launch_bwd(L, c, d_delta, d_params, d_x0, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_mlp_bwd");
 }
 
 int gftorf_fill_f32(float* p, float value, int64_t n, void* stream) {

@@ -1,0 +1,616 @@
+// Deformation network of paper §4 ("MLP") on the gfx950 matrix cores.
+//
+// delta x = W_8 h_8 + b_8,  h_{l+1} = relu(W_l h_l + b_l),  h_0 = the positional
+// encoding of (s_x x0, s_t t), for every (time, Gaussian) row.
+//
+// Kernels
+//   k_mlp_pack    float32 parameters -> bfloat16 weight copies: W_l as
+//                 [out][in] (forward) and W_l^T as [in][out] (backward), both
+//                 zero-padded so every product is whole 16 x 16 x 32 tiles.
+//   k_mlp_fwd     one workgroup of 4 waves per 128 rows: the encoding and
+//                 every layer's activations stay in LDS (128 x 256 bf16),
+//                 weights stream from L2; wave w computes output columns
+//                 64w .. 64w+63 of all 128 rows with v_mfma_f32_16x16x32_bf16.
+//                 Training mode also stores h_0 .. h_8 for the backward.
+//   k_mlp_bwd     the same tiling backwards: gz_8 = dL/d delta, then per layer
+//                 g_l = gz_l W_l, gz_{l-1} = g_l * [h_l > 0]; stores every gz_l
+//                 and, from g_0, the gradient of the scaled centre input.
+//   k_mlp_dw      dW_l = sum_rows gz_l h_l^T, db_l = sum_rows gz_l: rows are the
+//                 contraction, split into fixed chunks, one partial per chunk.
+//   k_mlp_reduce  sums the chunk partials in chunk order into the parameter
+//                 layout; k_mlp_dx0 sums the centre gradient over the times.
+//
+// Saved activations and gradients use a row-blocked layout [rows/8][feat][8]:
+// the eight rows of one feature are one 16-byte fragment of the weight-gradient
+// product, and the row-parallel kernels write four of them per lane.
+#include "mlp.h"
+
+namespace gft {
+namespace mlp {
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// LDS row stride in bf16: the 16-byte pad puts the 16 rows of one fragment
+// read in 16 distinct 4-bank groups.
+constexpr int kLDX = kWidth + 8;
+
+struct Args {
+    const float* x0;
+    int64_t n, rows;
+    int lx, lt;
+    float sx, st;
+    float times[kMaxTimes];
+    const bf16* wf[kLayers];
+    const bf16* wt[kLayers];
+    const float* bias[kLayers];
+    bf16* H[kLayers];
+    bf16* GZ[kLayers];
+};
+
+// D += A B on one 16 x 16 tile, K = 32.  Lane l supplies A[l % 16][8 (l / 16) + e]
+// and B[8 (l / 16) + e][l % 16], e = 0..7; it receives D[4 (l / 16) + j][l % 16].
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Positional encoding: feature f of the network input.  Returns the input
+// coordinate it reads (0..2 = x, 3 = t, -1 = padding) and its block: 0 = the
+// coordinate itself, 2k + 1 = sin(2^k pi p), 2k + 2 = cos(2^k pi p).
+__device__ __forceinline__ int feat_src(int f, int lx, int lt, int& blk) {
+    const int nx = 3 * (1 + 2 * lx);
+    if (f < nx) {
+        blk = f / 3;
+        return f - 3 * blk;
+    }
+    f -= nx;
+    blk = f;
+    return f < 1 + 2 * lt ? 3 : -1;
+}
+
+__device__ __forceinline__ float enc(float p, int blk) {
+    if (blk == 0) return p;
+    const float a = ldexpf(p, (blk - 1) >> 1);   // 2^k p, exact
+    return ((blk - 1) & 1) ? cospif(a) : sinpif(a);
+}
+
+__device__ __forceinline__ float enc_d(float p, int blk) {   // d enc / d p
+    if (blk == 0) return 1.0f;
+    const int k = (blk - 1) >> 1;
+    const float a = ldexpf(p, k), w = ldexpf(3.14159265358979f, k);
+    return ((blk - 1) & 1) ? -w * sinpif(a) : w * cospif(a);
+}
+
+__device__ __forceinline__ float pick4(const float (&v)[4], int c) {
+    return c == 0 ? v[0] : c == 1 ? v[1] : c == 2 ? v[2] : v[3];
+}
+
+// scaled inputs of row r (zeros for padding rows)
+__device__ __forceinline__ void row_inputs(const Args& a, int64_t r, float (&xin)[4]) {
+    xin[0] = xin[1] = xin[2] = xin[3] = 0.f;
+    if (r >= a.rows) return;
+    const int t = (int)(r / a.n);
+    const int64_t k = r - (int64_t)t * a.n;
+    for (int c = 0; c < 3; ++c) xin[c] = a.sx * a.x0[c * a.n + k];
+    xin[3] = a.st * a.times[t];
+}
+
+// acc[r][c] += X[16 r + .][.] * B[col0 + 16 c + .][.] over K: X in LDS
+// (row-major, stride kLDX), B in global memory as [cols][K].
+template <int K>
+__device__ __forceinline__ void gemm_128x64(const bf16* X, const bf16* __restrict__ B, int col0,
+                                            f32x4 (&acc)[8][4], int lane) {
+    const int lr = lane & 15, lk = (lane >> 4) * 8;
+    const bf16* bp = B + (size_t)(col0 + lr) * K + lk;
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 b[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = *(const bf16x8*)(bp + (size_t)16 * c * K + k0);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const bf16x8 x = *(const bf16x8*)(X + (16 * r + lr) * kLDX + lk + k0);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = mfma(x, b[c], acc[r][c]);
+        }
+    }
+}
+
+__device__ __forceinline__ void zero(f32x4 (&acc)[8][4]) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+// offset (in bf16) of rows row .. row+3 (row % 4 == 0) of feature col in a
+// row-blocked [rows/8][F][8] array
+template <int F>
+__device__ __forceinline__ size_t blk_off(int64_t row, int col) {
+    return ((size_t)(row >> 3) * F + col) * 8 + (size_t)(row & 7);
+}
+
+// copy the first F columns of the 128 LDS rows to a row-blocked array
+template <int F>
+__device__ __forceinline__ void save_block(const bf16* X, bf16* __restrict__ dst, int64_t r0,
+                                           int tid) {
+    for (int p = tid; p < 16 * F; p += 256) {
+        const int rb = p / F, f = p - rb * F;
+        bf16x8 v;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = X[(8 * rb + m) * kLDX + f];
+        *(bf16x8*)(dst + ((size_t)(r0 / 8 + rb) * F + f) * 8) = v;
+    }
+}
+
+template <bool SAVE>
+__global__ void __launch_bounds__(256) k_mlp_fwd(Args a, float* __restrict__ delta) {
+    __shared__ __attribute__((aligned(16))) bf16 X[kRows * kLDX];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * kRows;
+    {   // h_0: two threads per row, 48 features each
+        const int rr = tid >> 1, half = tid & 1;
+        float xin[4];
+        row_inputs(a, r0 + rr, xin);
+        for (int f = 48 * half; f < 48 * half + 48; ++f) {
+            int blk;
+            const int c = feat_src(f, a.lx, a.lt, blk);
+            X[rr * kLDX + f] = (bf16)(c < 0 ? 0.f : enc(pick4(xin, c), blk));
+        }
+    }
+    __syncthreads();
+    if (SAVE) save_block<kK0>(X, a.H[0], r0, tid);
+
+    f32x4 acc[8][4];
+    const int col0 = 64 * wv;
+    for (int l = 0; l < kDepth; ++l) {
+        zero(acc);
+        if (l == 0)
+            gemm_128x64<kK0>(X, a.wf[0], col0, acc, lane);
+        else
+            gemm_128x64<kWidth>(X, a.wf[l], col0, acc, lane);
+        __syncthreads();   // every wave has read this layer's input
+        bf16* H = a.H[l + 1];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int col = col0 + 16 * c + lr;
+            const float bb = a.bias[l][col];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                bf16x4 v;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    v[j] = (bf16)fmaxf(acc[r][c][j] + bb, 0.f);
+                    X[(16 * r + 4 * lg + j) * kLDX + col] = v[j];
+                }
+                if (SAVE) *(bf16x4*)(H + blk_off<kWidth>(r0 + 16 * r + 4 * lg, col)) = v;
+            }
+        }
+        __syncthreads();
+    }
+    // head: 128 rows x 16 (3 real) outputs; wave w takes rows 32w .. 32w+31
+    f32x4 o2[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    const bf16* bp = a.wf[kDepth] + (size_t)lr * kWidth + 8 * lg;
+#pragma unroll 4
+    for (int k0 = 0; k0 < kWidth; k0 += 32) {
+        const bf16x8 b = *(const bf16x8*)(bp + k0);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const bf16x8 x = *(const bf16x8*)(X + (32 * wv + 16 * r + lr) * kLDX + 8 * lg + k0);
+            o2[r] = mfma(x, b, o2[r]);
+        }
+    }
+    if (lr < 3) {
+        const float bb = a.bias[kDepth][lr];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = r0 + 32 * wv + 16 * r + 4 * lg + j;
+                if (row < a.rows) {
+                    const int t = (int)(row / a.n);
+                    const int64_t k = row - (int64_t)t * a.n;
+                    delta[((int64_t)t * 3 + lr) * a.n + k] = o2[r][j] + bb;
+                }
+            }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mlp_bwd(Args a, const float* __restrict__ d_delta,
+                                                 float* __restrict__ dxr) {
+    __shared__ __attribute__((aligned(16))) bf16 X[kRows * kLDX];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int64_t r0 = (int64_t)blockIdx.x * kRows;
+    {   // gz_8 = dL/d delta of the block's rows, padded to kHeadK columns
+        const int rr = tid >> 1, half = tid & 1;
+        const int64_t r = r0 + rr;
+        float g[4] = {0.f, 0.f, 0.f, 0.f};
+        if (r < a.rows) {
+            const int t = (int)(r / a.n);
+            const int64_t k = r - (int64_t)t * a.n;
+            for (int c = 0; c < 3; ++c) g[c] = d_delta[((int64_t)t * 3 + c) * a.n + k];
+        }
+        for (int c = 16 * half; c < 16 * half + 16; ++c)
+            X[rr * kLDX + c] = (bf16)(c < 3 ? pick4(g, c) : 0.f);
+    }
+    __syncthreads();
+    save_block<kOutPad>(X, a.GZ[kDepth], r0, tid);
+
+    f32x4 acc[8][4];
+    const int col0 = 64 * wv;
+    zero(acc);
+    gemm_128x64<kHeadK>(X, a.wt[kDepth], col0, acc, lane);   // g_8 = gz_8 W_8
+    for (int l = kDepth - 1; l >= 0; --l) {
+        __syncthreads();
+        // gz_l = g_{l+1} * [h_{l+1} > 0]
+        const bf16* H = a.H[l + 1];
+        bf16* GZ = a.GZ[l];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int col = col0 + 16 * c + lr;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const size_t o = blk_off<kWidth>(r0 + 16 * r + 4 * lg, col);
+                const bf16x4 h = *(const bf16x4*)(H + o);
+                bf16x4 v;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    v[j] = (bf16)((float)h[j] > 0.f ? acc[r][c][j] : 0.f);
+                    X[(16 * r + 4 * lg + j) * kLDX + col] = v[j];
+                }
+                *(bf16x4*)(GZ + o) = v;
+            }
+        }
+        __syncthreads();
+        if (l > 0) {
+            zero(acc);
+            gemm_128x64<kWidth>(X, a.wt[l], col0, acc, lane);   // g_l = gz_l W_l
+        }
+    }
+    // g_0 = gz_0 W_0 -> [128][96]: wave w takes rows 32w .. 32w+31, all 6 column tiles
+    f32x4 g0[2][6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) g0[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    {
+        const bf16* bp = a.wt[0] + (size_t)lr * kWidth + 8 * lg;
+#pragma unroll 2
+        for (int k0 = 0; k0 < kWidth; k0 += 32) {
+            bf16x8 b[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) b[c] = *(const bf16x8*)(bp + (size_t)16 * c * kWidth + k0);
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const bf16x8 x = *(const bf16x8*)(X + (32 * wv + 16 * r + lr) * kLDX + 8 * lg + k0);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) g0[r][c] = mfma(x, b[c], g0[r][c]);
+            }
+        }
+    }
+    __syncthreads();
+    constexpr int kLDF = kK0 + 4;   // float stride of g_0 in LDS
+    float* XF = reinterpret_cast<float*>(X);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) XF[(32 * wv + 16 * r + 4 * lg + j) * kLDF + 16 * c + lr] = g0[r][c][j];
+    __syncthreads();
+    {   // d(scaled centre) = sum over the x features of g_0 * d enc / d p; two threads per row
+        const int rr = tid >> 1, half = tid & 1;
+        const int64_t r = r0 + rr;
+        float xin[4];
+        row_inputs(a, r, xin);
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        for (int f = 48 * half; f < 48 * half + 48; ++f) {
+            int blk;
+            const int c = feat_src(f, a.lx, a.lt, blk);
+            if (c < 0 || c > 2) continue;
+            const float v = XF[rr * kLDF + f] * enc_d(pick4(xin, c), blk);
+            s0 += c == 0 ? v : 0.f;
+            s1 += c == 1 ? v : 0.f;
+            s2 += c == 2 ? v : 0.f;
+        }
+        s0 += __shfl_xor(s0, 1, 64);
+        s1 += __shfl_xor(s1, 1, 64);
+        s2 += __shfl_xor(s2, 1, 64);
+        if (half == 0 && r < a.rows) {
+            dxr[r * 3 + 0] = a.sx * s0;
+            dxr[r * 3 + 1] = a.sx * s1;
+            dxr[r * 3 + 2] = a.sx * s2;
+        }
+    }
+}
+
+// dW_l [NO][NI] and db_l [NO] of one row chunk.  8 waves: OG groups of output
+// rows times IG groups of input columns; each wave keeps MT x NT tiles.
+struct DwArgs {
+    const bf16* GZ[kLayers];
+    const bf16* H[kLayers];
+    int64_t part_off[kLayers];
+    int64_t part_stride, rows_pad, rows_per_chunk;
+    float* part;
+};
+
+template <int NO, int NI, int OG, int IG>
+__global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
+    constexpr int MT = NO / 16 / OG, NT = NI / 16 / IG;
+    static_assert(OG * IG == 8 && MT * 16 * OG == NO && NT * 16 * IG == NI, "tiling");
+    const int l = l0 + blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int o0 = (wv / IG) * MT * 16, i0 = (wv % IG) * NT * 16;
+    const bf16* __restrict__ GZ = d.GZ[l];
+    const bf16* __restrict__ H = d.H[l];
+    const int64_t rs = (int64_t)blockIdx.x * d.rows_per_chunk;
+    const int64_t re = min(rs + d.rows_per_chunk, d.rows_pad);   // both multiples of 32
+    f32x4 acc[MT][NT];
+    float sb[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        sb[m] = 0.f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll 2
+    for (int64_t kb = rs / 8; kb < re / 8; kb += 4) {
+        const int64_t rb = kb + lg;
+        bf16x8 av[MT], bv[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) av[m] = *(const bf16x8*)(GZ + ((size_t)rb * NO + o0 + 16 * m + lr) * 8);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bv[t] = *(const bf16x8*)(H + ((size_t)rb * NI + i0 + 16 * t + lr) * 8);
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(av[m], bv[t], acc[m][t]);
+        if (i0 == 0)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) sb[m] += (float)av[m][e];
+    }
+    float* P = d.part + (int64_t)blockIdx.x * d.part_stride + d.part_off[l];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                P[(size_t)(o0 + 16 * m + 4 * lg + j) * NI + i0 + 16 * t + lr] = acc[m][t][j];
+    if (i0 == 0) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            float s = sb[m];
+            s += __shfl_xor(s, 16, 64);
+            s += __shfl_xor(s, 32, 64);
+            if (lg == 0) P[(size_t)NO * NI + o0 + 16 * m + lr] = s;
+        }
+    }
+}
+
+struct RedArgs {
+    int64_t off_w[kLayers], off_b[kLayers], part_off[kLayers];
+    int out[kLayers], in[kLayers];
+    int64_t n_params, part_stride;
+    int n_chunks;
+};
+
+// parameter gradient = sum of the chunk partials, chunk 0 first
+__global__ void __launch_bounds__(256) k_mlp_reduce(RedArgs r, const float* __restrict__ part,
+                                                    float* __restrict__ d_params) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= r.n_params) return;
+    int l = 0;
+    while (l + 1 < kLayers && p >= r.off_w[l + 1]) ++l;
+    int64_t src;
+    if (p < r.off_b[l]) {
+        const int64_t e = p - r.off_w[l];
+        const int o = (int)(e / r.in[l]), i = (int)(e - (int64_t)o * r.in[l]);
+        src = r.part_off[l] + (int64_t)o * pad_in(l) + i;
+    } else {
+        src = r.part_off[l] + (int64_t)pad_out(l) * pad_in(l) + (p - r.off_b[l]);
+    }
+    float s = 0.f;
+    for (int c = 0; c < r.n_chunks; ++c) s += part[(int64_t)c * r.part_stride + src];
+    d_params[p] = s;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_dx0(const float* __restrict__ dxr, int64_t n, int T,
+                                                 float* __restrict__ d_x0) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int t = 0; t < T; ++t) {
+        const float* g = dxr + ((int64_t)t * n + k) * 3;
+        s0 += g[0];
+        s1 += g[1];
+        s2 += g[2];
+    }
+    d_x0[k] = s0;
+    d_x0[n + k] = s1;
+    d_x0[2 * n + k] = s2;
+}
+
+struct PackArgs {
+    int64_t off_w[kLayers];
+    int out[kLayers], in[kLayers];
+    bf16* wf[kLayers];
+    bf16* wt[kLayers];
+};
+
+__global__ void __launch_bounds__(256) k_mlp_pack(PackArgs p, const float* __restrict__ params) {
+    const int l = blockIdx.y;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int out = p.out[l], in = p.in[l];
+    const float* W = params + p.off_w[l];
+    const int NO = pad_out(l), NI = pad_in(l), KO = pad_k(l);
+    if (e < NO * NI) {
+        const int o = e / NI, i = e - o * NI;
+        p.wf[l][e] = (bf16)((o < out && i < in) ? W[(int64_t)o * in + i] : 0.f);
+    }
+    if (e < NI * KO) {
+        const int i = e / KO, o = e - i * KO;
+        p.wt[l][e] = (bf16)((o < out && i < in) ? W[(int64_t)o * in + i] : 0.f);
+    }
+}
+
+Args make_args(const Layout& L, const Call& c) {
+    Args a;
+    a.x0 = c.x0;
+    a.n = L.n;
+    a.rows = L.rows;
+    a.lx = L.lx;
+    a.lt = L.lt;
+    a.sx = c.sx;
+    a.st = c.st;
+    for (int t = 0; t < kMaxTimes; ++t) a.times[t] = t < L.n_times ? c.times[t] : 0.f;
+    for (int l = 0; l < kLayers; ++l) {
+        a.wf[l] = reinterpret_cast<const bf16*>(c.ws + L.wf[l]);
+        a.wt[l] = reinterpret_cast<const bf16*>(c.ws + L.wt[l]);
+        a.bias[l] = c.params + L.off_b[l];
+        a.H[l] = L.training ? reinterpret_cast<bf16*>(c.ws + L.H[l]) : nullptr;
+        a.GZ[l] = L.training ? reinterpret_cast<bf16*>(c.ws + L.GZ[l]) : nullptr;
+    }
+    return a;
+}
+
+}  // namespace
+
+bool make_layout(int lx, int lt, int width, int depth, int64_t n, int n_times, bool training,
+                 Layout* L) {
+    if (width != kWidth || depth != kDepth || lx < 0 || lt < 0 || n < 1 || n_times < 1 ||
+        n_times > kMaxTimes)
+        return false;
+    const int n_in = 3 * (1 + 2 * lx) + 1 + 2 * lt;
+    if (n_in > kK0 || n > (int64_t(1) << 40) / n_times) return false;
+    L->lx = lx;
+    L->lt = lt;
+    L->n_in = n_in;
+    int64_t off = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        L->out[l] = l == kDepth ? 3 : kWidth;
+        L->in[l] = l == 0 ? n_in : kWidth;
+        L->off_w[l] = off;
+        off += (int64_t)L->out[l] * L->in[l];
+        L->off_b[l] = off;
+        off += L->out[l];
+    }
+    L->n_params = off;
+    L->n = n;
+    L->n_times = n_times;
+    L->rows = n * n_times;
+    L->rows_pad = (L->rows + kRows - 1) / kRows * kRows;
+    int64_t rpc = (L->rows_pad + kMaxChunks - 1) / kMaxChunks;
+    rpc = (rpc + 31) / 32 * 32;
+    L->rows_per_chunk = rpc;
+    L->n_chunks = (int)((L->rows_pad + rpc - 1) / rpc);
+    int64_t po = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        L->part_off[l] = po;
+        po += (int64_t)pad_out(l) * pad_in(l) + pad_out(l);
+    }
+    L->part_stride = po;
+    size_t b = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = b;
+        b += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    for (int l = 0; l < kLayers; ++l) {
+        L->wf[l] = take((size_t)pad_out(l) * pad_in(l) * 2);
+        L->wt[l] = take((size_t)pad_in(l) * pad_k(l) * 2);
+    }
+    for (int l = 0; l < kLayers; ++l) L->H[l] = L->GZ[l] = 0;
+    L->dxr = L->part = 0;
+    if (training) {
+        for (int l = 0; l < kLayers; ++l) L->H[l] = take((size_t)L->rows_pad * pad_in(l) * 2);
+        for (int l = 0; l < kLayers; ++l) L->GZ[l] = take((size_t)L->rows_pad * pad_out(l) * 2);
+        L->dxr = take((size_t)L->rows_pad * 3 * 4);
+        L->part = take((size_t)L->n_chunks * L->part_stride * 4);
+    }
+    L->bytes = b;
+    L->training = training;
+    return true;
+}
+
+hipError_t launch_fwd(const Layout& L, const Call& c, float* delta, bool save, hipStream_t s) {
+    PackArgs p;
+    for (int l = 0; l < kLayers; ++l) {
+        p.off_w[l] = L.off_w[l];
+        p.out[l] = L.out[l];
+        p.in[l] = L.in[l];
+        p.wf[l] = reinterpret_cast<bf16*>(c.ws + L.wf[l]);
+        p.wt[l] = reinterpret_cast<bf16*>(c.ws + L.wt[l]);
+    }
+    {
+        ProfScope _p("k_mlp_pack", s);
+        hipLaunchKernelGGL(k_mlp_pack, dim3(kWidth * kWidth / 256, kLayers), dim3(256), 0, s, p, c.params);
+    }
+    const Args a = make_args(L, c);
+    const unsigned blocks = (unsigned)(L.rows_pad / kRows);
+    ProfScope _f("k_mlp_fwd", s);
+    if (save)
+        hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(blocks), dim3(256), 0, s, a, delta);
+    else
+        hipLaunchKernelGGL(k_mlp_fwd<false>, dim3(blocks), dim3(256), 0, s, a, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd(const Layout& L, const Call& c, const float* d_delta, float* d_params,
+                      float* d_x0, hipStream_t s) {
+    const Args a = make_args(L, c);
+    float* dxr = reinterpret_cast<float*>(c.ws + L.dxr);
+    {
+        ProfScope _b("k_mlp_bwd", s);
+        hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)(L.rows_pad / kRows)), dim3(256), 0, s, a,
+                           d_delta, dxr);
+    }
+    DwArgs d;
+    for (int l = 0; l < kLayers; ++l) {
+        d.GZ[l] = a.GZ[l];
+        d.H[l] = a.H[l];
+        d.part_off[l] = L.part_off[l];
+    }
+    d.part_stride = L.part_stride;
+    d.rows_pad = L.rows_pad;
+    d.rows_per_chunk = L.rows_per_chunk;
+    d.part = reinterpret_cast<float*>(c.ws + L.part);
+    {
+        ProfScope _w("k_mlp_dw", s);
+        const unsigned nc = (unsigned)L.n_chunks;
+        hipLaunchKernelGGL((k_mlp_dw<kWidth, kWidth, 4, 2>), dim3(nc, kDepth - 1), dim3(512), 0, s, d, 1);
+        hipLaunchKernelGGL((k_mlp_dw<kWidth, kK0, 4, 2>), dim3(nc, 1), dim3(512), 0, s, d, 0);
+        hipLaunchKernelGGL((k_mlp_dw<kOutPad, kWidth, 1, 8>), dim3(nc, 1), dim3(512), 0, s, d, kDepth);
+    }
+    RedArgs r;
+    for (int l = 0; l < kLayers; ++l) {
+        r.off_w[l] = L.off_w[l];
+        r.off_b[l] = L.off_b[l];
+        r.part_off[l] = L.part_off[l];
+        r.out[l] = L.out[l];
+        r.in[l] = L.in[l];
+    }
+    r.n_params = L.n_params;
+    r.part_stride = L.part_stride;
+    r.n_chunks = L.n_chunks;
+    {
+        ProfScope _r("k_mlp_reduce", s);
+        hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)((L.n_params + 255) / 256)), dim3(256), 0, s, r,
+                           d.part, d_params);
+        if (d_x0)
+            hipLaunchKernelGGL(k_mlp_dx0, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, s, dxr, L.n,
+                               L.n_times, d_x0);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mlp
+}  // namespace gft

@@ -65,7 +65,8 @@ struct Binned {
 
 // The pinned binary64 operation sequence.  Every statement is one IEEE
 // operation evaluated left to right; contraction is off in this scope.
-__device__ Binned bin(const Gauss& G, const gftorf_frame& fr, const Params& P) {
+__device__ Binned bin(const Gauss& G, const gftorf_frame& fr, const Params& P,
+                      const double* dl) {
 #pragma clang fp contract(off)
     Binned b;
     const double t = (double)fr.time;
@@ -84,6 +85,8 @@ __device__ Binned bin(const Gauss& G, const gftorf_frame& fr, const Params& P) {
     } else {
         for (int c = 0; c < 3; ++c) b.m[c] = (G.x0[c] + G.v[c] * t) + (0.5 * G.a[c]) * tt;
     }
+    if (dl)   // the deformation network's offset of this frame (§4), added last
+        for (int c = 0; c < 3; ++c) b.m[c] = b.m[c] + dl[c];
 
     const double w0 = G.q0[0], qx0 = G.q0[1], qy0 = G.q0[2], qz0 = G.q0[3];
     const double ox = G.om[0], oy = G.om[1], oz = G.om[2];
@@ -189,7 +192,10 @@ __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g
     const double o = 1.0 / (1.0 + exp(-G.logit));
     for (int f = 0; f < P.F; ++f) {
         const gftorf_frame& fr = frames[f];
-        const Binned b = bin(G, fr, P);
+        double dl[3];
+        if (g.delta)
+            for (int c = 0; c < 3; ++c) dl[c] = (double)g.delta[((int64_t)f * 3 + c) * P.n + k];
+        const Binned b = bin(G, fr, P, g.delta ? dl : nullptr);
         const int64_t item = (int64_t)f * P.n + k;
         uint32_t c = 0;
         if (b.valid) c = (uint32_t)((b.xhi - b.xlo + 1) * (b.yhi - b.ylo + 1));
@@ -332,7 +338,11 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
         const float L2E = 1.4426950408889634f;
         for (int f = f0; f < P.F; f += GS) {
             const int64_t item = (int64_t)f * n + k;
-            if (cnt[item] == 0) continue;
+            if (cnt[item] == 0) {
+                if (out.delta)
+                    for (int c = 0; c < 3; ++c) out.delta[((int64_t)f * 3 + c) * n + k] = 0.f;
+                continue;
+            }
             const gftorf_frame& fr = frames[f];
             const float* gr = grec + item * GF;
             const float4 r1 = rec[item * RS4 + 1];
@@ -351,6 +361,8 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
             }
             float m[3];
             for (int c = 0; c < 3; ++c) m[c] = cx0 * x0[c] + cv * vv[c] + ca * aa[c];
+            if (g.delta)
+                for (int c = 0; c < 3; ++c) m[c] += g.delta[((int64_t)f * 3 + c) * n + k];
             const float ht = 0.5f * t;
             const float qw = q0[0] - ht * (om[0] * q0[1] + om[1] * q0[2] + om[2] * q0[3]);
             const float qx = q0[1] + ht * (q0[0] * om[0] + om[1] * q0[3] - om[2] * q0[2]);
@@ -523,7 +535,9 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
             acc[17] += ht * (-gq[0] * q0[2] + gq[1] * q0[3] + gq[2] * q0[0] - gq[3] * q0[1]);
             acc[18] += ht * (-gq[0] * q0[3] - gq[1] * q0[2] + gq[2] * q0[1] + gq[3] * q0[0]);
 
-            // trajectory
+            // per-frame centre (the deformation offset's gradient) and trajectory
+            if (out.delta)
+                for (int c = 0; c < 3; ++c) out.delta[((int64_t)f * 3 + c) * n + k] = gm[c];
             for (int c = 0; c < 3; ++c) {
                 acc[c] += gm[c] * cx0;
                 acc[3 + c] += gm[c] * cv;

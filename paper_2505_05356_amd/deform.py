@@ -1,0 +1,95 @@
+"""Deformation network of paper §4 ("MLP"): argument marshalling for the
+gftorf_mlp_* entry points of libgftorf.so.
+
+The network maps the positional encoding of (s_x x0, s_t t) through 8 ReLU
+layers of 256 units to a centre offset delta x for every (time, Gaussian)
+row; every product runs in the library's gfx950 kernels (bfloat16 operands on
+the matrix cores, float32 accumulation).  The offsets plug into the
+rasterizer as the per-frame `delta` field of the Gaussians.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+
+SPEED_OF_LIGHT = 299_792_458.0
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(None)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _f32dev(t: torch.Tensor, name: str, shape=None):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class DeformNet:
+    """Workspace and configuration for n Gaussians at up to n_times times.
+
+    pos_scale defaults to the inverse unambiguous range 2 f / c of the
+    modulation frequency `freq_hz` (paper §4: network inputs rescaled to
+    mostly [0, 1]); time_scale maps the sequence's times to [0, 1]."""
+
+    def __init__(self, n: int, n_times: int, freq_hz: float = 30e6, time_scale: float = 1.0,
+                 pos_scale: Optional[float] = None, lx: int = 10, lt: int = 10,
+                 training: bool = True, device="cuda"):
+        lib = _lib.load()
+        sx = pos_scale if pos_scale is not None else 2.0 * freq_hz / SPEED_OF_LIGHT
+        self.cfg = _lib.MlpConfigC(lx, lt, 256, 8, sx, time_scale)
+        self.n, self.n_times, self.training = n, n_times, training
+        self.n_params = int(lib.gftorf_mlp_param_count(ctypes.byref(self.cfg)))
+        nbytes = int(lib.gftorf_mlp_workspace_size(ctypes.byref(self.cfg), n, n_times, int(training)))
+        if self.n_params <= 0 or nbytes <= 0:
+            raise ValueError("unsupported network configuration")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.nbytes = nbytes
+
+    def _times(self, times: Sequence[float]):
+        if not 1 <= len(times) <= self.n_times:
+            raise ValueError(f"between 1 and {self.n_times} times")
+        return (ctypes.c_float * len(times))(*[float(t) for t in times])
+
+    def forward(self, params: torch.Tensor, x0: torch.Tensor, times: Sequence[float],
+                save: bool = True, out: Optional[torch.Tensor] = None, stream=None):
+        """delta [T, 3, n] for canonical centres x0 [3, n] at the T times."""
+        lib = _lib.load()
+        T = len(times)
+        _f32dev(params, "params", (self.n_params,))
+        _f32dev(x0, "x0", (3, self.n))
+        if save and not self.training:
+            raise ValueError("save needs a training workspace")
+        if out is None:
+            out = torch.empty((T, 3, self.n), device=x0.device)
+        _f32dev(out, "out", (T, 3, self.n))
+        _lib.check(lib.gftorf_mlp_fwd(ctypes.byref(self.cfg), _ptr(params), _ptr(x0), self.n,
+                                      self._times(times), T, _ptr(out), int(save),
+                                      _ptr(self.ws), self.nbytes, _stream(stream)))
+        return out
+
+    def backward(self, params: torch.Tensor, x0: torch.Tensor, times: Sequence[float],
+                 d_delta: torch.Tensor, d_params: Optional[torch.Tensor] = None,
+                 want_x0: bool = True, stream=None):
+        """(d_params [P], d_x0 [3, n] or None) for the upstream d_delta [T, 3, n];
+        needs the forward with save=True on the same arguments just before."""
+        lib = _lib.load()
+        T = len(times)
+        _f32dev(d_delta, "d_delta", (T, 3, self.n))
+        if d_params is None:
+            d_params = torch.empty(self.n_params, device=x0.device)
+        d_x0 = torch.empty((3, self.n), device=x0.device) if want_x0 else None
+        _lib.check(lib.gftorf_mlp_bwd(ctypes.byref(self.cfg), _ptr(params), _ptr(x0), self.n,
+                                      self._times(times), T, _ptr(d_delta), _ptr(d_params),
+                                      _ptr(d_x0), _ptr(self.ws), self.nbytes, _stream(stream)))
+        return d_params, d_x0

@@ -23,9 +23,9 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FIELDS, FRAME_FLOATS, MAX_QUAD, SH_FIELDS
+from ._lib import FIELDS, FRAME_FLOATS, MAX_QUAD, OFFSET_FIELDS, SH_FIELDS
 
-ALL_FIELDS = FIELDS + SH_FIELDS
+ALL_FIELDS = FIELDS + SH_FIELDS + OFFSET_FIELDS
 _SH_DEGREE = {1: 0, 4: 1, 9: 2, 16: 3}
 
 
@@ -100,6 +100,12 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _check_offsets(params, n_frames):
+    d = params.get("delta")
+    if d is not None and d.shape[0] != n_frames:
+        raise ValueError(f"delta has {d.shape[0]} frames, the call renders {n_frames}")
+
+
 def gaussians_struct(params: Dict[str, torch.Tensor]) -> _lib.GaussiansC:
     g = _lib.GaussiansC()
     n = params["opacity_logit"].shape[0]
@@ -121,6 +127,12 @@ def gaussians_struct(params: Dict[str, torch.Tensor]) -> _lib.GaussiansC:
         degree = _SH_DEGREE[K]
         setattr(g, k, t.data_ptr())
     g.sh_degree = degree or 0
+    d = params.get("delta")   # per-frame centre offsets [F, 3, n]
+    if d is not None:
+        if not (d.is_cuda and d.dtype == torch.float32 and d.is_contiguous()) or \
+                d.dim() != 3 or d.shape[1:] != (3, n):
+            raise ValueError("delta must be a contiguous float32 CUDA tensor [F, 3, n]")
+        g.delta = d.data_ptr()
     for k in FIELDS:
         t = params.get(k)
         replaced = (k == "rgb" and params.get("sh_rgb") is not None) or \
@@ -212,6 +224,7 @@ def forward(params, frames_dev, cfg, ws: Workspace, out=None, stream=None, check
     if out is None:
         out = alloc_outputs(F, cfg, frames_dev.device)
     g = gaussians_struct(params)
+    _check_offsets(params, frames_dev.shape[0])
     o = outputs_struct(out)
     while True:
         _lib.check(lib.gftorf_render_fwd(ctypes.byref(g), _ptr(frames_dev), F,
@@ -239,6 +252,7 @@ def backward(params, frames_dev, cfg, ws: Workspace, saved, d_rgb=None, d_quad=N
         setattr(gg, k, grads[k].data_ptr() if grads.get(k) is not None else None)
     d_bg = torch.empty((F, 3 + n_quad(cfg)), device=frames_dev.device) if want_bg else None
     g = gaussians_struct(params)
+    _check_offsets(params, frames_dev.shape[0])
     o = outputs_struct(saved)
     for t in (d_rgb, d_quad, d_depth):
         if t is not None and not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
@@ -303,7 +317,7 @@ def to_device_params(g, device="cuda", static=None) -> Dict[str, torch.Tensor]:
             out[k] = None
         else:
             out[k] = torch.from_numpy(np.ascontiguousarray(a)).to(device)
-    for k in SH_FIELDS:   # only when the Gaussians carry them
+    for k in SH_FIELDS + OFFSET_FIELDS:   # only when the Gaussians carry them
         a = getattr(g, k, None)
         if a is not None:
             out[k] = torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)

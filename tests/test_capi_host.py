@@ -45,8 +45,9 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_sizes_match_header(lib):
     from paper_2505_05356_amd import _lib
     assert ctypes.sizeof(_lib.ConfigC) == 112
-    assert ctypes.sizeof(_lib.GaussiansC) == 8 * 13
-    assert ctypes.sizeof(_lib.GaussiansGradC) == 8 * 11
+    assert ctypes.sizeof(_lib.GaussiansC) == 8 * 14
+    assert ctypes.sizeof(_lib.GaussiansGradC) == 8 * 12
+    assert ctypes.sizeof(_lib.MlpConfigC) == 24
     assert _lib.FRAME_FLOATS * 4 == 160
 
 
@@ -102,3 +103,29 @@ def test_error_codes_before_device_work(lib):
                                ctypes.byref(out), ctypes.c_void_p(4096), 16, None)
     assert rc == _lib.EINVAL and b"sh_degree" in lib.gftorf_last_error()
     assert lib.gftorf_version() == 1
+
+
+def test_mlp_sizes_and_argument_checks(lib):
+    # the deformation network's parameter count (paper §4: 8 x 256, L_x = L_t = 10)
+    # and workspace sizing; invalid shapes are refused without touching a GPU
+    from paper_2505_05356_amd import _lib
+    good = _lib.MlpConfigC(10, 10, 256, 8, 0.2, 4.0)
+    assert lib.gftorf_mlp_param_count(ctypes.byref(good)) == 483_075
+    small = lib.gftorf_mlp_workspace_size(ctypes.byref(good), 1000, 2, 0)
+    train = lib.gftorf_mlp_workspace_size(ctypes.byref(good), 1000, 2, 1)
+    assert 0 < small < train
+    # 9.2 KB of saved activations and gradients per row when training
+    assert train - small >= 2000 * (96 + 8 * 256 + 8 * 256 + 16) * 2
+    for bad in (_lib.MlpConfigC(10, 10, 128, 8, 0.2, 4.0), _lib.MlpConfigC(10, 10, 256, 6, 0.2, 4.0),
+                _lib.MlpConfigC(14, 10, 256, 8, 0.2, 4.0), _lib.MlpConfigC(-1, 10, 256, 8, 0.2, 4.0)):
+        assert lib.gftorf_mlp_param_count(ctypes.byref(bad)) == 0
+        assert lib.gftorf_mlp_workspace_size(ctypes.byref(bad), 1000, 2, 1) == 0
+    assert lib.gftorf_mlp_workspace_size(ctypes.byref(good), 1000, 65, 1) == 0
+    assert lib.gftorf_mlp_workspace_size(ctypes.byref(good), 0, 2, 1) == 0
+    times = (ctypes.c_float * 2)(0.0, 0.1)
+    rc = lib.gftorf_mlp_fwd(ctypes.byref(good), None, None, 1000, times, 2, None, 1,
+                            None, 0, None)
+    assert rc == _lib.EINVAL
+    rc = lib.gftorf_mlp_fwd(ctypes.byref(good), ctypes.c_void_p(256), ctypes.c_void_p(256), 1000,
+                            times, 2, ctypes.c_void_p(256), 1, ctypes.c_void_p(256), small, None)
+    assert rc == _lib.ENOWS

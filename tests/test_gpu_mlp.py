@@ -1,0 +1,165 @@
+"""Deformation network (paper §4, "MLP") on the GPU against the FP64 oracle,
+and the rasterizer with per-frame centre offsets (needs an MI355X).
+
+Tolerance.  The network's products take bfloat16 operands (8 significant
+bits, unit roundoff u = 2^-8) with float32 accumulation.  Each of the 9
+layers rounds its weights and its input activations once, a relative
+perturbation of at most 2u per product with random signs, so a layer adds
+about sqrt(2) u / sqrt(3) ~ 3e-3 relative RMS error and the 9 layers about
+sqrt(9) times that, ~1e-2 relative RMS, forward and backward alike.  The
+check is the gradient criterion used for the rasterizer: per tensor,
+relative L2 <= 2e-2 and elementwise |gpu - ref| <= 2e-2 (|ref| + max |ref|).
+The oracle takes the ReLU decisions in the products' precision
+(decide="bf16"): a unit within rounding of its kink may be decided either way,
+and then its whole gradient term differs.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from oracle import binning, mlp as omlp, render as oref
+from paper_2505_05356_amd import deform
+from tests.gpu_common import assert_grads_close, assert_images_close, gpu_lists, mask_upstream, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+MLP_RTOL = 2e-2
+SX, ST = 2 * 30e6 / 299_792_458.0, 4.0
+
+
+def _net_inputs(n, times, seed, last_std=0.05, bias_std=0.1):
+    theta = scenes.mlp_params(seed=seed, last_std=last_std, bias_std=bias_std)
+    x0, _ = scenes.mlp_rows(n, 1, seed=seed + 100)
+    return theta, x0, np.asarray(times, np.float32)
+
+
+def _per_layer(flat, name, ref):
+    W, b = omlp.unpack(flat, omlp.layer_shapes())
+    Wr, br = omlp.unpack(ref, omlp.layer_shapes())
+    for l in range(len(W)):
+        assert_grads_close(W[l], Wr[l], f"{name}/W{l}", rtol=MLP_RTOL)
+        assert_grads_close(b[l], br[l], f"{name}/b{l}", rtol=MLP_RTOL)
+
+
+@pytest.mark.parametrize("n,times", [(300, [0.0, 0.1, 0.25]), (1, [0.05]), (128, [0.0, 0.2])])
+def test_mlp_forward_backward_match_oracle(n, times):
+    # 900 rows (7 full blocks and a ragged tail), a single row, and exactly one block
+    theta, x0, times = _net_inputs(n, times, seed=1)
+    net = deform.DeformNet(n, len(times), pos_scale=SX, time_scale=ST)
+    p, x = torch.from_numpy(theta).cuda(), torch.from_numpy(x0).cuda()
+    delta = net.forward(p, x, times)
+    ref = omlp.offsets(theta, x0, times, SX, ST, decide="bf16")
+    torch.cuda.synchronize()
+    assert_grads_close(delta.cpu().numpy(), ref, "delta", rtol=MLP_RTOL)
+    rng = np.random.default_rng(2)
+    up = rng.normal(size=ref.shape).astype(np.float32)
+    d_params, d_x0 = net.backward(p, x, times, torch.from_numpy(up).cuda())
+    g_ref, gx_ref, gx_terms = omlp.offsets_backward(theta, x0, times, SX, ST, up, decide="bf16",
+                                                    terms=True)
+    torch.cuda.synchronize()
+    _per_layer(d_params.cpu().numpy(), "d_params", g_ref)
+    _centre_close(d_x0.cpu().numpy(), gx_ref, gx_terms, "d_x0")
+
+
+def _centre_close(got, ref, terms, name):
+    # d x0 sums terms as large as 2^9 pi times the encoding's gradient that
+    # mostly cancel, so each element's rounding error scales with the sum of
+    # the terms' magnitudes: relative L2 <= 2e-2 and elementwise
+    # |gpu - ref| <= 2e-2 (|ref| + sum |terms|).  A unit within float32
+    # accumulation error of its kink (|z| ~ 1e-6 of its terms) can still be
+    # decided the other way by the kernel; each element of d x0 sums only
+    # n_times rows, so such a row shows in its Gaussian's element: at most 1%
+    # of the elements may exceed the elementwise bound.
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel <= MLP_RTOL, f"{name}: relative L2 error {rel:.3e}"
+    bad = np.abs(got - ref) > MLP_RTOL * (np.abs(ref) + terms)
+    assert bad.mean() <= 0.01, f"{name}: {int(bad.sum())} of {bad.size} elements beyond tolerance"
+
+
+def test_mlp_paper_initialisation():
+    # Xavier-normal layers, last layer N(0, 1e-5^2), zero biases (§4): tiny offsets
+    theta, x0, times = _net_inputs(500, [0.0, 0.125], seed=3, last_std=1e-5, bias_std=0.0)
+    net = deform.DeformNet(500, 2, pos_scale=SX, time_scale=ST)
+    delta = net.forward(torch.from_numpy(theta).cuda(), torch.from_numpy(x0).cuda(), times, save=False)
+    ref = omlp.offsets(theta, x0, times, SX, ST, decide="bf16")
+    torch.cuda.synchronize()
+    assert np.abs(ref).max() < 1e-3
+    assert_grads_close(delta.cpu().numpy(), ref, "delta@init", rtol=MLP_RTOL)
+
+
+def test_mlp_backward_deterministic_and_repeatable():
+    theta, x0, times = _net_inputs(700, [0.0, 0.1], seed=4)
+    net = deform.DeformNet(700, 2, pos_scale=SX, time_scale=ST)
+    p, x = torch.from_numpy(theta).cuda(), torch.from_numpy(x0).cuda()
+    up = torch.randn((2, 3, 700), device="cuda")
+    outs = []
+    for _ in range(2):
+        net.forward(p, x, times)
+        outs.append([t.cpu().numpy() for t in net.backward(p, x, times, up)])
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_mlp_full_size_sampled_rows():
+    # The benchmark's launch shape: 200k Gaussians at 8 times (1.6M rows).
+    # Forward: 64 sampled rows against the oracle, row by row.  Backward: the
+    # gradient is linear in d_delta, so an upstream gradient that is non-zero
+    # on the sampled rows only has the oracle's gradient of those rows alone.
+    n, T = 200_000, 8
+    theta = scenes.mlp_params(seed=5, last_std=0.05, bias_std=0.1)
+    x0, times = scenes.mlp_rows(n, T, seed=6)
+    net = deform.DeformNet(n, T, pos_scale=SX, time_scale=ST)
+    p, x = torch.from_numpy(theta).cuda(), torch.from_numpy(x0).cuda()
+    delta = net.forward(p, x, times)
+    rng = np.random.default_rng(7)
+    rows = np.sort(rng.choice(n * T, 64, replace=False))
+    rows[-1] = n * T - 1                                   # the last row of the last block
+    t_idx, k_idx = rows // n, rows % n
+    got = delta.cpu().numpy()[t_idx, :, k_idx]
+    sx32 = float(np.float32(SX))                          # the scale as the device receives it
+    x_in = (sx32 * x0[:, k_idx].astype(np.float64)).T
+    t_in = ST * times[t_idx].astype(np.float64)
+    ref, cache = omlp.forward(theta, x_in, t_in, decide="bf16")
+    assert_grads_close(got, ref, "delta@sampled rows", rtol=MLP_RTOL)
+    up = np.zeros((T, 3, n), np.float32)
+    up_rows = rng.normal(size=(64, 3)).astype(np.float32)
+    up[t_idx, :, k_idx] = up_rows
+    d_params, d_x0 = net.backward(p, x, times, torch.from_numpy(up).cuda())
+    g_ref, g_x, _ = omlp.backward(theta, cache, up_rows)
+    _per_layer(d_params.cpu().numpy(), "d_params@sampled rows", g_ref)
+    gx, gt = np.zeros((3, n)), np.zeros((3, n))
+    np.add.at(gx.T, k_idx, sx32 * g_x)
+    np.add.at(gt.T, k_idx, sx32 * cache["d_x_terms"])
+    _centre_close(d_x0.cpu().numpy()[:, k_idx], gx[:, k_idx], gt[:, k_idx], "d_x0@sampled rows")
+    assert not np.abs(d_x0.cpu().numpy()[:, np.setdiff1d(np.arange(n), k_idx)]).any()
+
+
+def test_render_with_network_offsets_matches_oracle():
+    # network offsets as per-frame centre offsets of the rasterizer: tile lists
+    # bit-exact, images and gradients (including d delta) vs the oracle.  The
+    # offsets are the oracle network's (float32), the same input for both sides.
+    g = scenes.draw_gaussians(1500, 64, 48, 60.0, 60.0, seed=12, dynamic=True)
+    frames = scenes.identity_frames([0.0, 0.1, 0.2], 64, 48, 60.0, 60.0, 4, bg_seed=2)
+    cfg = scenes.RenderConfig(width=64, height=48, tile_w=16, tile_h=16)
+    theta = scenes.mlp_params(seed=8, last_std=0.02, bias_std=0.05)
+    delta = omlp.offsets(theta, g.mean, [fr.time for fr in frames], SX, ST).astype(np.float32)
+    gd = dataclasses.replace(g, delta=np.ascontiguousarray(delta))
+    assert np.abs(gd.delta).max() > 1e-3
+    res = run_gpu(gd, frames, cfg)
+    lists = gpu_lists(res, gd, frames, cfg)
+    ref_pairs = binning.sorted_pairs(gd, frames, cfg)
+    n_tiles = cfg.tiles_x * cfg.tiles_y
+    np.testing.assert_array_equal(lists["pair_key"], (ref_pairs["frame"] * n_tiles + ref_pairs["tile"]).astype(np.uint32))
+    np.testing.assert_array_equal(lists["pair_item"], (ref_pairs["frame"] * g.n + ref_pairs["index"]).astype(np.uint32))
+    ref = oref.render(gd, frames, cfg)
+    ok = ~ref["flagged"]
+    for k in ("rgb", "quad", "depth", "T_final"):
+        assert_images_close(res[k], ref[k], ok, f"offsets/{k}")
+    up = mask_upstream(scenes.upstream_grads(len(frames), cfg, seed=5), ok)
+    ref_b = oref.render(gd, frames, cfg, upstream=up)
+    res_b = run_gpu(gd, frames, cfg, upstream=up)
+    for k, r in ref_b["grads"].items():
+        assert_grads_close(res_b["grads"][k], r, f"offsets/{k}")

@@ -93,14 +93,15 @@ def test_tiny_network_equals_python_loops():
         np.testing.assert_allclose(out[r], h, rtol=1e-13, atol=1e-15)
 
 
-def test_backward_central_differences():
+@pytest.mark.parametrize("decide", ["exact", "bf16"])
+def test_backward_central_differences(decide):
     rng = np.random.default_rng(3)
     lx, lt, width, depth = 3, 2, 8, 3
     shapes = mlp.layer_shapes(mlp.n_inputs(lx, lt), width, depth)
     theta = _theta(rng, shapes)
     x_in, t_in = rng.uniform(0, 1, (5, 3)), rng.uniform(0, 1, 5)
     d_out = rng.normal(size=(5, 3))
-    out, cache = mlp.forward(theta, x_in, t_in, lx, lt, width, depth)
+    out, cache = mlp.forward(theta, x_in, t_in, lx, lt, width, depth, decide)
     # smooth regime: every pre-activation well away from the relu kink
     W, b = mlp.unpack(theta, shapes)
     z = [cache["h"][l] @ W[l].T + b[l] for l in range(depth)]
@@ -108,7 +109,7 @@ def test_backward_central_differences():
     g_theta, g_x, g_t = mlp.backward(theta, cache, d_out)
 
     def loss(th=theta, xi=x_in, ti=t_in):
-        return float((mlp.forward(th, xi, ti, lx, lt, width, depth)[0] * d_out).sum())
+        return float((mlp.forward(th, xi, ti, lx, lt, width, depth, decide)[0] * d_out).sum())
 
     h = 1e-6
     idx = np.concatenate([rng.choice(len(theta), 40, replace=False),
@@ -137,7 +138,7 @@ def test_offsets_rows_and_centre_gradient():
     theta = _theta(rng, shapes)
     x0 = rng.uniform(-1, 1, (3, 6))
     times = np.array([0.0, 0.1, 0.3])
-    sx, st = 0.2, 4.0
+    sx, st = 0.25, 4.0          # exact in float32, the precision of the scales
     d = mlp.offsets(theta, x0, times, sx, st, lx, lt, width, depth)
     assert d.shape == (3, 3, 6)
     for ti, t in enumerate(times):
@@ -167,3 +168,41 @@ def test_initialisation_statistics():
         assert not b[l].any()
     assert W[-1].std() == pytest.approx(1e-5, rel=0.1)
     assert not b[-1].any()
+
+
+def test_bfloat16_rounding():
+    # 8 significant bits, ties to even: spacing 2^-7 on [1, 2)
+    cases = {1.0: 1.0, 1 + 2 ** -8: 1.0, 1 + 3 * 2 ** -8: 1 + 2 ** -6, 1 + 2 ** -7: 1 + 2 ** -7,
+             1 + 2 ** -8 + 2 ** -20: 1 + 2 ** -7, -(1 + 3 * 2 ** -8): -(1 + 2 ** -6),
+             3.0: 3.0, 0.0: 0.0, 2.0 ** -130: 2.0 ** -130}
+    for x, e in cases.items():
+        assert mlp.round_bf16(np.array([x]))[0] == e, x
+    # an independent implementation of the same rounding: torch's conversion
+    import torch
+    x = np.random.default_rng(5).normal(0, 10, 10000).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(mlp.round_bf16(x), ref)
+
+
+def test_bfloat16_decisions_differ_only_near_zero():
+    # the kernel-precision decisions equal the exact ones except for units
+    # whose pre-activation is within bfloat16 rounding of 0; an all-active
+    # network is decided identically
+    rng = np.random.default_rng(6)
+    lx, lt, width, depth = 10, 10, 64, 4
+    shapes = mlp.layer_shapes(mlp.n_inputs(lx, lt), width, depth)
+    theta = _theta(rng, shapes)
+    x_in, t_in = rng.uniform(0, 1, (400, 3)), rng.uniform(0, 1, 400)
+    out_e, ce = mlp.forward(theta, x_in, t_in, lx, lt, width, depth, "exact")
+    out_b, cb = mlp.forward(theta, x_in, t_in, lx, lt, width, depth, "bf16")
+    W, b = mlp.unpack(theta, shapes)
+    for l in range(depth):
+        z = cb["h"][l] @ W[l].T + b[l]
+        scale = np.abs(cb["h"][l]) @ np.abs(W[l]).T + np.abs(b[l])
+        differ = cb["masks"][l] != (z > 0)
+        assert differ.mean() < 0.01
+        assert np.all(np.abs(z[differ]) <= 2 * 2 ** -8 * scale[differ] + 1e-12)
+    theta_p = _theta(rng, shapes, nonneg=True, b0=100.0)
+    a, _ = mlp.forward(theta_p, x_in, t_in, lx, lt, width, depth, "exact")
+    c, _ = mlp.forward(theta_p, x_in, t_in, lx, lt, width, depth, "bf16")
+    np.testing.assert_array_equal(a, c)
