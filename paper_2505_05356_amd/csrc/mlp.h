@@ -13,7 +13,7 @@ constexpr int kK0 = 96;          // encoded input features, zero-padded
 constexpr int kOutPad = 16;      // head outputs (3) padded to one matrix tile
 constexpr int kHeadK = 32;       // head outputs padded to one k-step (backward)
 constexpr int kRows = 128;       // rows per workgroup of the row-parallel kernels
-constexpr int kMaxChunks = 64;   // row chunks of the weight-gradient reduction
+constexpr int kMaxChunks = 144;  // row chunks of the weight-gradient reduction (~4 blocks per CU)
 constexpr int kMaxTimes = GFTORF_MLP_MAX_TIMES;
 
 // Padded matrix shapes of layer l: forward weights [NO][NI], transposed

@@ -105,7 +105,7 @@ __device__ __forceinline__ void gemm_128x64(const bf16* X, const bf16* __restric
                                             f32x4 (&acc)[8][4], int lane) {
     const int lr = lane & 15, lk = (lane >> 4) * 8;
     const bf16* bp = B + (size_t)(col0 + lr) * K + lk;
-#pragma unroll 2
+#pragma unroll
     for (int k0 = 0; k0 < K; k0 += 32) {
         bf16x8 b[4];
 #pragma unroll
@@ -243,12 +243,22 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(Args a, const float* __restrict
 
     f32x4 acc[8][4];
     const int col0 = 64 * wv;
+    // the activations whose signs gate this layer's gradient, loaded before
+    // the product so that their latency hides behind it
+    bf16x4 hm[8][4];
+    auto load_masks = [&](const bf16* H) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                hm[r][c] = *(const bf16x4*)(H + blk_off<kWidth>(r0 + 16 * r + 4 * lg, col0 + 16 * c + lr));
+    };
+    load_masks(a.H[kDepth]);
     zero(acc);
     gemm_128x64<kHeadK>(X, a.wt[kDepth], col0, acc, lane);   // g_8 = gz_8 W_8
     for (int l = kDepth - 1; l >= 0; --l) {
         __syncthreads();
         // gz_l = g_{l+1} * [h_{l+1} > 0]
-        const bf16* H = a.H[l + 1];
         bf16* GZ = a.GZ[l];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -256,7 +266,7 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(Args a, const float* __restrict
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 const size_t o = blk_off<kWidth>(r0 + 16 * r + 4 * lg, col);
-                const bf16x4 h = *(const bf16x4*)(H + o);
+                const bf16x4 h = hm[r][c];
                 bf16x4 v;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -268,6 +278,7 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(Args a, const float* __restrict
         }
         __syncthreads();
         if (l > 0) {
+            load_masks(a.H[l]);
             zero(acc);
             gemm_128x64<kWidth>(X, a.wt[l], col0, acc, lane);   // g_l = gz_l W_l
         }
