@@ -100,21 +100,34 @@ __device__ __forceinline__ void row_inputs(const Args& a, int64_t r, float (&xin
 
 // acc[r][c] += X[16 r + .][.] * B[col0 + 16 c + .][.] over K: X in LDS
 // (row-major, stride kLDX), B in global memory as [cols][K].
-template <int K>
+// With PIPE the next k-step's weight fragments are in flight while this one
+// multiplies (pinned by a scheduling barrier); without it the compiler
+// schedules the loads, which suits the backward, whose mask loads are
+// already queued ahead of the product.
+template <int K, bool PIPE>
 __device__ __forceinline__ void gemm_128x64(const bf16* X, const bf16* __restrict__ B, int col0,
                                             f32x4 (&acc)[8][4], int lane) {
     const int lr = lane & 15, lk = (lane >> 4) * 8;
     const bf16* bp = B + (size_t)(col0 + lr) * K + lk;
+    bf16x8 b[4], bn[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) b[c] = *(const bf16x8*)(bp + (size_t)16 * c * K);
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 b[4];
+        if (k0 + 32 < K) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = *(const bf16x8*)(bp + (size_t)16 * c * K + k0);
+            for (int c = 0; c < 4; ++c) bn[c] = *(const bf16x8*)(bp + (size_t)16 * c * K + k0 + 32);
+        }
+        if (PIPE) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const bf16x8 x = *(const bf16x8*)(X + (16 * r + lr) * kLDX + lk + k0);
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[r][c] = mfma(x, b[c], acc[r][c]);
+        }
+        if (k0 + 32 < K) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = bn[c];
         }
     }
 }
@@ -168,17 +181,20 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(Args a, float* __restrict__ del
     f32x4 acc[8][4];
     const int col0 = 64 * wv;
     for (int l = 0; l < kDepth; ++l) {
+        float bias[4];   // read before the product: no load wait behind the stores below
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bias[c] = a.bias[l][col0 + 16 * c + lr];
         zero(acc);
         if (l == 0)
-            gemm_128x64<kK0>(X, a.wf[0], col0, acc, lane);
+            gemm_128x64<kK0, true>(X, a.wf[0], col0, acc, lane);
         else
-            gemm_128x64<kWidth>(X, a.wf[l], col0, acc, lane);
+            gemm_128x64<kWidth, true>(X, a.wf[l], col0, acc, lane);
         __syncthreads();   // every wave has read this layer's input
         bf16* H = a.H[l + 1];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int col = col0 + 16 * c + lr;
-            const float bb = a.bias[l][col];
+            const float bb = bias[c];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 bf16x4 v;
@@ -255,7 +271,7 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(Args a, const float* __restrict
     };
     load_masks(a.H[kDepth]);
     zero(acc);
-    gemm_128x64<kHeadK>(X, a.wt[kDepth], col0, acc, lane);   // g_8 = gz_8 W_8
+    gemm_128x64<kHeadK, false>(X, a.wt[kDepth], col0, acc, lane);   // g_8 = gz_8 W_8
     for (int l = kDepth - 1; l >= 0; --l) {
         __syncthreads();
         // gz_l = g_{l+1} * [h_{l+1} > 0]
@@ -280,7 +296,7 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(Args a, const float* __restrict
         if (l > 0) {
             load_masks(a.H[l]);
             zero(acc);
-            gemm_128x64<kWidth>(X, a.wt[l], col0, acc, lane);   // g_l = gz_l W_l
+            gemm_128x64<kWidth, false>(X, a.wt[l], col0, acc, lane);   // g_l = gz_l W_l
         }
     }
     // g_0 = gz_0 W_0 -> [128][96]: wave w takes rows 32w .. 32w+31, all 6 column tiles
@@ -370,14 +386,20 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-#pragma unroll 2
-    for (int64_t kb = rs / 8; kb < re / 8; kb += 4) {
+    // one k-step (32 rows) of fragments in flight ahead of the products
+    bf16x8 av[MT], bv[NT], an[MT], bn[NT];
+    auto load = [&](int64_t kb, bf16x8 (&A)[MT], bf16x8 (&Bf)[NT]) {
         const int64_t rb = kb + lg;
-        bf16x8 av[MT], bv[NT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) av[m] = *(const bf16x8*)(GZ + ((size_t)rb * NO + o0 + 16 * m + lr) * 8);
+        for (int m = 0; m < MT; ++m) A[m] = *(const bf16x8*)(GZ + ((size_t)rb * NO + o0 + 16 * m + lr) * 8);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) bv[t] = *(const bf16x8*)(H + ((size_t)rb * NI + i0 + 16 * t + lr) * 8);
+        for (int t = 0; t < NT; ++t) Bf[t] = *(const bf16x8*)(H + ((size_t)rb * NI + i0 + 16 * t + lr) * 8);
+    };
+    if (rs < re) load(rs / 8, av, bv);
+    for (int64_t kb = rs / 8; kb < re / 8; kb += 4) {
+        const bool more = kb + 4 < re / 8;
+        if (more) load(kb + 4, an, bn);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -387,6 +409,12 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
             for (int m = 0; m < MT; ++m)
 #pragma unroll
                 for (int e = 0; e < 8; ++e) sb[m] += (float)av[m][e];
+        if (more) {
+#pragma unroll
+            for (int m = 0; m < MT; ++m) av[m] = an[m];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bv[t] = bn[t];
+        }
     }
     float* P = d.part + (int64_t)blockIdx.x * d.part_stride + d.part_off[l];
 #pragma unroll
