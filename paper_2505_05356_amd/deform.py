@@ -93,3 +93,28 @@ class DeformNet:
                                       self._times(times), T, _ptr(d_delta), _ptr(d_params),
                                       _ptr(d_x0), _ptr(self.ws), self.nbytes, _stream(stream)))
         return d_params, d_x0
+
+
+class DeformOffsets(torch.autograd.Function):
+    """delta [T, 3, n] = network(params, x0, times) as an autograd node: its
+    backward is gftorf_mlp_bwd on the same workspace, so it composes with
+    raster.RasterizeCToF (pass the result as the Gaussians' `delta`)."""
+
+    @staticmethod
+    def forward(ctx, net: DeformNet, times, params, x0):
+        params, x0 = params.contiguous(), x0.contiguous()
+        ctx.net, ctx.times = net, list(times)
+        ctx.save_for_backward(params, x0)
+        return net.forward(params, x0, ctx.times, save=True)
+
+    @staticmethod
+    def backward(ctx, d_delta):
+        params, x0 = ctx.saved_tensors
+        d_params, d_x0 = ctx.net.backward(params, x0, ctx.times, d_delta.contiguous(),
+                                          want_x0=ctx.needs_input_grad[3])
+        return None, None, d_params, d_x0
+
+
+def offsets(net: DeformNet, params: torch.Tensor, x0: torch.Tensor, times: Sequence[float]):
+    """Differentiable per-frame centre offsets for the rasterizer."""
+    return DeformOffsets.apply(net, times, params, x0)

@@ -163,3 +163,38 @@ def test_render_with_network_offsets_matches_oracle():
     res_b = run_gpu(gd, frames, cfg, upstream=up)
     for k, r in ref_b["grads"].items():
         assert_grads_close(res_b["grads"][k], r, f"offsets/{k}")
+
+
+def test_network_offsets_compose_with_the_rasterizer_under_autograd():
+    # a loss on the rendered images back-propagates through the rasterizer's
+    # per-frame offsets into the network (one torch graph), and the result
+    # equals the two library backwards called by hand
+    from paper_2505_05356_amd import raster
+    g = scenes.draw_gaussians(800, 48, 32, 45.0, 45.0, seed=21)
+    frames = scenes.identity_frames([0.0, 0.1], 48, 32, 45.0, 45.0, 4, bg_seed=3)
+    cfg = scenes.RenderConfig(width=48, height=32, tile_w=16, tile_h=16)
+    theta = torch.from_numpy(scenes.mlp_params(seed=9, last_std=0.02, bias_std=0.05)).cuda()
+    net = deform.DeformNet(g.n, 2, pos_scale=SX, time_scale=ST)
+    params = raster.to_device_params(g, "cuda")
+    times = [fr.time for fr in frames]
+    theta.requires_grad_(True)
+    params["mean"].requires_grad_(True)
+    delta = deform.offsets(net, theta, params["mean"], times)
+    out = raster.render(dict(params, delta=delta), frames, cfg)
+    up = {k: torch.from_numpy(v).cuda() for k, v in scenes.upstream_grads(2, cfg, seed=4).items()}
+    loss = (out["rgb"] * up["rgb"]).sum() + (out["quad"] * up["quad"]).sum() + (out["depth"] * up["depth"]).sum()
+    loss.backward()
+    g_theta, g_mean = theta.grad.clone(), params["mean"].grad.clone()
+    # by hand: rasterizer backward -> d delta -> network backward
+    fdev = raster.pack_frames(frames, cfg)
+    p2 = {k: (v.detach() if v is not None else None) for k, v in params.items()}
+    d_fixed = net.forward(theta.detach(), p2["mean"], times)
+    p2["delta"] = d_fixed
+    ws = raster.Workspace(g.n, 2, cfg)
+    o2 = raster.forward(p2, fdev, cfg, ws)
+    gr = raster.backward(p2, fdev, cfg, ws, o2, up["rgb"], up["quad"], up["depth"])
+    net.forward(theta.detach(), p2["mean"], times)
+    d_params, d_x0 = net.backward(theta.detach(), p2["mean"], times, gr["delta"])
+    torch.cuda.synchronize()
+    assert_grads_close(g_theta.cpu().numpy(), d_params.cpu().numpy(), "autograd/params", rtol=1e-4)
+    assert_grads_close(g_mean.cpu().numpy(), (gr["mean"] + d_x0).cpu().numpy(), "autograd/mean", rtol=1e-4)
