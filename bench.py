@@ -343,6 +343,36 @@ def main():
     value = F * args.steps / (ms_b / 1e3)
     print(f"# batched: {ms_step:.3f} ms/step, {value:.1f} frames/s, P={P}", file=sys.stderr, flush=True)
 
+    # the same batched step captured once as a HIP graph and replayed
+    import ctypes
+    lib = raster._lib.load()
+    gstream = torch.cuda.Stream(device=dev)
+    gsp = ctypes.c_void_p(gstream.cuda_stream)
+    torch.cuda.synchronize()
+    gexec = ctypes.c_void_p()
+    raster._lib.check(lib.gftorf_graph_begin(gsp))
+    try:
+        raster.forward(params, fdev, cfg, ws, out=out, check=False, stream=gstream)
+        raster.backward(params, fdev, cfg, ws, out, d["rgb"], d["quad"], d["depth"], grads=grads,
+                        stream=gstream)
+    finally:
+        rc = lib.gftorf_graph_end(gsp, ctypes.byref(gexec))
+    raster._lib.check(rc)
+    for _ in range(args.warmup):
+        raster._lib.check(lib.gftorf_graph_launch(gexec, gsp))
+    torch.cuda.synchronize()
+    gs_ev, ge_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gs_ev.record(gstream)
+    for _ in range(args.steps):
+        raster._lib.check(lib.gftorf_graph_launch(gexec, gsp))
+    ge_ev.record(gstream)
+    torch.cuda.synchronize()
+    ms_g = gs_ev.elapsed_time(ge_ev) / args.steps
+    raster._lib.check(lib.gftorf_graph_destroy(gexec))
+    graph_value = F / (ms_g / 1e3)
+    print(f"# batched, graph-replayed: {ms_g:.3f} ms/step, {graph_value:.1f} frames/s",
+          file=sys.stderr, flush=True)
+
     per_frame = None
     if not args.no_per_frame:
         for _ in range(args.warmup):
@@ -400,6 +430,8 @@ def main():
                    "outputs": "rgb+quad+depth", "pairs": P, "evals_fwd": work["E_fwd"],
                    "evals_bwd": work["E_bwd"], "composited": work["C"],
                    "tile_times_ms": tile_times},
+        "graph_value": round(graph_value, 2),
+        "graph_ms_per_step": round(ms_g, 4),
         "per_frame_value": None if per_frame is None else round(per_frame, 2),
         "batched_over_per_frame": None if per_frame is None else round(value / per_frame, 3),
         "roofline": roof,
