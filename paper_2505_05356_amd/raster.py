@@ -5,9 +5,12 @@ backward pass runs in the HIP kernels of libgftorf.so.
 
     params  dict of float32 CUDA tensors: mean [3,N], vel [3,N] | None,
             acc [3,N] | None, scale [3,N], quat [4,N], omega [3,N] | None,
-            opacity_logit [N], rgb [3,N], albedo [N]
+            opacity_logit [N], rgb [3,N], albedo [N]; optional sh_rgb [K,3,N],
+            sh_albedo [K,N] (spherical harmonics) and delta [F,3,N] (per-frame
+            centre offsets, e.g. deform.offsets)
     frames  list of frame descriptors (objects with R, t, fx, fy, cx, cy,
-            time, bg_rgb, bg_quad) or a packed float32 CUDA tensor [F, 36]
+            time, bg_rgb, bg_quad, and optionally t_lo, t_hi, quad_mask) or a
+            packed float32 CUDA tensor [F, 40]
     cfg     object with width, height, freqs, phases, tile_w, tile_h,
             alpha_min, alpha_max, T_min, extent_sigma, dilation, near_z,
             source_intensity, bg_T_power
