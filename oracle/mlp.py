@@ -207,3 +207,40 @@ def offsets_backward(theta, x0, times, s_x, s_t, d_delta, lx: int = 10, lt: int 
     if terms:
         return flat, d_x0, s_x * cache["d_x_terms"].reshape(T, N, 3).sum(axis=0).T
     return flat, d_x0
+
+
+def eq7_weights(frame):
+    """Eq. 7 weights (w1, w2) of a frame with anchors t_lo < t_hi: its centre
+    is w1 x(t_lo) + w2 x(t_hi); (1, 0) for a frame without anchors.  The frame
+    values are float32, widened exactly."""
+    f32 = lambda v: float(np.float32(v))
+    t, lo, hi = f32(frame.time), f32(getattr(frame, "t_lo", 0.0)), f32(getattr(frame, "t_hi", 0.0))
+    if hi > lo:
+        return (hi - t) / (hi - lo), (t - lo) / (hi - lo)
+    return 1.0, 0.0
+
+
+def blend_offsets(delta_steps, frames, anchors):
+    """Eq. 7 with the network: per-frame offsets [F][3][N] from offsets at
+    integer timesteps delta_steps [S][3][N]; frame f reads steps
+    anchors[f] = (lo, hi) with its Eq. 7 weights."""
+    d = np.asarray(delta_steps, np.float64)
+    out = np.empty((len(frames),) + d.shape[1:])
+    for f, fr in enumerate(frames):
+        w1, w2 = eq7_weights(fr)
+        lo, hi = anchors[f]
+        out[f] = w1 * d[lo] + w2 * d[hi]
+    return out
+
+
+def blend_offsets_backward(d_frames, frames, anchors, n_steps):
+    """Gradient of sum(d_frames * blend_offsets(...)) with respect to
+    delta_steps [S][3][N]."""
+    g = np.asarray(d_frames, np.float64)
+    out = np.zeros((n_steps,) + g.shape[1:])
+    for f, fr in enumerate(frames):
+        w1, w2 = eq7_weights(fr)
+        lo, hi = anchors[f]
+        out[lo] += w1 * g[f]
+        out[hi] += w2 * g[f]
+    return out

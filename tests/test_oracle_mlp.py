@@ -206,3 +206,34 @@ def test_bfloat16_decisions_differ_only_near_zero():
     a, _ = mlp.forward(theta_p, x_in, t_in, lx, lt, width, depth, "exact")
     c, _ = mlp.forward(theta_p, x_in, t_in, lx, lt, width, depth, "bf16")
     np.testing.assert_array_equal(a, c)
+
+
+def test_eq7_blend_of_offsets():
+    # Eq. 7 is exact for motion linear in time: offsets A + B t at the integer
+    # timesteps blend to A + B t at every fractional frame time
+    import dataclasses
+    rng = np.random.default_rng(7)
+    A, B = rng.normal(size=(3, 5)), rng.normal(size=(3, 5))
+    step_t = [0.0, 0.25, 0.5]
+    steps = np.stack([A + B * t for t in step_t])
+    base = scenes.Frame()
+    frames, anchors = [], []
+    for k in range(8):
+        i, j = divmod(k, 4)
+        t = float(np.float32(0.25 * (i + j / 4)))
+        frames.append(dataclasses.replace(base, time=t, t_lo=float(np.float32(0.25 * i)),
+                                          t_hi=float(np.float32(0.25 * (i + 1)))))
+        anchors.append((i, i + 1))
+    out = mlp.blend_offsets(steps, frames, anchors)
+    for f, fr in enumerate(frames):
+        np.testing.assert_allclose(out[f], A + B * fr.time, rtol=1e-12, atol=1e-12)
+    # a frame at its first anchor takes that step's offsets; one without
+    # anchors takes its first index unchanged
+    assert mlp.eq7_weights(frames[0]) == (1.0, 0.0)
+    plain = mlp.blend_offsets(steps, [base], [(2, 0)])
+    np.testing.assert_array_equal(plain[0], steps[2])
+    # the backward is the adjoint: <blend(x), y> = <x, blend_bwd(y)>
+    y = rng.normal(size=out.shape)
+    lhs = (out * y).sum()
+    rhs = (steps * mlp.blend_offsets_backward(y, frames, anchors, 3)).sum()
+    assert lhs == pytest.approx(rhs, rel=1e-12)
