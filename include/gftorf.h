@@ -356,6 +356,28 @@ int gftorf_mlp_bwd(const gftorf_mlp_config* cfg, const float* params, const floa
                    const float* times, int32_t n_times, const float* d_delta, float* d_params,
                    float* d_x0, void* ws, size_t ws_bytes, void* stream);
 
+/* Eq. 7 with the deformation network (paper §4): the network is evaluated at
+ * integer timesteps only, and a raw frame between two of them takes the
+ * straight line between the deformed positions.  With delta_steps
+ * [n_steps][3][n] the network's offsets at the timesteps, frame f gets
+ *   delta_frames[f] = w1 delta_steps[lo_f] + w2 delta_steps[hi_f],
+ *   w1 = (t_hi - t) / (t_hi - t_lo), w2 = (t - t_lo) / (t_hi - t_lo)
+ * from frames[f] (device; the rasterizer's descriptors), and
+ * (lo_f, hi_f) = anchors[2 f], anchors[2 f + 1] (HOST int32 [n_frames][2],
+ * each in [0, n_steps)).  A frame with t_hi <= t_lo takes delta_steps[lo_f].
+ * The result is the `delta` of gftorf_gaussians.  n_frames <= 256. */
+#define GFTORF_MAX_BLEND_FRAMES 256
+int gftorf_blend_offsets(const float* delta_steps, int32_t n_steps, int64_t n,
+                         const gftorf_frame* frames, int32_t n_frames, const int32_t* anchors,
+                         float* delta_frames, void* stream);
+
+/* Transpose of gftorf_blend_offsets: d_steps [n_steps][3][n] (overwritten) =
+ * the gradient of sum(d_frames * delta_frames) with respect to delta_steps,
+ * summed over frames in frame order (deterministic). */
+int gftorf_blend_offsets_bwd(const float* d_frames, int32_t n_frames, int64_t n,
+                             const gftorf_frame* frames, const int32_t* anchors, int32_t n_steps,
+                             float* d_steps, void* stream);
+
 const char* gftorf_strerror(int code);
 const char* gftorf_last_error(void);
 int gftorf_version(void);

@@ -107,6 +107,10 @@ _SIGS = {
                                  c_int32, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
     "gftorf_mlp_bwd": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, POINTER(c_float),
                                  c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gftorf_blend_offsets": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int32, POINTER(c_int32),
+                                       c_void_p, c_void_p]),
+    "gftorf_blend_offsets_bwd": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, POINTER(c_int32), c_int32,
+                                           c_void_p, c_void_p]),
     "gftorf_strerror": (c_char_p, [c_int32]),
     "gftorf_last_error": (c_char_p, []),
     "gftorf_version": (c_int32, []),

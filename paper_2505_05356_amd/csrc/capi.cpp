@@ -412,6 +412,47 @@ int gftorf_mlp_bwd(const gftorf_mlp_config* cfg, const float* params, const floa
     return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_mlp_bwd");
 }
 
+namespace {
+int blend_args(int32_t n_steps, int64_t n, const gftorf_frame* frames, int32_t n_frames,
+               const int32_t* anchors, gft::mlp::Blend* b) {
+    if (!frames || !anchors || n < 0 || n_steps < 1 || n_frames < 0 ||
+        n_frames > gft::mlp::kMaxBlendFrames)
+        return fail(GFTORF_EINVAL, "bad blend arguments (1 <= n_steps, 0 <= n_frames <= 256)");
+    for (int f = 0; f < 2 * n_frames; ++f)
+        if (anchors[f] < 0 || anchors[f] >= n_steps)
+            return fail(GFTORF_EINVAL, "anchor step out of range");
+    for (int f = 0; f < 2 * gft::mlp::kMaxBlendFrames; ++f) b->anchors[f] = f < 2 * n_frames ? anchors[f] : 0;
+    b->n_frames = n_frames;
+    b->n_steps = n_steps;
+    b->n = n;
+    return GFTORF_OK;
+}
+}  // namespace
+
+int gftorf_blend_offsets(const float* delta_steps, int32_t n_steps, int64_t n,
+                         const gftorf_frame* frames, int32_t n_frames, const int32_t* anchors,
+                         float* delta_frames, void* stream) {
+    gft::mlp::Blend b;
+    const int rc = blend_args(n_steps, n, frames, n_frames, anchors, &b);
+    if (rc != GFTORF_OK) return rc;
+    if ((!delta_steps || !delta_frames) && n > 0) return fail(GFTORF_EINVAL, "NULL pointer");
+    (void)hipGetLastError();
+    const hipError_t e = gft::mlp::launch_blend(b, delta_steps, frames, delta_frames, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_blend_offsets");
+}
+
+int gftorf_blend_offsets_bwd(const float* d_frames, int32_t n_frames, int64_t n,
+                             const gftorf_frame* frames, const int32_t* anchors, int32_t n_steps,
+                             float* d_steps, void* stream) {
+    gft::mlp::Blend b;
+    const int rc = blend_args(n_steps, n, frames, n_frames, anchors, &b);
+    if (rc != GFTORF_OK) return rc;
+    if ((!d_frames || !d_steps) && n > 0) return fail(GFTORF_EINVAL, "NULL pointer");
+    (void)hipGetLastError();
+    const hipError_t e = gft::mlp::launch_blend_bwd(b, d_frames, frames, d_steps, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_blend_offsets_bwd");
+}
+
 int gftorf_fill_f32(float* p, float value, int64_t n, void* stream) {
     if (!p && n > 0) return fail(GFTORF_EINVAL, "NULL pointer");
     (void)hipGetLastError();

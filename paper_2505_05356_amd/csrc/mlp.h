@@ -50,6 +50,17 @@ struct Call {
 };
 
 hipError_t launch_fwd(const Layout& L, const Call& c, float* delta, bool save, hipStream_t s);
+
+constexpr int kMaxBlendFrames = GFTORF_MAX_BLEND_FRAMES;
+struct Blend {
+    int32_t anchors[2 * kMaxBlendFrames];   // (lo, hi) step of every frame
+    int32_t n_frames, n_steps;
+    int64_t n;
+};
+hipError_t launch_blend(const Blend& b, const float* steps, const gftorf_frame* frames, float* out,
+                        hipStream_t s);
+hipError_t launch_blend_bwd(const Blend& b, const float* d_frames, const gftorf_frame* frames,
+                            float* d_steps, hipStream_t s);
 hipError_t launch_bwd(const Layout& L, const Call& c, const float* d_delta, float* d_params,
                       float* d_x0, hipStream_t s);
 

@@ -19,6 +19,8 @@
 //                 contraction, split into fixed chunks, one partial per chunk.
 //   k_mlp_reduce  sums the chunk partials in chunk order into the parameter
 //                 layout; k_mlp_dx0 sums the centre gradient over the times.
+//   k_blend       Eq. 7 with the network: per-frame offsets from the offsets
+//                 at two integer timesteps; k_blend_bwd is its transpose.
 //
 // Saved activations and gradients use a row-blocked layout [rows/8][feat][8]:
 // the eight rows of one feature are one 16-byte fragment of the weight-gradient
@@ -501,6 +503,56 @@ __global__ void __launch_bounds__(256) k_mlp_pack(PackArgs p, const float* __res
     }
 }
 
+// Eq. 7 weights of a frame (1, 0 without anchors)
+__device__ __forceinline__ void eq7_weights(const gftorf_frame& fr, float& w1, float& w2) {
+    if (fr.t_hi > fr.t_lo) {
+        const float span = fr.t_hi - fr.t_lo;
+        w1 = (fr.t_hi - fr.time) / span;
+        w2 = (fr.time - fr.t_lo) / span;
+    } else {
+        w1 = 1.0f;
+        w2 = 0.0f;
+    }
+}
+
+// out[f] = w1_f steps[lo_f] + w2_f steps[hi_f], one thread per (frame, element)
+__global__ void __launch_bounds__(256) k_blend(Blend b, const float* __restrict__ steps,
+                                               const gftorf_frame* __restrict__ frames,
+                                               float* __restrict__ out) {
+    const int64_t per = 3 * b.n;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)b.n_frames * per) return;
+    const int f = (int)(i / per);
+    const int64_t e = i - (int64_t)f * per;
+    float w1, w2;
+    eq7_weights(frames[f], w1, w2);
+    float v = w1 * steps[(int64_t)b.anchors[2 * f] * per + e];
+    if (w2 != 0.0f) v += w2 * steps[(int64_t)b.anchors[2 * f + 1] * per + e];
+    out[i] = v;
+}
+
+// d_steps[s] = sum over frames (in frame order) of the weight of s times d_frames[f]
+__global__ void __launch_bounds__(256) k_blend_bwd(Blend b, const float* __restrict__ d_frames,
+                                                   const gftorf_frame* __restrict__ frames,
+                                                   float* __restrict__ d_steps) {
+    const int64_t per = 3 * b.n;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)b.n_steps * per) return;
+    const int st = (int)(i / per);
+    const int64_t e = i - (int64_t)st * per;
+    float acc = 0.0f;
+    for (int f = 0; f < b.n_frames; ++f) {
+        const int lo = b.anchors[2 * f], hi = b.anchors[2 * f + 1];
+        if (lo != st && hi != st) continue;
+        float w1, w2;
+        eq7_weights(frames[f], w1, w2);
+        const float g = d_frames[(int64_t)f * per + e];
+        if (lo == st) acc += w1 * g;
+        if (hi == st && w2 != 0.0f) acc += w2 * g;
+    }
+    d_steps[i] = acc;
+}
+
 Args make_args(const Layout& L, const Call& c) {
     Args a;
     a.x0 = c.x0;
@@ -600,6 +652,25 @@ hipError_t launch_fwd(const Layout& L, const Call& c, float* delta, bool save, h
         hipLaunchKernelGGL(k_mlp_fwd<true>, dim3(blocks), dim3(256), 0, s, a, delta);
     else
         hipLaunchKernelGGL(k_mlp_fwd<false>, dim3(blocks), dim3(256), 0, s, a, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend(const Blend& b, const float* steps, const gftorf_frame* frames, float* out,
+                        hipStream_t s) {
+    const int64_t total = (int64_t)b.n_frames * 3 * b.n;
+    if (total == 0) return hipSuccess;
+    ProfScope _p("k_blend", s);
+    hipLaunchKernelGGL(k_blend, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, b, steps, frames, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_bwd(const Blend& b, const float* d_frames, const gftorf_frame* frames,
+                            float* d_steps, hipStream_t s) {
+    const int64_t total = (int64_t)b.n_steps * 3 * b.n;
+    if (total == 0) return hipSuccess;
+    ProfScope _p("k_blend_bwd", s);
+    hipLaunchKernelGGL(k_blend_bwd, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, b, d_frames,
+                       frames, d_steps);
     return hipGetLastError();
 }
 

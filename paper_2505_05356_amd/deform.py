@@ -118,3 +118,49 @@ class DeformOffsets(torch.autograd.Function):
 def offsets(net: DeformNet, params: torch.Tensor, x0: torch.Tensor, times: Sequence[float]):
     """Differentiable per-frame centre offsets for the rasterizer."""
     return DeformOffsets.apply(net, times, params, x0)
+
+
+def _anchors(anchors, n_frames):
+    flat = [int(v) for pair in anchors for v in pair]
+    if len(flat) != 2 * n_frames:
+        raise ValueError("one (lo, hi) anchor pair per frame")
+    return (ctypes.c_int32 * len(flat))(*flat)
+
+
+def blend(delta_steps: torch.Tensor, frames_dev: torch.Tensor, anchors, stream=None):
+    """Eq. 7 with the network: per-frame offsets [F, 3, n] from the offsets at
+    integer timesteps delta_steps [S, 3, n]; frame f blends steps anchors[f] =
+    (lo, hi) with its Eq. 7 weights (frames_dev: packed frame descriptors)."""
+    lib = _lib.load()
+    _f32dev(delta_steps, "delta_steps")
+    S, _, n = delta_steps.shape
+    F = frames_dev.shape[0]
+    out = torch.empty((F, 3, n), device=delta_steps.device)
+    _lib.check(lib.gftorf_blend_offsets(_ptr(delta_steps), S, n, _ptr(frames_dev), F,
+                                        _anchors(anchors, F), _ptr(out), _stream(stream)))
+    return out
+
+
+def blend_backward(d_frames: torch.Tensor, frames_dev: torch.Tensor, anchors, n_steps: int,
+                   stream=None):
+    """Transpose of blend: d delta_steps [S, 3, n] from d_frames [F, 3, n]."""
+    lib = _lib.load()
+    _f32dev(d_frames, "d_frames")
+    F, _, n = d_frames.shape
+    out = torch.empty((n_steps, 3, n), device=d_frames.device)
+    _lib.check(lib.gftorf_blend_offsets_bwd(_ptr(d_frames), F, n, _ptr(frames_dev),
+                                            _anchors(anchors, F), n_steps, _ptr(out), _stream(stream)))
+    return out
+
+
+class BlendOffsets(torch.autograd.Function):
+    """blend as an autograd node (network at the timesteps -> raw frames)."""
+
+    @staticmethod
+    def forward(ctx, frames_dev, anchors, delta_steps):
+        ctx.frames, ctx.anchors, ctx.S = frames_dev, list(anchors), delta_steps.shape[0]
+        return blend(delta_steps.contiguous(), frames_dev, ctx.anchors)
+
+    @staticmethod
+    def backward(ctx, d_frames):
+        return None, None, blend_backward(d_frames.contiguous(), ctx.frames, ctx.anchors, ctx.S)

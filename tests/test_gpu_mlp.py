@@ -198,3 +198,32 @@ def test_network_offsets_compose_with_the_rasterizer_under_autograd():
     torch.cuda.synchronize()
     assert_grads_close(g_theta.cpu().numpy(), d_params.cpu().numpy(), "autograd/params", rtol=1e-4)
     assert_grads_close(g_mean.cpu().numpy(), (gr["mean"] + d_x0).cpu().numpy(), "autograd/mean", rtol=1e-4)
+
+
+def test_eq7_blend_of_network_offsets_matches_oracle():
+    # two asynchronous quartets (8 raw frames) between three integer
+    # timesteps: per-frame offsets and their transpose against the oracle
+    from paper_2505_05356_amd import raster
+    n = 1000
+    rng = np.random.default_rng(11)
+    steps = rng.normal(0, 0.02, (3, 3, n)).astype(np.float32)
+    base = scenes.identity_frames([0.0], 32, 32, 30.0, 30.0, 4)[0]
+    frames = scenes.async_quartet_frames(2, 0.1, base)
+    anchors = [(k // 4, k // 4 + 1) for k in range(8)]
+    cfg = scenes.RenderConfig(width=32, height=32)
+    fdev = raster.pack_frames(frames, cfg)
+    out = deform.blend(torch.from_numpy(steps).cuda(), fdev, anchors)
+    ref = omlp.blend_offsets(steps, frames, anchors)
+    up = rng.normal(size=ref.shape).astype(np.float32)
+    back = deform.blend_backward(torch.from_numpy(up).cuda(), fdev, anchors, 3)
+    ref_b = omlp.blend_offsets_backward(up, frames, anchors, 3)
+    torch.cuda.synchronize()
+    # float32 error of w1 a + w2 b is relative to |w1 a| + |w2 b| (the weights
+    # are in [0, 1]), not to the possibly cancelled result
+    scale = omlp.blend_offsets(np.abs(steps), frames, anchors)
+    assert np.all(np.abs(out.cpu().numpy() - ref) <= 1e-6 * scale + 1e-12)
+    scale_b = omlp.blend_offsets_backward(np.abs(up), frames, anchors, 3)
+    assert np.all(np.abs(back.cpu().numpy() - ref_b) <= 1e-6 * scale_b + 1e-12)
+    # out-of-range anchors are refused on the host
+    with pytest.raises(Exception):
+        deform.blend(torch.from_numpy(steps).cuda(), fdev, [(0, 3)] * 8)
