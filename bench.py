@@ -134,19 +134,26 @@ def bench_train_step(args):
     print(json.dumps(line), flush=True)
 
 
-def traffic_bytes(name):
+# the same for the deformation network's kernels (k_mlp_dw: its three launches together)
+MLP_TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
+MLP_TRAFFIC_SHA256 = "c649c4cec792a0d9190eb04c2584c4bec1f1075c0b447c7d365bc8856c0b062a"
+MLP_TRAFFIC_KIB = {"k_mlp_fwd": (198992, 6718750), "k_mlp_bwd": (3407343, 6468750),
+                   "k_mlp_dw": (10715462, 278404)}   # KiB per launch, 1.6M rows
+
+
+def traffic_bytes(name, files=TRAFFIC_FILES, sha=TRAFFIC_SHA256, table=TRAFFIC_KIB):
     """Counter-measured HBM bytes per launch of `name`, or None when there is
     no measurement for the kernel source as it is now."""
     import hashlib
-    if name not in TRAFFIC_KIB or TRAFFIC_SHA256 is None or FETCH_SCALE is None:
+    if name not in table or sha is None or FETCH_SCALE is None:
         return None
     h = hashlib.sha256()
-    for f in TRAFFIC_FILES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != TRAFFIC_SHA256:
+    if h.hexdigest() != sha:
         return None
-    fetch, write = TRAFFIC_KIB[name]
+    fetch, write = table[name]
     return int(round((fetch * FETCH_SCALE + write * WRITE_SCALE) * 1024))
 
 
@@ -206,12 +213,21 @@ def bench_mlp(args):
                                  frac=round(tf / MFMA_BF16_PEAK_TFLOPS, 4))
     dominant = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"])
     a = per_kernel[dominant]["tflops"]
+    traffic = None
+    if n == 200_000 and T == 8:   # the counters were taken on this shape
+        traffic = traffic_bytes(dominant, MLP_TRAFFIC_FILES, MLP_TRAFFIC_SHA256, MLP_TRAFFIC_KIB)
     roof = dict(bound="mfma", achieved=a, peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=round(a / MFMA_BF16_PEAK_TFLOPS, 4), traffic=None, kernel=dominant,
+                frac=round(a / MFMA_BF16_PEAK_TFLOPS, 4), traffic=traffic, kernel=dominant,
                 avg_ms=per_kernel[dominant]["avg_ms"],
                 work=f"{flop:.4g} FLOP per launch = {rows} rows x {mlp_flop_per_row()} (bf16 products)")
     print("# kernels: " + ", ".join(f"{k} {v * 1e3:.1f}us" for k, v in sorted(kern.items(), key=lambda kv: -kv[1])),
           file=sys.stderr, flush=True)
+    if args.calibration_copy_mib > 0:   # a plain copy of known size for counter scaling
+        src = torch.ones(args.calibration_copy_mib * 262144, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import mlp as omlp
