@@ -257,6 +257,17 @@ def cfg2(seed: int = 0, n: int = 100_000) -> Workload:
                     f"static scene, {n} Gaussians, 640x480, 1 frame")
 
 
+def cfg2_320(seed: int = 0, n: int = 100_000) -> Workload:
+    """cfg2's distributions at the paper's dataset resolution, 320x240
+    (fx = fy = 262.5, the same field of view)."""
+    W, H, f = 320, 240, 262.5
+    g = draw_gaussians(n, W, H, f, f, seed)
+    cfg = RenderConfig(width=W, height=H, freqs=(30e6,))
+    return Workload(f"static-{n // 1000}k-320x240", g,
+                    identity_frames([0.0], W, H, f, f, 4), cfg,
+                    f"static scene, {n} Gaussians, 320x240, 1 frame")
+
+
 def cfg3(seed: int = 0, n: int = 200_000, n_frames: int = 8) -> Workload:
     """Dynamic, 200k Gaussians, 8 frames at t in [0, 0.25 s], 640x480."""
     W, H, f = 640, 480, 525.0
