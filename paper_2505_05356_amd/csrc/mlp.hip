@@ -35,6 +35,7 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
 
 // LDS row stride in bf16: the 16-byte pad puts the 16 rows of one fragment
 // read in 16 distinct 4-bank groups.
@@ -183,10 +184,13 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(Args a, float* __restrict__ del
     f32x4 acc[8][4];
     const int col0 = 64 * wv;
     for (int l = 0; l < kDepth; ++l) {
-        float bias[4];   // read before the product: no load wait behind the stores below
+        // the products accumulate onto the bias
 #pragma unroll
-        for (int c = 0; c < 4; ++c) bias[c] = a.bias[l][col0 + 16 * c + lr];
-        zero(acc);
+        for (int c = 0; c < 4; ++c) {
+            const float bb = a.bias[l][col0 + 16 * c + lr];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) acc[r][c] = f32x4{bb, bb, bb, bb};
+        }
         if (l == 0)
             gemm_128x64<kK0, true>(X, a.wf[0], col0, acc, lane);
         else
@@ -196,15 +200,15 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(Args a, float* __restrict__ del
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int col = col0 + 16 * c + lr;
-            const float bb = bias[c];
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                bf16x4 v;
+                // bfloat16 first, then ReLU as a packed 16-bit integer max with 0:
+                // a negative bfloat16 is a negative int16
+                const bf16x4 z = __builtin_convertvector(acc[r][c], bf16x4);
+                const s16x4 zi = __builtin_bit_cast(s16x4, z);
+                const bf16x4 v = __builtin_bit_cast(bf16x4, __builtin_elementwise_max(zi, s16x4{0, 0, 0, 0}));
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    v[j] = (bf16)fmaxf(acc[r][c][j] + bb, 0.f);
-                    X[(16 * r + 4 * lg + j) * kLDX + col] = v[j];
-                }
+                for (int j = 0; j < 4; ++j) X[(16 * r + 4 * lg + j) * kLDX + col] = v[j];
                 if (SAVE) *(bf16x4*)(H + blk_off<kWidth>(r0 + 16 * r + 4 * lg, col)) = v;
             }
         }

