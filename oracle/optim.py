@@ -26,6 +26,16 @@ def l2_loss_grad(pred_rgb, pred_quad, tgt_rgb, tgt_quad, quad_weight=1.0):
     return loss, 2.0 * rr / rr.size, quad_weight * 2.0 * rq / rq.size
 
 
+def decayed_lr(lr, lr_final, decay_steps, step):
+    """Exponential learning-rate decay (§4: the network's rate falls from
+    8e-4 to 1.6e-6 over 60K iterations): lr at 1-based step 1, lr_final from
+    step decay_steps + 1 on, geometric in between; constant without decay."""
+    if decay_steps <= 0:
+        return lr
+    s = min(step - 1, decay_steps) / decay_steps
+    return lr * (lr_final / lr) ** s
+
+
 def adam_step(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-15):
     """One Adam update at 1-based step `step`; returns new (p, m, v)."""
     p, g = np.asarray(p, np.float64), np.asarray(g, np.float64)

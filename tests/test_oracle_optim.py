@@ -64,3 +64,16 @@ def test_paper_constants():
     assert [float(x) for x in g["random_background_range"]] == [-1.0, 1.0]
     gt, tr, _ = scenes.cfg5_scenes(n=10)
     assert np.all(tr.albedo == np.float32(float(g["initial_reflectivity"][0])))
+
+
+def test_decayed_learning_rate():
+    # §4's network schedule: 8e-4 at the first step, 1.6e-6 from step 60001 on,
+    # a constant ratio between consecutive steps in between
+    lr0, lr1, S = 8e-4, 1.6e-6, 60_000
+    assert optim.decayed_lr(lr0, lr1, S, 1) == lr0
+    assert optim.decayed_lr(lr0, lr1, S, S + 1) == pytest.approx(lr1, rel=1e-12)
+    assert optim.decayed_lr(lr0, lr1, S, 10 * S) == pytest.approx(lr1, rel=1e-12)
+    r = [optim.decayed_lr(lr0, lr1, S, t + 1) / optim.decayed_lr(lr0, lr1, S, t) for t in (1, 500, 59_999)]
+    assert r[0] == pytest.approx(r[1], rel=1e-9) and r[1] == pytest.approx(r[2], rel=1e-9)
+    assert r[0] == pytest.approx((lr1 / lr0) ** (1 / S), rel=1e-12)
+    assert optim.decayed_lr(lr0, lr1, 0, 123) == lr0
