@@ -257,7 +257,13 @@ typedef struct gftorf_adam_group {
     float* m;      /* first moment, same size, start at 0  */
     float* v;      /* second moment, same size, start at 0 */
     int64_t n;
-    float lr;
+    float lr;      /* learning rate (at step 1 when decaying)                 */
+    float lr_final;        /* with decay_steps > 0: the rate from step decay_steps + 1 on */
+    int32_t decay_steps;   /* 0: constant lr; else lr (lr_final / lr)^(min(t - 1, decay_steps) / decay_steps)
+                              at 1-based step t (paper §4: the network's rate, 8e-4 to
+                              1.6e-6 over 60K iterations), computed on the device from
+                              the step counter, so a replayed graph follows the schedule */
+    int32_t reserved;      /* must be 0 */
 } gftorf_adam_group;
 
 /* Adam (paper §4: beta = (0.9, 0.999), eps = 1e-15, per-group learning

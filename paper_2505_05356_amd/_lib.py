@@ -69,7 +69,8 @@ class StatusC(ctypes.Structure):
 
 class AdamGroupC(ctypes.Structure):
     _fields_ = [("param", c_void_p), ("grad", c_void_p), ("m", c_void_p), ("v", c_void_p),
-                ("n", c_int64), ("lr", c_float)]
+                ("n", c_int64), ("lr", c_float), ("lr_final", c_float), ("decay_steps", c_int32),
+                ("reserved", c_int32)]
 
 
 class ProfileEntryC(ctypes.Structure):

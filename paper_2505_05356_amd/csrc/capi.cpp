@@ -327,6 +327,10 @@ int gftorf_adam_step(const gftorf_adam_group* groups, int32_t n_groups, int32_t*
     for (int i = 0; i < n_groups; ++i)
         if (groups[i].n < 0 || (groups[i].n > 0 && (!groups[i].param || !groups[i].grad || !groups[i].m || !groups[i].v)))
             return fail(GFTORF_EINVAL, "bad Adam group " + std::to_string(i));
+    for (int i = 0; i < n_groups; ++i)
+        if (groups[i].decay_steps < 0 || groups[i].reserved != 0 ||
+            (groups[i].decay_steps > 0 && !(groups[i].lr > 0.f && groups[i].lr_final > 0.f)))
+            return fail(GFTORF_EINVAL, "bad learning-rate decay in Adam group " + std::to_string(i));
     (void)hipGetLastError();
     gft::launch_adam(groups, n_groups, step, beta1, beta2, eps, static_cast<hipStream_t>(stream));
     hipError_t e = hipGetLastError();

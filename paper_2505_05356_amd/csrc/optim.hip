@@ -41,6 +41,8 @@ struct AdamArgs {
     float* v[kMaxGroups];
     long long start[kMaxGroups + 1];
     float lr[kMaxGroups];
+    float lr_final[kMaxGroups];
+    int decay[kMaxGroups];
     int n_groups;
     float b1, b2, eps;
 };
@@ -54,10 +56,20 @@ __global__ void __launch_bounds__(256) k_adam(AdamArgs A, const int32_t* __restr
     const float bc1 = 1.0f - powf(A.b1, (float)t);
     const float bc2 = 1.0f - powf(A.b2, (float)t);
     const long long total = A.start[A.n_groups];
+    int lr_g = -1;   // group whose (possibly decayed) rate is in lr
+    float lr = 0.0f;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (long long)gridDim.x * blockDim.x) {
         int gi = 0;
         while (i >= A.start[gi + 1]) ++gi;
+        if (gi != lr_g) {
+            lr_g = gi;
+            lr = A.lr[gi];
+            if (A.decay[gi] > 0) {
+                const float s = (float)min(t - 1, A.decay[gi]) / (float)A.decay[gi];
+                lr = A.lr[gi] * powf(A.lr_final[gi] / A.lr[gi], s);
+            }
+        }
         const long long j = i - A.start[gi];
         const float g = A.g[gi][j];
         const float m = A.b1 * A.m[gi][j] + (1.0f - A.b1) * g;
@@ -66,7 +78,7 @@ __global__ void __launch_bounds__(256) k_adam(AdamArgs A, const int32_t* __restr
         A.v[gi][j] = v;
         const float mh = m / bc1;
         const float vh = v / bc2;
-        A.p[gi][j] -= A.lr[gi] * mh / (sqrtf(vh) + A.eps);
+        A.p[gi][j] -= lr * mh / (sqrtf(vh) + A.eps);
     }
 }
 
@@ -129,6 +141,8 @@ void launch_adam(const gftorf_adam_group* groups, int32_t n_groups, int32_t* ste
             A.m[i] = g.m;
             A.v[i] = g.v;
             A.lr[i] = g.lr;
+            A.lr_final[i] = g.lr_final;
+            A.decay[i] = g.decay_steps;
             A.start[i + 1] = A.start[i] + g.n;
         }
         long long blocks = (A.start[ng] + 256 * 4 - 1) / (256 * 4);

@@ -48,6 +48,7 @@ def test_struct_sizes_match_header(lib):
     assert ctypes.sizeof(_lib.GaussiansC) == 8 * 14
     assert ctypes.sizeof(_lib.GaussiansGradC) == 8 * 12
     assert ctypes.sizeof(_lib.MlpConfigC) == 24
+    assert ctypes.sizeof(_lib.AdamGroupC) == 56
     assert _lib.FRAME_FLOATS * 4 == 160
 
 

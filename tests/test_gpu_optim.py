@@ -178,3 +178,38 @@ def test_graph_replay_equals_eager():
             close = np.abs(a - b) <= 1e-5 * np.abs(a) + 1e-7
             assert close.mean() >= 0.999, (k, close.mean())
     assert not graph.status()["overflow"]
+
+
+def test_adam_with_learning_rate_decay():
+    # §4's exponential decay computed on the device from the step counter: a
+    # decaying group and a constant one, at steps inside and past the horizon
+    lib = _lib.load()
+    rng = np.random.default_rng(4)
+    n = 500
+    for t_new, S in ((3, 4), (9, 4)):
+        p0 = rng.normal(size=(2, n)).astype(np.float32)
+        g = rng.normal(size=(2, n)).astype(np.float32) * 1e-2
+        dp = [torch.from_numpy(p0[i].copy()).cuda() for i in range(2)]
+        dg = [torch.from_numpy(g[i]).cuda() for i in range(2)]
+        dm = [torch.zeros(n, device="cuda") for _ in range(2)]
+        dv = [torch.zeros(n, device="cuda") for _ in range(2)]
+        groups = (_lib.AdamGroupC * 2)()
+        for i in range(2):
+            groups[i].param, groups[i].grad = dp[i].data_ptr(), dg[i].data_ptr()
+            groups[i].m, groups[i].v = dm[i].data_ptr(), dv[i].data_ptr()
+            groups[i].n, groups[i].lr = n, 8e-4
+        groups[0].lr_final, groups[0].decay_steps = 8e-6, S
+        step = torch.full((1,), t_new - 1, dtype=torch.int32, device="cuda")
+        _lib.check(lib.gftorf_adam_step(groups, 2, _p(step), 0.9, 0.999, 1e-15, _s()))
+        torch.cuda.synchronize()
+        assert step.item() == t_new
+        for i in range(2):
+            lr = ooptim.decayed_lr(8e-4, 8e-6, S, t_new) if i == 0 else 8e-4
+            exp, _, _ = ooptim.adam_step(p0[i], g[i], np.zeros(n), np.zeros(n), t_new, lr)
+            got = dp[i].cpu().numpy().astype(np.float64)
+            ulp = np.spacing(np.abs(p0[i])).astype(np.float64)
+            assert np.all(np.abs((got - p0[i]) - (exp - p0[i])) <= 1e-4 * np.abs(exp - p0[i]) + ulp), (t_new, i)
+    bad = (_lib.AdamGroupC * 1)()
+    bad[0].n, bad[0].lr, bad[0].decay_steps = 0, 0.0, 5
+    assert lib.gftorf_adam_step(bad, 1, _p(torch.zeros(1, dtype=torch.int32, device="cuda")),
+                                0.9, 0.999, 1e-15, _s()) == _lib.EINVAL
