@@ -48,10 +48,10 @@ SORT_BYTES_PER_KEY_PASS = 16  # read key + value, write key + value (4 B each)
 # by what the same counter reads for a plain device copy of known size
 # (--calibration-copy-mib).  A figure holds only for the kernel source it was
 # measured on: the sha256 of the listed files must match, else traffic is null.
-FETCH_SCALE, WRITE_SCALE = 1048576 / 524321, 1048576 / 1048576   # 1 GiB copy: FETCH 524321 KiB, WRITE 1048576 KiB
+FETCH_SCALE, WRITE_SCALE = 1048576 / 524316, 1048576 / 1048576   # 1 GiB copy: FETCH 524316 KiB, WRITE 1048576 KiB
 TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
-TRAFFIC_SHA256 = "c95cf043e538bc4a4cb3f78e364ea03df3f983b17522ae13f24c65284a11ba62"
-TRAFFIC_KIB = {"k_composite_bwd": (52024, 51901), "k_composite_fwd": (4817, 96125)}   # KiB per launch
+TRAFFIC_SHA256 = "a946a99b38e9846fe40c47ae97c55287ff9a258d3eb89e0466e986041a02ff2e"
+TRAFFIC_KIB = {"k_composite_bwd": (52019, 51901), "k_composite_fwd": (4815, 96136)}   # KiB per launch
 
 
 def parse():
@@ -139,9 +139,9 @@ def bench_train_step(args):
 
 # the same for the deformation network's kernels (k_mlp_dw: its three launches together)
 MLP_TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
-MLP_TRAFFIC_SHA256 = "c649c4cec792a0d9190eb04c2584c4bec1f1075c0b447c7d365bc8856c0b062a"
-MLP_TRAFFIC_KIB = {"k_mlp_fwd": (198992, 6718750), "k_mlp_bwd": (3407343, 6468750),
-                   "k_mlp_dw": (10715462, 278404)}   # KiB per launch, 1.6M rows
+MLP_TRAFFIC_SHA256 = "fdf52f0f1d098d0d0713829107b723a32c12c4cf35a8561511aac01ce5cba235"
+MLP_TRAFFIC_KIB = {"k_mlp_fwd": (197822, 6718750), "k_mlp_bwd": (3407892, 6468750),
+                   "k_mlp_dw": (10819119, 278298)}   # KiB per launch, 1.6M rows
 
 
 def traffic_bytes(name, files=TRAFFIC_FILES, sha=TRAFFIC_SHA256, table=TRAFFIC_KIB):

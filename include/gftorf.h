@@ -217,7 +217,10 @@ int gftorf_render_bwd(const gftorf_gaussians* g, const gftorf_frame* frames, int
                       void* ws, size_t ws_bytes, void* stream);
 
 /* Synchronises `stream`, then copies the status of the last forward that
- * used `ws` into *out (host).  Returns GFTORF_EOVERFLOW if it overflowed. */
+ * used `ws` into *out (host).  Returns GFTORF_EOVERFLOW if it overflowed.
+ * n_evaluated / n_composited are summed here from the forward's per-tile
+ * counts (zero if no forward has filled this workspace since its first 64
+ * bytes were cleared). */
 int gftorf_read_status(const void* ws, gftorf_status* out, void* stream);
 
 /* Introspection of the forward's binning, for tests and tools: copies

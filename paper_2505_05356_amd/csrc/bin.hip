@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(256) k_tile_colscan(Params P, const uint32_t* 
 __global__ void __launch_bounds__(1024) k_tile_keyscan(const uint32_t* __restrict__ tcount, long long K,
                                                        unsigned long long cap, uint2* __restrict__ ranges,
                                                        const uint32_t* __restrict__ nf_block, int n_blocks,
-                                                       Status* status) {
+                                                       unsigned long long wcount_off, Status* status) {
     __shared__ unsigned long long scratch[17];
     unsigned long long carry = 0;
     // 4 consecutive tiles per thread, 4096 per round
@@ -479,6 +479,9 @@ __global__ void __launch_bounds__(1024) k_tile_keyscan(const uint32_t* __restric
         status->cap = cap;
         status->overflow = carry > cap ? 1u : 0u;
         status->nonfinite = nf_sum;
+        status->wcount_off = wcount_off;
+        status->n_items = (unsigned long long)K;
+        status->magic = kStatusMagic;
     }
 }
 
@@ -565,7 +568,9 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
         ProfScope _p("k_tile_keyscan", s);
         hipLaunchKernelGGL(k_tile_keyscan, dim3(1), dim3(1024), 0, s, w.tcount,
                            (long long)P.F * P.n_tiles, (unsigned long long)P.cap, w.ranges, w.nf_block,
-                           (int)((P.n + 255) / 256), w.status);
+                           (int)((P.n + 255) / 256),
+                           (unsigned long long)(reinterpret_cast<char*>(w.wcount) - reinterpret_cast<char*>(w.status)),
+                           w.status);
     }
     {
         ProfScope _p("k_tile_place", s);

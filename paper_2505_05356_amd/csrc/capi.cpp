@@ -266,8 +266,22 @@ int gftorf_read_status(const void* ws, gftorf_status* out, void* stream) {
     out->max_pairs = (int64_t)st.cap;
     out->overflow = (int32_t)st.overflow;
     out->nonfinite = (int32_t)st.nonfinite;
-    out->n_evaluated = (int64_t)st.n_eval;
-    out->n_composited = (int64_t)st.n_comp;
+    out->n_evaluated = out->n_composited = 0;
+    // the forward's per-work-item counts, summed here (the stream is idle)
+    if (st.magic == gft::kStatusMagic && st.n_items > 0 && st.n_items <= (1ull << 26) &&
+        st.wcount_off >= sizeof(gft::Status) && st.wcount_off % 8 == 0 && st.wcount_off < (1ull << 44)) {
+        std::vector<uint2> wc((size_t)st.n_items);
+        e = hipMemcpy(wc.data(), static_cast<const char*>(ws) + st.wcount_off, sizeof(uint2) * wc.size(),
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "gftorf_read_status");
+        unsigned long long ev = 0, co = 0;
+        for (const uint2& c : wc) {
+            ev += c.x;
+            co += c.y;
+        }
+        out->n_evaluated = (int64_t)ev;
+        out->n_composited = (int64_t)co;
+    }
     if (st.overflow) return fail(GFTORF_EOVERFLOW, "pairs exceeded max_pairs: " + std::to_string(st.n_pairs));
     return GFTORF_OK;
 }

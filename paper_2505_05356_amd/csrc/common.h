@@ -47,10 +47,15 @@ struct Status {
     unsigned long long cap;       // capacity (max_pairs)
     unsigned int overflow;
     unsigned int nonfinite;
-    unsigned long long n_eval;   // (pixel, entry) alpha evaluations of the forward
-    unsigned long long n_comp;   // (pixel, entry) pairs composited by the forward
-    unsigned int pad[6];
+    unsigned long long wcount_off;   // byte offset of the forward's per-work-item counts
+    unsigned long long n_items;      // work items (frames x tiles) of the last forward
+    unsigned int magic;              // kStatusMagic once a forward has filled the fields
+    unsigned int pad[5];
 };
+constexpr unsigned int kStatusMagic = 0x47465352u;
+// The (evaluations, composited) counts of every work item are summed on the
+// host by gftorf_read_status, which synchronises anyway, so no forward pays a
+// reduction launch for them.
 
 // Everything a kernel needs to know about a call, passed by value.
 struct Params {

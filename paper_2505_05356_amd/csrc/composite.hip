@@ -224,7 +224,8 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
         }
     }
     {   // workload counters of this work item (algorithmic FLOP accounting);
-        // summed over work items by k_sum_counts, not by same-address atomics
+        // summed over work items on the host by gftorf_read_status, not by
+        // same-address atomics
         __shared__ uint2 wred[BS / 64];
         uint32_t e = n_eval, c = n_comp;
 #pragma unroll
@@ -518,32 +519,6 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
     }
 }
 
-__global__ void __launch_bounds__(1024) k_sum_counts(const uint2* __restrict__ wcount, int n,
-                                                     Status* status) {
-    __shared__ unsigned long long scratch[2][16];
-    unsigned long long e = 0, c = 0;
-#pragma unroll 4
-    for (int i = threadIdx.x; i < n; i += 1024) {
-        e += wcount[i].x;
-        c += wcount[i].y;
-    }
-    e = wave_reduce_sum(e);
-    c = wave_reduce_sum(c);
-    if (lane_id() == 0) {
-        scratch[0][threadIdx.x / 64] = e;
-        scratch[1][threadIdx.x / 64] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long te = 0, tc = 0;
-        for (int q = 0; q < 16; ++q) {
-            te += scratch[0][q];
-            tc += scratch[1][q];
-        }
-        status->n_eval = te;
-        status->n_comp = tc;
-    }
-}
 
 template <int TW, int TH>
 hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w,
@@ -562,10 +537,6 @@ hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& 
         }
     }
 #undef GFT_FWD
-    {
-        ProfScope _q("k_sum_counts", s);
-        hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(1024), 0, s, w.wcount, (int)blocks, w.status);
-    }
     return hipGetLastError();
 }
 

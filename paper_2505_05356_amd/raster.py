@@ -176,6 +176,7 @@ class Workspace:
         off = (-self.buf.data_ptr()) % 256
         self.ptr = self.buf.data_ptr() + off
         self.nbytes = size
+        self.buf[off:off + 64].zero_()   # status header: no forward has run yet
 
     def grow(self, pairs: int):
         self._alloc(int(pairs * 1.25) + 4096)
