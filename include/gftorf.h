@@ -365,6 +365,19 @@ int gftorf_mlp_bwd(const gftorf_mlp_config* cfg, const float* params, const floa
                    const float* times, int32_t n_times, const float* d_delta, float* d_params,
                    float* d_x0, void* ws, size_t ws_bytes, void* stream);
 
+/* The same with the times read on the device from frames[0 .. n_frames)
+ * (.time of each descriptor), so a replayed graph follows the frames that
+ * gftorf_select_frames wrote; n_frames <= GFTORF_MLP_MAX_TIMES.  The
+ * backward with accumulate_x0 != 0 ADDS the centre gradient to d_x0 (e.g.
+ * the rasterizer's gradient of the same centres) instead of overwriting. */
+int gftorf_mlp_fwd_frames(const gftorf_mlp_config* cfg, const float* params, const float* x0,
+                          int64_t n, const gftorf_frame* frames, int32_t n_frames, float* delta,
+                          int32_t save, void* ws, size_t ws_bytes, void* stream);
+int gftorf_mlp_bwd_frames(const gftorf_mlp_config* cfg, const float* params, const float* x0,
+                          int64_t n, const gftorf_frame* frames, int32_t n_frames,
+                          const float* d_delta, float* d_params, float* d_x0, int32_t accumulate_x0,
+                          void* ws, size_t ws_bytes, void* stream);
+
 /* Eq. 7 with the deformation network (paper §4): the network is evaluated at
  * integer timesteps only, and a raw frame between two of them takes the
  * straight line between the deformed positions.  With delta_steps

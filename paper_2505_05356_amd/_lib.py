@@ -21,6 +21,7 @@ MAX_FREQ = 4
 MAX_PHASE = 4
 MAX_QUAD = 16
 FRAME_FLOATS = 9 + 3 + 4 + 1 + 3 + MAX_QUAD + 4   # 40: ... t_lo, t_hi, quad_mask, reserved
+FRAME_TIME = 9 + 3 + 4                            # column of .time
 
 OK, EINVAL, ENOWS, EHIP, EOVERFLOW = 0, -1, -2, -3, -4
 
@@ -108,6 +109,10 @@ _SIGS = {
                                  c_int32, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
     "gftorf_mlp_bwd": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, POINTER(c_float),
                                  c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gftorf_mlp_fwd_frames": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, c_void_p, c_int32,
+                                        c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
+    "gftorf_mlp_bwd_frames": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, c_void_p, c_int32,
+                                        c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
     "gftorf_blend_offsets": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, c_int32, POINTER(c_int32),
                                        c_void_p, c_void_p]),
     "gftorf_blend_offsets_bwd": (c_int32, [c_void_p, c_int32, c_int64, c_void_p, POINTER(c_int32), c_int32,

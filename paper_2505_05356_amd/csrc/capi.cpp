@@ -373,12 +373,12 @@ bool mlp_layout(const gftorf_mlp_config* cfg, int64_t n, int32_t n_times, bool t
 }
 
 int mlp_call(const gftorf_mlp_config* cfg, const float* params, const float* x0, int64_t n,
-             const float* times, int32_t n_times, void* ws, size_t ws_bytes, bool training,
-             gft::mlp::Layout* L, gft::mlp::Call* c) {
+             const float* times, const gftorf_frame* frames, int32_t n_times, void* ws,
+             size_t ws_bytes, bool training, gft::mlp::Layout* L, gft::mlp::Call* c) {
     if (!mlp_layout(cfg, n, n_times, training, L))
         return fail(GFTORF_EINVAL, "unsupported network: width must be 256, depth 8, "
                                    "3 (1 + 2 L_x) + 1 + 2 L_t <= 96, 1 <= n_times <= 64");
-    if (!params || !x0 || !times || !ws) return fail(GFTORF_EINVAL, "NULL pointer");
+    if (!params || !x0 || (!times && !frames) || !ws) return fail(GFTORF_EINVAL, "NULL pointer");
     if (!std::isfinite(cfg->pos_scale) || !std::isfinite(cfg->time_scale))
         return fail(GFTORF_EINVAL, "non-finite input scale");
     if (ws_bytes < L->bytes) return fail(GFTORF_ENOWS, "workspace too small for the network");
@@ -387,7 +387,8 @@ int mlp_call(const gftorf_mlp_config* cfg, const float* params, const float* x0,
     c->x0 = x0;
     c->sx = cfg->pos_scale;
     c->st = cfg->time_scale;
-    for (int t = 0; t < gft::mlp::kMaxTimes; ++t) c->times[t] = t < n_times ? times[t] : 0.f;
+    for (int t = 0; t < gft::mlp::kMaxTimes; ++t) c->times[t] = (times && t < n_times) ? times[t] : 0.f;
+    c->frames = times ? nullptr : frames;
     c->ws = static_cast<char*>(ws);
     return GFTORF_OK;
 }
@@ -409,7 +410,7 @@ int gftorf_mlp_fwd(const gftorf_mlp_config* cfg, const float* params, const floa
                    size_t ws_bytes, void* stream) {
     gft::mlp::Layout L;
     gft::mlp::Call c;
-    const int rc = mlp_call(cfg, params, x0, n, times, n_times, ws, ws_bytes, save != 0, &L, &c);
+    const int rc = mlp_call(cfg, params, x0, n, times, nullptr, n_times, ws, ws_bytes, save != 0, &L, &c);
     if (rc != GFTORF_OK) return rc;
     if (!delta) return fail(GFTORF_EINVAL, "NULL pointer");
     (void)hipGetLastError();
@@ -422,12 +423,42 @@ int gftorf_mlp_bwd(const gftorf_mlp_config* cfg, const float* params, const floa
                    float* d_x0, void* ws, size_t ws_bytes, void* stream) {
     gft::mlp::Layout L;
     gft::mlp::Call c;
-    const int rc = mlp_call(cfg, params, x0, n, times, n_times, ws, ws_bytes, true, &L, &c);
+    const int rc = mlp_call(cfg, params, x0, n, times, nullptr, n_times, ws, ws_bytes, true, &L, &c);
     if (rc != GFTORF_OK) return rc;
     if (!d_delta || !d_params) return fail(GFTORF_EINVAL, "NULL pointer");
     (void)hipGetLastError();
-    const hipError_t e = gft::mlp::launch_bwd(L, c, d_delta, d_params, d_x0, static_cast<hipStream_t>(stream));
+    const hipError_t e = gft::mlp::launch_bwd(L, c, d_delta, d_params, d_x0, false, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_mlp_bwd");
+}
+
+int gftorf_mlp_fwd_frames(const gftorf_mlp_config* cfg, const float* params, const float* x0,
+                          int64_t n, const gftorf_frame* frames, int32_t n_frames, float* delta,
+                          int32_t save, void* ws, size_t ws_bytes, void* stream) {
+    gft::mlp::Layout L;
+    gft::mlp::Call c;
+    if (!frames) return fail(GFTORF_EINVAL, "NULL pointer");
+    const int rc = mlp_call(cfg, params, x0, n, nullptr, frames, n_frames, ws, ws_bytes, save != 0, &L, &c);
+    if (rc != GFTORF_OK) return rc;
+    if (!delta) return fail(GFTORF_EINVAL, "NULL pointer");
+    (void)hipGetLastError();
+    const hipError_t e = gft::mlp::launch_fwd(L, c, delta, save != 0, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_mlp_fwd_frames");
+}
+
+int gftorf_mlp_bwd_frames(const gftorf_mlp_config* cfg, const float* params, const float* x0,
+                          int64_t n, const gftorf_frame* frames, int32_t n_frames,
+                          const float* d_delta, float* d_params, float* d_x0, int32_t accumulate_x0,
+                          void* ws, size_t ws_bytes, void* stream) {
+    gft::mlp::Layout L;
+    gft::mlp::Call c;
+    if (!frames) return fail(GFTORF_EINVAL, "NULL pointer");
+    const int rc = mlp_call(cfg, params, x0, n, nullptr, frames, n_frames, ws, ws_bytes, true, &L, &c);
+    if (rc != GFTORF_OK) return rc;
+    if (!d_delta || !d_params) return fail(GFTORF_EINVAL, "NULL pointer");
+    (void)hipGetLastError();
+    const hipError_t e = gft::mlp::launch_bwd(L, c, d_delta, d_params, d_x0, accumulate_x0 != 0,
+                                              static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_mlp_bwd_frames");
 }
 
 namespace {

@@ -45,7 +45,8 @@ struct Call {
     const float* params;
     const float* x0;
     float sx, st;
-    float times[kMaxTimes];
+    float times[kMaxTimes];          // host times, or
+    const gftorf_frame* frames;      // device frame descriptors whose .time is read
     char* ws;
 };
 
@@ -62,7 +63,7 @@ hipError_t launch_blend(const Blend& b, const float* steps, const gftorf_frame* 
 hipError_t launch_blend_bwd(const Blend& b, const float* d_frames, const gftorf_frame* frames,
                             float* d_steps, hipStream_t s);
 hipError_t launch_bwd(const Layout& L, const Call& c, const float* d_delta, float* d_params,
-                      float* d_x0, hipStream_t s);
+                      float* d_x0, bool accumulate_x0, hipStream_t s);
 
 }  // namespace mlp
 }  // namespace gft

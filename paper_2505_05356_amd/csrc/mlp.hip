@@ -47,6 +47,7 @@ struct Args {
     int lx, lt;
     float sx, st;
     float times[kMaxTimes];
+    const gftorf_frame* frames;   // if set, time t is frames[t].time (device)
     const bf16* wf[kLayers];
     const bf16* wt[kLayers];
     const float* bias[kLayers];
@@ -98,7 +99,7 @@ __device__ __forceinline__ void row_inputs(const Args& a, int64_t r, float (&xin
     const int t = (int)(r / a.n);
     const int64_t k = r - (int64_t)t * a.n;
     for (int c = 0; c < 3; ++c) xin[c] = a.sx * a.x0[c * a.n + k];
-    xin[3] = a.st * a.times[t];
+    xin[3] = a.st * (a.frames ? a.frames[t].time : a.times[t]);
 }
 
 // acc[r][c] += X[16 r + .][.] * B[col0 + 16 c + .][.] over K: X in LDS
@@ -469,7 +470,7 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(RedArgs r, const float* __re
 }
 
 __global__ void __launch_bounds__(256) k_mlp_dx0(const float* __restrict__ dxr, int64_t n, int T,
-                                                 float* __restrict__ d_x0) {
+                                                 int accumulate, float* __restrict__ d_x0) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= n) return;
     float s0 = 0.f, s1 = 0.f, s2 = 0.f;
@@ -478,6 +479,11 @@ __global__ void __launch_bounds__(256) k_mlp_dx0(const float* __restrict__ dxr, 
         s0 += g[0];
         s1 += g[1];
         s2 += g[2];
+    }
+    if (accumulate) {
+        s0 += d_x0[k];
+        s1 += d_x0[n + k];
+        s2 += d_x0[2 * n + k];
     }
     d_x0[k] = s0;
     d_x0[n + k] = s1;
@@ -567,6 +573,7 @@ Args make_args(const Layout& L, const Call& c) {
     a.sx = c.sx;
     a.st = c.st;
     for (int t = 0; t < kMaxTimes; ++t) a.times[t] = t < L.n_times ? c.times[t] : 0.f;
+    a.frames = c.frames;
     for (int l = 0; l < kLayers; ++l) {
         a.wf[l] = reinterpret_cast<const bf16*>(c.ws + L.wf[l]);
         a.wt[l] = reinterpret_cast<const bf16*>(c.ws + L.wt[l]);
@@ -679,7 +686,7 @@ hipError_t launch_blend_bwd(const Blend& b, const float* d_frames, const gftorf_
 }
 
 hipError_t launch_bwd(const Layout& L, const Call& c, const float* d_delta, float* d_params,
-                      float* d_x0, hipStream_t s) {
+                      float* d_x0, bool accumulate_x0, hipStream_t s) {
     const Args a = make_args(L, c);
     float* dxr = reinterpret_cast<float*>(c.ws + L.dxr);
     {
@@ -721,7 +728,7 @@ hipError_t launch_bwd(const Layout& L, const Call& c, const float* d_delta, floa
                            d.part, d_params);
         if (d_x0)
             hipLaunchKernelGGL(k_mlp_dx0, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, s, dxr, L.n,
-                               L.n_times, d_x0);
+                               L.n_times, accumulate_x0 ? 1 : 0, d_x0);
     }
     return hipGetLastError();
 }

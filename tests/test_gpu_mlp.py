@@ -330,3 +330,100 @@ def test_render_offsets_with_quartets_and_spherical_harmonics():
     res_b = run_gpu(gd, frames, cfg, upstream=up)
     for k, r in ref_b["grads"].items():
         assert_grads_close(res_b["grads"][k], r, f"combined/{k}")
+
+
+def _net_step(seed=3, decay_steps=4):
+    # the optimisation step's scene with a deformation network: frames 0 and 1
+    # of a 6-frame sequence, step-0 backgrounds, network weights of moderate size
+    from paper_2505_05356_amd import raster, step as gstep
+    from tests.test_gpu_optim import _train_setup
+    g, cfg, seq, tr, tq, bg = _train_setup(seed=seed)
+    theta = scenes.mlp_params(seed=seed + 20, last_std=0.02, bias_std=0.05)
+    net = deform.DeformNet(g.n, 2, pos_scale=SX, time_scale=ST)
+    params = raster.to_device_params(g, "cuda", static=False)
+    ts = gstep.TrainStep(params, raster.pack_frames(seq, cfg), torch.from_numpy(tr).cuda(),
+                         torch.from_numpy(tq).cuda(), cfg, batch=2, bg_table=torch.from_numpy(bg).cuda(),
+                         net=net, net_params=torch.from_numpy(theta).cuda(), net_decay_steps=decay_steps)
+    return ts, g, cfg, seq, tr, tq, bg, theta
+
+
+def test_train_step_with_network():
+    # one optimisation step with the network in the loop: the offsets at the
+    # frames' device times and the loss against the oracle; the gradients
+    # against the same chain called by hand through the separately checked
+    # entry points (network at host times, rasterizer forward/backward); the
+    # network's Adam update against the oracle's Adam
+    from oracle import optim as ooptim
+    from paper_2505_05356_amd import raster
+    ts, g, cfg, seq, tr, tq, bg, theta = _net_step()
+    p0 = {k: v.clone() for k, v in ts.params.items() if v is not None}
+    th0 = ts.net_params.clone()
+    ts.step()
+    torch.cuda.synchronize()
+    assert ts.step_counter.item() == 1
+    times = [seq[0].time, seq[1].time]
+    ref_delta = omlp.offsets(theta, g.mean, times, SX, ST, decide="bf16")
+    assert np.abs(ref_delta).max() > 1e-3
+    _close(ts.delta.cpu().numpy(), ref_delta, "step/delta", allowed=0.0)
+    # loss: the oracle renders with its own offsets; the GPU's offsets differ
+    # by the network's bfloat16 error, which moves the loss by at most
+    # sum |d loss / d delta| |delta_gpu - delta_ref| to first order
+    frames = [dataclasses.replace(seq[b], bg_rgb=bg[0, b, :3], bg_quad=bg[0, b, 3:].reshape(1, 4))
+              for b in range(2)]
+    gd = dataclasses.replace(g, delta=np.ascontiguousarray(ref_delta.astype(np.float32)))
+    out = oref.render(gd, frames, cfg)
+    loss_ref, d_rgb, d_quad = ooptim.l2_loss_grad(out["rgb"], out["quad"], tr[:2], tq[:2], 1.0)
+    ref_b = oref.render(gd, frames, cfg, upstream={"rgb": d_rgb, "quad": d_quad, "depth": np.zeros((2, 32, 40))})
+    first = np.sum(np.abs(ref_b["grads"]["delta"]) * np.abs(ts.delta.cpu().numpy() - ref_delta))
+    assert abs(ts.loss.item() - loss_ref) <= 2.0 * first + 1e-4 * loss_ref
+    # the chain by hand on the step's own frames and loss gradients
+    fdev = ts.frames
+    d_fixed = ts.net.forward(th0, p0["mean"], times)
+    np.testing.assert_array_equal(d_fixed.cpu().numpy(), ts.delta.cpu().numpy())
+    p_in = dict(p0, delta=d_fixed)
+    ws = raster.Workspace(g.n, 2, cfg)
+    o2 = raster.forward(p_in, fdev, cfg, ws)
+    for k in ("rgb", "quad"):
+        np.testing.assert_allclose(o2[k].cpu().numpy(), ts.out[k].cpu().numpy(), rtol=1e-6, atol=1e-7)
+    gr = raster.backward(p_in, fdev, cfg, ws, o2, ts.d_rgb, ts.d_quad, None)
+    ts.net.forward(th0, p0["mean"], times)
+    d_params, d_x0 = ts.net.backward(th0, p0["mean"], times, gr["delta"])
+    torch.cuda.synchronize()
+    assert_grads_close(ts.net_grad.cpu().numpy(), d_params.cpu().numpy(), "step/net grad", rtol=1e-4)
+    assert_grads_close(ts.grads["mean"].cpu().numpy(), (gr["mean"] + d_x0).cpu().numpy(), "step/mean", rtol=1e-4)
+    for k in ("vel", "scale", "opacity_logit", "rgb", "albedo"):
+        assert_grads_close(ts.grads[k].cpu().numpy(), gr[k].cpu().numpy(), f"step/{k}", rtol=1e-4)
+    # the network's Adam group: first step at the undecayed rate
+    gk = ts.net_grad.cpu().numpy().astype(np.float64)
+    exp, _, _ = ooptim.adam_step(theta, gk, np.zeros_like(gk), np.zeros_like(gk), 1,
+                                 ooptim.decayed_lr(8e-4, 1.6e-6, 4, 1))
+    np.testing.assert_allclose(ts.net_params.cpu().numpy(), exp, rtol=1e-6, atol=8e-4 * 1e-4)
+
+
+def test_train_step_with_network_graph_replay():
+    # the step with the network captured as one graph and replayed: equal to
+    # eager steps (up to the rasterizer's atomic summation order), the
+    # network's rate decaying from the device step counter
+    eager = _net_step(seed=5)[0]
+    graph = _net_step(seed=5)[0]
+    graph.capture()
+    from oracle import optim as ooptim
+    for it in range(4):
+        eager.step()
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()
+        assert graph.step_counter.item() == eager.step_counter.item() == it + 1
+        assert graph.loss.item() == pytest.approx(eager.loss.item(), rel=1e-5)
+        assert_grads_close(graph.net_grad.cpu().numpy(), eager.net_grad.cpu().numpy(),
+                           f"replay {it} net grad", rtol=1e-4)
+        assert_grads_close(graph.grads["mean"].cpu().numpy(), eager.grads["mean"].cpu().numpy(),
+                           f"replay {it} mean grad", rtol=1e-4)
+        # an entry whose gradient sits at rounding level may move by up to 2 lr
+        a, b = eager.net_params.cpu().numpy(), graph.net_params.cpu().numpy()
+        bound = sum(2.01 * ooptim.decayed_lr(8e-4, 1.6e-6, 4, s) for s in range(1, it + 2))
+        assert np.abs(a - b).max() <= bound
+        close = np.abs(a - b) <= 1e-5 * np.abs(a) + 1e-7
+        assert close.mean() >= 0.999, close.mean()
+        np.testing.assert_array_equal(graph.frames.cpu().numpy(), eager.frames.cpu().numpy())
+    assert not graph.status()["overflow"]
