@@ -69,7 +69,8 @@ def gaussian_2d(g, k, frame, cfg):
 
 def render_frame(g, frame, cfg):
     """Returns dict of nested lists: rgb[3][H][W], quad[NQ][H][W],
-    depth[H][W], T_final[H][W], n_contrib[H][W]."""
+    depth[H][W], T_final[H][W], n_contrib[H][W], n_evaluated[H][W] (entries
+    whose alpha the pixel computes) and n_composited[H][W]."""
     H, W = cfg.height, cfg.width
     gs = [gaussian_2d(g, k, frame, cfg) for k in range(g.n)]
     NQ = cfg.n_quad
@@ -79,7 +80,8 @@ def render_frame(g, frame, cfg):
     res = dict(rgb=[[[0.0] * W for _ in range(H)] for _ in range(3)],
                quad=[[[0.0] * W for _ in range(H)] for _ in range(NQ)],
                depth=[[0.0] * W for _ in range(H)], T_final=[[0.0] * W for _ in range(H)],
-               n_contrib=[[0] * W for _ in range(H)])
+               n_contrib=[[0] * W for _ in range(H)], n_evaluated=[[0] * W for _ in range(H)],
+               n_composited=[[0] * W for _ in range(H)])
     for j in range(H):
         for i in range(W):
             tx, ty = i // cfg.tile_w, j // cfg.tile_h
@@ -100,8 +102,10 @@ def render_frame(g, frame, cfg):
             dep = 0.0
             quad = [0.0] * NQ
             last = 0
+            n_eval = n_comp = 0
             for pos, (_, k) in enumerate(cand):
                 q = gs[k]
+                n_eval += 1
                 dx, dy = x - q["u"], y - q["v"]
                 power = -0.5 * (q["A"] * dx * dx + q["C"] * dy * dy) - q["B"] * dx * dy
                 alpha = min(cfg.alpha_max, q["o"] * math.exp(power))
@@ -120,6 +124,7 @@ def render_frame(g, frame, cfg):
                         m += 1
                 T = nt
                 last = pos + 1
+                n_comp += 1
             for ch in range(3):
                 res["rgb"][ch][j][i] = rgb[ch] + bgr[ch] * T
             for m in range(NQ):
@@ -127,4 +132,6 @@ def render_frame(g, frame, cfg):
             res["depth"][j][i] = dep
             res["T_final"][j][i] = T
             res["n_contrib"][j][i] = last
+            res["n_evaluated"][j][i] = n_eval
+            res["n_composited"][j][i] = n_comp
     return res

@@ -169,7 +169,7 @@ def _raw_alpha(q, sel, px, py):
     return q["o"][sel][:, None] * torch.exp(power)
 
 
-def visit_pass(q, sel, px, py, inside, cfg, flag_rel=(1e-5, 1e-4), chunk=1024):
+def visit_pass(q, sel, px, py, inside, cfg, flag_rel=(1e-5, 1e-4), chunk=1024, counts=None):
     """Per-pixel walk over one tile list without gradients.
 
     Returns (active [K,P] bool, K, n_contrib [P], flagged [P]).  K is the list
@@ -177,7 +177,9 @@ def visit_pass(q, sel, px, py, inside, cfg, flag_rel=(1e-5, 1e-4), chunk=1024):
     pixel.  `flagged` marks pixels where some skip / clamp / stop predicate
     lies within the relative window flag_rel = (alpha window, T window) of
     its threshold, i.e. where a float32 evaluation may legitimately decide
-    differently.
+    differently.  With a dict `counts`, counts["n_evaluated"] [P] is the
+    number of entries whose alpha each pixel evaluates: every entry up to and
+    including the one that stops it (the whole list if none does).
     """
     amin, amax, tmin = _s(cfg.alpha_min), _s(cfg.alpha_max), _s(cfg.T_min)
     ea, et = flag_rel
@@ -186,6 +188,7 @@ def visit_pass(q, sel, px, py, inside, cfg, flag_rel=(1e-5, 1e-4), chunk=1024):
     T = np.ones(P)
     done = ~inside.copy()
     ncontrib = np.zeros(P, np.int64)
+    n_eval = np.zeros(P, np.int64)
     flagged = np.zeros(P, bool)
     active_rows = []
     K = 0
@@ -197,6 +200,7 @@ def visit_pass(q, sel, px, py, inside, cfg, flag_rel=(1e-5, 1e-4), chunk=1024):
                 k = c0 + r
                 a = alpha[r]
                 live = ~done
+                n_eval += live
                 flagged |= live & (np.abs(a - amin) <= ea * amin) & (amin > 0)
                 flagged |= live & (np.abs(raw[r] - amax) <= ea * amax)
                 cons = live & (a >= amin)
@@ -215,6 +219,8 @@ def visit_pass(q, sel, px, py, inside, cfg, flag_rel=(1e-5, 1e-4), chunk=1024):
             if done.all():
                 break
     active = np.stack(active_rows) if active_rows else np.zeros((0, P), bool)
+    if counts is not None:
+        counts["n_evaluated"] = n_eval
     return active, K, ncontrib, flagged
 
 
@@ -260,8 +266,10 @@ def render(g, frames, cfg, tiles=None, upstream=None, flag_rel=(1e-5, 1e-4),
     upstream: None or dict(rgb [F,3,H,W], quad [F,NQ,H,W], depth [F,H,W]).
 
     Returns dict of float64 numpy arrays: rgb, quad, depth, T_final,
-    n_contrib (int64), flagged (bool), computed (bool), pairs (binning),
-    E (sum of n_contrib over computed pixels) and, with `upstream`, grads
+    n_contrib (int64), n_evaluated and n_composited (int64: entries whose
+    alpha the pixel evaluates / that it composites), flagged (bool),
+    computed (bool), pairs (binning), E (sum of n_contrib over computed
+    pixels) and, with `upstream`, grads
     (per parameter field), grad_bg_rgb [F,3], grad_bg_quad [F,NQ] and
     grad2d (per frame dict of per-Gaussian screen-space gradients).
     """
@@ -275,6 +283,8 @@ def render(g, frames, cfg, tiles=None, upstream=None, flag_rel=(1e-5, 1e-4),
     out = dict(rgb=np.full((F, 3, H, Wd), np.nan), quad=np.full((F, NQ, H, Wd), np.nan),
                depth=np.full((F, H, Wd), np.nan), T_final=np.full((F, H, Wd), np.nan),
                n_contrib=np.full((F, H, Wd), -1, np.int64),
+               n_evaluated=np.full((F, H, Wd), -1, np.int64),
+               n_composited=np.full((F, H, Wd), -1, np.int64),
                flagged=np.zeros((F, H, Wd), bool), computed=np.zeros((F, H, Wd), bool),
                pairs=pairs)
     want_grad = upstream is not None
@@ -305,8 +315,9 @@ def render(g, frames, cfg, tiles=None, upstream=None, flag_rel=(1e-5, 1e-4),
             px = torch.from_numpy(gx + 0.5)
             py = torch.from_numpy(gy + 0.5)
             sel_all = torch.from_numpy(lists[tid])
+            counts = {}
             active, K, ncontrib, flagged = visit_pass(leaves, sel_all, px, py, inside, cfg,
-                                                      flag_rel)
+                                                      flag_rel, counts=counts)
             sel = sel_all[:K]
             rgb, quad, depth, Tf, A = composite_tile(leaves, sel, px, py, active, frame, cfg,
                                                      bgr, bgq)
@@ -317,6 +328,8 @@ def render(g, frames, cfg, tiles=None, upstream=None, flag_rel=(1e-5, 1e-4),
             out["depth"][f][yy, xx] = depth.detach().numpy()[ii]
             out["T_final"][f][yy, xx] = Tf.detach().numpy()[ii]
             out["n_contrib"][f][yy, xx] = ncontrib[ii]
+            out["n_evaluated"][f][yy, xx] = counts["n_evaluated"][ii]
+            out["n_composited"][f][yy, xx] = active.sum(axis=0)[ii]
             out["flagged"][f][yy, xx] = flagged[ii]
             out["computed"][f][yy, xx] = True
             if keep_tile_data:

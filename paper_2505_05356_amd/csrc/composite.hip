@@ -440,16 +440,19 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
                 as[k] = (k & 1) ? rp.z : rp.x;
                 ac[k] = (k & 1) ? rp.w : rp.y;
             }
+            // Sums start from their first term (pixel 0), not from 0 + term:
+            // the compiler must keep an addition of +0 (it turns -0 into +0)
             float g[NGP];
 #pragma unroll
-            for (int q = 0; q < NGP; ++q) g[q] = 0.f;
+            for (int q = NG; q < NGP; ++q) g[q] = 0.f;
+            auto put = [](float& acc, float term, int i) { acc = i == 0 ? term : acc + term; };
             bool any = false;
             // Branch-free per pixel: inactive pixels contribute zero and keep
             // their state (selects instead of divergent blocks, so the field
             // registers are never copied at control-flow joins).
             // The conic and centre gradients only need, per lane (one pixel
             // column, so one dx), sum gq, sum gq dy and sum gq dy^2
-            float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+            float p0, p1, p2;
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
                 const float G = __builtin_amdgcn_exp2f(qe[i]);
@@ -464,40 +467,40 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
                 const float Ti = T[i] * rom;
                 const float T2 = Ti * Ti;
                 const float u = gr[i][0] * r2.x + gr[i][1] * r2.y + gr[i][2] * r2.z + gd[i] * r2.w;
-                float v = 0.f;
+                float v = gS[i][0] * as[0] + gC[i][0] * ac[0];
 #pragma unroll
-                for (int k = 0; k < NF; ++k) v += gS[i][k] * as[k] + gC[i][k] * ac[k];
+                for (int k = 1; k < NF; ++k) v += gS[i][k] * as[k] + gC[i][k] * ac[k];
                 const float dA = Ti * u + T2 * v - rom * A[i];
                 T[i] = Ti;
                 const float w1 = ae * Ti;
                 const float w2 = ae * T2;
                 A[i] += w1 * u + w2 * (2.0f * v);
-                g[6] += w1 * gr[i][0];
-                g[7] += w1 * gr[i][1];
-                g[8] += w1 * gr[i][2];
-                g[9] += w1 * gd[i];
+                put(g[6], w1 * gr[i][0], i);
+                put(g[7], w1 * gr[i][1], i);
+                put(g[8], w1 * gr[i][2], i);
+                put(g[9], w1 * gd[i], i);
 #pragma unroll
                 for (int k = 0; k < NF; ++k) {
-                    g[10 + 2 * k] += w2 * gS[i][k];
-                    g[11 + 2 * k] += w2 * gC[i][k];
+                    put(g[10 + 2 * k], w2 * gS[i][k], i);
+                    put(g[11 + 2 * k], w2 * gC[i][k], i);
                 }
                 // alpha = o 2^q unless clamped (then alpha has no gradient);
                 // gq = dL/dq / ln 2
                 const float dAe = (act && oG <= amax) ? dA : 0.0f;
                 const float gq = dAe * a;
-                g[5] += G * dAe;                                 // d/do
+                put(g[5], G * dAe, i);                           // d/do
                 const float gy = gq * dy[i];
-                p0 += gq;
-                p1 += gy;
-                p2 += gy * dy[i];
+                put(p0, gq, i);
+                put(p1, gy, i);
+                put(p2, gy * dy[i], i);
             }
             {
                 const float dxl = dx[0];                         // the lane's column
-                g[0] += dxl * p0;                                // sum gx
-                g[1] += p1;                                      // sum gy
-                g[2] += (dxl * dxl) * p0;                        // d/dcA
-                g[3] += dxl * p1;                                // d/dcB
-                g[4] += p2;                                      // d/dcC
+                g[0] = dxl * p0;                                 // sum gx
+                g[1] = p1;                                       // sum gy
+                g[2] = (dxl * dxl) * p0;                         // d/dcA
+                g[3] = dxl * p1;                                 // d/dcB
+                g[4] = p2;                                       // d/dcC
             }
             if (__ballot(any) == 0ull) continue;
             // one reduce-scatter over the wave, then one atomic instruction whose

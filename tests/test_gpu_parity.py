@@ -101,6 +101,28 @@ def test_forward_matches_oracle(name, oracle_cache):
     for k in ("rgb", "quad", "depth", "T_final"):
         assert_images_close(res[k], ref[k], ok, f"{name}/{k}")
     np.testing.assert_array_equal(res["n_contrib"][ok], ref["n_contrib"][ok])
+    _check_workload_counts(res["status"], ref, wl)
+
+
+def _check_workload_counts(status, ref, wl):
+    # the evaluated / composited (pixel, entry) totals that the library reports
+    # (the work measure of the roofline figures) against the oracle's per-pixel
+    # counts: equal on unflagged pixels; a flagged pixel may count anything
+    # from 0 to its tile's list length
+    cfg, F = wl.cfg, len(wl.frames)
+    ok = ~ref["flagged"] & ref["computed"]
+    pairs = ref["pairs"]
+    n_tiles = cfg.tiles_x * cfg.tiles_y
+    L = np.bincount(np.asarray(pairs["frame"], np.int64) * n_tiles + np.asarray(pairs["tile"], np.int64),
+                    minlength=F * n_tiles).reshape(F, cfg.tiles_y, cfg.tiles_x)
+    Lpx = np.repeat(np.repeat(L, cfg.tile_h, axis=1), cfg.tile_w, axis=2)[:, :cfg.height, :cfg.width]
+    slack = int(Lpx[ref["computed"] & ref["flagged"]].sum())
+    for key, ref_key in (("n_evaluated", "n_evaluated"), ("n_composited", "n_composited")):
+        base = int(ref[ref_key][ok].sum())
+        got = int(status[key])
+        assert base <= got <= base + slack, (key, got, base, slack)
+        if slack == 0:
+            assert got == base
 
 
 @pytest.mark.parametrize("name", list(CASES))

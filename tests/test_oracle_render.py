@@ -165,6 +165,11 @@ def test_matches_brute_force(strict, seed):
     np.testing.assert_allclose(out["depth"][0], np.array(ref["depth"]), rtol=1e-11, atol=1e-13)
     np.testing.assert_allclose(out["T_final"][0], np.array(ref["T_final"]), rtol=1e-11, atol=1e-14)
     assert (out["n_contrib"][0] == np.array(ref["n_contrib"])).all()
+    # the workload counts: entries evaluated up to the stop, entries composited
+    assert (out["n_evaluated"][0] == np.array(ref["n_evaluated"])).all()
+    assert (out["n_composited"][0] == np.array(ref["n_composited"])).all()
+    if not strict:
+        assert (out["n_evaluated"][0] > out["n_composited"][0]).any()
 
 
 def test_recursion_S2_S3_matches_autograd():
