@@ -67,10 +67,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--workload", default="cfg3",
-                    choices=("cfg2", "cfg3", "cfg4", "cfg5", "mlp", "fwd320"),
+                    choices=("cfg2", "cfg3", "cfg4", "cfg5", "cfg5net", "mlp", "fwd320"),
                     help="cfg3 (default): the headline batched vs per-frame line; cfg2 / cfg4: the "
                          "same measurement on the static 100k / 1M-Gaussian 16-frame workloads; "
-                         "cfg5: the graph-replayed optimisation step; mlp: the deformation "
+                         "cfg5: the graph-replayed optimisation step; cfg5net: the same step "
+                         "with the deformation network's offsets in the loop; mlp: the deformation "
                          "network's forward + backward over (Gaussian, time) rows; fwd320: "
                          "forward-only rendering at 320x240 (cfg2's distributions), the "
                          "resolution of the paper's rendering-rate statement")
@@ -83,11 +84,14 @@ def bench_train_step(args):
     """Optimisation-step loop: 300k trainable Gaussians fitted to a 60-frame
     sequence rendered by the forward from a seeded ground-truth scene, batch of
     4 frames per step, RGB + quad L2 loss, Adam on every field, one captured
-    HIP graph replayed per step.  Prints one JSON line (steps/s)."""
+    HIP graph replayed per step.  With --workload cfg5net the deformation
+    network (8 x 256, paper initialisation: last layer N(0, 1e-10), zero
+    biases) adds its offsets at the batch's times, and the step also runs its
+    backward and its Adam group.  Prints one JSON line (steps/s)."""
     import torch
 
     import scenes
-    from paper_2505_05356_amd import raster, step as gstep
+    from paper_2505_05356_amd import deform, raster, step as gstep
 
     dev = "cuda:0"
     gt, tr, cfg = scenes.cfg5_scenes()
@@ -109,7 +113,14 @@ def bench_train_step(args):
     rng = np.random.default_rng(7)
     bg = torch.from_numpy(rng.uniform(-1, 1, (64, 4, 3 + cfg.n_quad)).astype(np.float32)).to(dev)
     params = raster.to_device_params(tr, dev, static=False)
-    ts = gstep.TrainStep(params, seq_dev, tgt_rgb, tgt_quad, cfg, batch=4, bg_table=bg)
+    with_net = args.workload == "cfg5net"
+    net_kw = {}
+    if with_net:
+        # network inputs: centres scaled by 2 f / c, the sequence's times (0 .. 2 s) by 1/2
+        net = deform.DeformNet(tr.n, 4, freq_hz=cfg.freqs[0], time_scale=0.5, device=dev)
+        theta = torch.from_numpy(scenes.mlp_params(seed=11)).to(dev)
+        net_kw = dict(net=net, net_params=theta)
+    ts = gstep.TrainStep(params, seq_dev, tgt_rgb, tgt_quad, cfg, batch=4, bg_table=bg, **net_kw)
     ts.size_workspace()
     ts.capture()
     for _ in range(args.warmup):
@@ -125,12 +136,15 @@ def bench_train_step(args):
     torch.cuda.synchronize()
     ms = s_ev.elapsed_time(e_ev)
     line = {
-        "metric": "optimisation steps/s (4-frame batch: fwd + L2 loss + bwd + Adam, one HIP graph)",
+        "metric": ("optimisation steps/s (4-frame batch: deformation network fwd + render fwd + L2 loss + "
+                   "render bwd + network bwd + Adam, one HIP graph)" if with_net else
+                   "optimisation steps/s (4-frame batch: fwd + L2 loss + bwd + Adam, one HIP graph)"),
         "value": round(args.steps / (ms / 1e3), 2), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded ground-truth scene rendered as targets; no dataset)",
-        "config": {"workload": f"train-{tr.n // 1000}k-{S}f-{W}x{H}-batch4", "n_gaussians": tr.n,
+        "config": {"workload": f"train-{tr.n // 1000}k-{S}f-{W}x{H}-batch4" + ("-deform-mlp" if with_net else ""),
+                   "n_gaussians": tr.n, "network_rows": 4 * tr.n if with_net else 0,
                    "sequence_frames": S, "batch": 4, "wall_s": round(time.perf_counter() - t0, 3),
                    "loss_after_warmup": l0, "loss_last": ts.loss.item()},
     }
@@ -314,7 +328,7 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    if args.workload == "cfg5":
+    if args.workload in ("cfg5", "cfg5net"):
         return bench_train_step(args)
     if args.workload == "mlp":
         return bench_mlp(args)
