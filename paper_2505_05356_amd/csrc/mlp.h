@@ -33,7 +33,7 @@ struct Layout {
     int n_chunks;
     int64_t part_off[kLayers], part_stride;   // floats
     // byte offsets into the workspace
-    size_t wf[kLayers], wt[kLayers], H[kLayers], GZ[kLayers], dxr, part, bytes;
+    size_t wf[kLayers], wt[kLayers], H[kLayers], GZ[kLayers], mask, dxr, part, bytes;
     bool training;
 };
 

@@ -24,7 +24,10 @@
 //
 // Saved activations and gradients use a row-blocked layout [rows/8][feat][8]:
 // the eight rows of one feature are one 16-byte fragment of the weight-gradient
-// product, and the row-parallel kernels write four of them per lane.
+// product, and the row-parallel kernels write four of them per lane.  The
+// forward also keeps the ReLU decisions of h_1 .. h_8 as bits, 16 bytes per
+// lane and layer in the lane's own accumulator order, so the backward gates
+// its gradients from 4 registers instead of re-reading the activations.
 #include "mlp.h"
 
 namespace gft {
@@ -53,6 +56,7 @@ struct Args {
     const float* bias[kLayers];
     bf16* H[kLayers];
     bf16* GZ[kLayers];
+    uint4* mask;   // [blocks][kDepth][256 threads]: word c, bit mask_bit(r, j) = [h > 0] of acc[r][c][j]
 };
 
 // D += A B on one 16 x 16 tile, K = 32.  Lane l supplies A[l % 16][8 (l / 16) + e]
@@ -136,6 +140,22 @@ __device__ __forceinline__ void gemm_128x64(const bf16* X, const bf16* __restric
     }
 }
 
+// Bit of element j of accumulator row tile r in its column tile's mask word.
+// The forward derives the four bits of a tile from the two 32-bit words of its
+// bfloat16 ReLU outputs (each half non-negative): adding 0x7fff to a half sets
+// its bit 15 exactly when the half is non-zero, without carrying into the
+// other half; bits 15 and 31 of the two sums then shift into place together.
+__device__ __forceinline__ constexpr int mask_bit(int r, int j) {
+    return r + (j == 0 ? 0 : j == 1 ? 16 : j == 2 ? 8 : 24);
+}
+
+__device__ __forceinline__ uint32_t relu_bits(bf16x4 v, int r) {
+    const uint2 d = __builtin_bit_cast(uint2, v);
+    const uint32_t s0 = (d.x + 0x7fff7fffu) & 0x80008000u;   // j = 0 at bit 15, j = 1 at bit 31
+    const uint32_t s1 = (d.y + 0x7fff7fffu) & 0x80008000u;   // j = 2, j = 3
+    return (s0 >> (15 - r)) | (s1 >> (7 - r));
+}
+
 __device__ __forceinline__ void zero(f32x4 (&acc)[8][4]) {
 #pragma unroll
     for (int r = 0; r < 8; ++r)
@@ -164,7 +184,7 @@ __device__ __forceinline__ void save_block(const bf16* X, bf16* __restrict__ dst
 }
 
 template <bool SAVE>
-__global__ void __launch_bounds__(256) k_mlp_fwd(Args a, float* __restrict__ delta) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_mlp_fwd(Args a, float* __restrict__ delta) {
     __shared__ __attribute__((aligned(16))) bf16 X[kRows * kLDX];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int lr = lane & 15, lg = lane >> 4;
@@ -197,7 +217,10 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(Args a, float* __restrict__ del
         else
             gemm_128x64<kWidth, true>(X, a.wf[l], col0, acc, lane);
         __syncthreads();   // every wave has read this layer's input
-        bf16* H = a.H[l + 1];
+        // rows r0 + 16 r + 4 lg .. +3 of feature col0 + 16 c + lr sit at
+        // hb + (16 r / 8) * kWidth * 8 + 16 c * 8 in the row-blocked layout
+        bf16* hb = a.H[l + 1] + ((size_t)(r0 / 8 + (lg >> 1)) * kWidth + col0 + lr) * 8 + 4 * (lg & 1);
+        uint32_t mw[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int col = col0 + 16 * c + lr;
@@ -210,9 +233,13 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(Args a, float* __restrict__ del
                 const bf16x4 v = __builtin_bit_cast(bf16x4, __builtin_elementwise_max(zi, s16x4{0, 0, 0, 0}));
 #pragma unroll
                 for (int j = 0; j < 4; ++j) X[(16 * r + 4 * lg + j) * kLDX + col] = v[j];
-                if (SAVE) *(bf16x4*)(H + blk_off<kWidth>(r0 + 16 * r + 4 * lg, col)) = v;
+                if (SAVE) {
+                    *(bf16x4*)(hb + (size_t)r * (2 * kWidth * 8) + c * 128) = v;
+                    mw[c] |= relu_bits(v, r);
+                }
             }
         }
+        if (SAVE) a.mask[((size_t)blockIdx.x * kDepth + l) * 256 + tid] = make_uint4(mw[0], mw[1], mw[2], mw[3]);
         __syncthreads();
     }
     // head: 128 rows x 16 (3 real) outputs; wave w takes rows 32w .. 32w+31
@@ -243,7 +270,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(Args a, float* __restrict__ del
     }
 }
 
-__global__ void __launch_bounds__(256) k_mlp_bwd(Args a, const float* __restrict__ d_delta,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_mlp_bwd(Args a, const float* __restrict__ d_delta,
                                                  float* __restrict__ dxr) {
     __shared__ __attribute__((aligned(16))) bf16 X[kRows * kLDX];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -266,42 +293,39 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(Args a, const float* __restrict
 
     f32x4 acc[8][4];
     const int col0 = 64 * wv;
-    // the activations whose signs gate this layer's gradient, loaded before
-    // the product so that their latency hides behind it
-    bf16x4 hm[8][4];
-    auto load_masks = [&](const bf16* H) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int r = 0; r < 8; ++r)
-                hm[r][c] = *(const bf16x4*)(H + blk_off<kWidth>(r0 + 16 * r + 4 * lg, col0 + 16 * c + lr));
-    };
-    load_masks(a.H[kDepth]);
+    // the forward's ReLU decisions for h_{l+1} (layer l's output), loaded
+    // before the product so that their latency hides behind it
+    uint4 hm;
+    auto load_masks = [&](int l) { hm = a.mask[((size_t)blockIdx.x * kDepth + l) * 256 + tid]; };
+    // rows r0 + 16 r + 4 lg .. +3 of feature col0 + 16 c + lr of a row-blocked
+    // array sit at base + r * 2 kWidth 8 + c * 128
+    const size_t base = ((size_t)(r0 / 8 + (lg >> 1)) * kWidth + col0 + lr) * 8 + 4 * (lg & 1);
+    load_masks(kDepth - 1);
     zero(acc);
     gemm_128x64<kHeadK, false>(X, a.wt[kDepth], col0, acc, lane);   // g_8 = gz_8 W_8
     for (int l = kDepth - 1; l >= 0; --l) {
         __syncthreads();
         // gz_l = g_{l+1} * [h_{l+1} > 0]
-        bf16* GZ = a.GZ[l];
+        bf16* gzb = a.GZ[l] + base;
+        const uint32_t mw[4] = {hm.x, hm.y, hm.z, hm.w};
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int col = col0 + 16 * c + lr;
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
-                const size_t o = blk_off<kWidth>(r0 + 16 * r + 4 * lg, col);
-                const bf16x4 h = hm[r][c];
+                const size_t o = (size_t)r * (2 * kWidth * 8) + c * 128;
                 bf16x4 v;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    v[j] = (bf16)((float)h[j] > 0.f ? acc[r][c][j] : 0.f);
+                    v[j] = (bf16)(((mw[c] >> mask_bit(r, j)) & 1u) ? acc[r][c][j] : 0.f);
                     X[(16 * r + 4 * lg + j) * kLDX + col] = v[j];
                 }
-                *(bf16x4*)(GZ + o) = v;
+                *(bf16x4*)(gzb + o) = v;
             }
         }
         __syncthreads();
         if (l > 0) {
-            load_masks(a.H[l]);
+            load_masks(l - 1);
             zero(acc);
             gemm_128x64<kWidth, false>(X, a.wt[l], col0, acc, lane);   // g_l = gz_l W_l
         }
@@ -581,6 +605,7 @@ Args make_args(const Layout& L, const Call& c) {
         a.H[l] = L.training ? reinterpret_cast<bf16*>(c.ws + L.H[l]) : nullptr;
         a.GZ[l] = L.training ? reinterpret_cast<bf16*>(c.ws + L.GZ[l]) : nullptr;
     }
+    a.mask = L.training ? reinterpret_cast<uint4*>(c.ws + L.mask) : nullptr;
     return a;
 }
 
@@ -631,10 +656,12 @@ bool make_layout(int lx, int lt, int width, int depth, int64_t n, int n_times, b
         L->wt[l] = take((size_t)pad_in(l) * pad_k(l) * 2);
     }
     for (int l = 0; l < kLayers; ++l) L->H[l] = L->GZ[l] = 0;
-    L->dxr = L->part = 0;
+    L->mask = L->dxr = L->part = 0;
     if (training) {
         for (int l = 0; l < kLayers; ++l) L->H[l] = take((size_t)L->rows_pad * pad_in(l) * 2);
         for (int l = 0; l < kLayers; ++l) L->GZ[l] = take((size_t)L->rows_pad * pad_out(l) * 2);
+        // ReLU bits: 16 bytes per thread, layer and 128-row block = 2 bytes per row and unit
+        L->mask = take((size_t)(L->rows_pad / kRows) * kDepth * 256 * 16);
         L->dxr = take((size_t)L->rows_pad * 3 * 4);
         L->part = take((size_t)L->n_chunks * L->part_stride * 4);
     }
