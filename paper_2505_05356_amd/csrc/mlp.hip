@@ -410,10 +410,15 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
     const int64_t rs = (int64_t)blockIdx.x * d.rows_per_chunk;
     const int64_t re = min(rs + d.rows_per_chunk, d.rows_pad);   // both multiples of 32
     f32x4 acc[MT][NT];
-    float sb[MT];
+    // db on the matrix cores: the product with a fragment of ones sums every
+    // output row over the chunk's rows (the waves of the first input group)
+    f32x4 ab[MT];
+    bf16x8 ones;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ones[e] = (bf16)1.0f;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-        sb[m] = 0.f;
+        ab[m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
@@ -437,9 +442,7 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
             for (int t = 0; t < NT; ++t) acc[m][t] = mfma(av[m], bv[t], acc[m][t]);
         if (i0 == 0)
 #pragma unroll
-            for (int m = 0; m < MT; ++m)
-#pragma unroll
-                for (int e = 0; e < 8; ++e) sb[m] += (float)av[m][e];
+            for (int m = 0; m < MT; ++m) ab[m] = mfma(av[m], ones, ab[m]);
         if (more) {
 #pragma unroll
             for (int m = 0; m < MT; ++m) av[m] = an[m];
@@ -455,14 +458,11 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 P[(size_t)(o0 + 16 * m + 4 * lg + j) * NI + i0 + 16 * t + lr] = acc[m][t][j];
-    if (i0 == 0) {
+    if (i0 == 0 && lr == 0) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            float s = sb[m];
-            s += __shfl_xor(s, 16, 64);
-            s += __shfl_xor(s, 32, 64);
-            if (lg == 0) P[(size_t)NO * NI + o0 + 16 * m + lr] = s;
-        }
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) P[(size_t)NO * NI + o0 + 16 * m + 4 * lg + j] = ab[m][j];
     }
 }
 
