@@ -48,10 +48,10 @@ SORT_BYTES_PER_KEY_PASS = 16  # read key + value, write key + value (4 B each)
 # by what the same counter reads for a plain device copy of known size
 # (--calibration-copy-mib).  A figure holds only for the kernel source it was
 # measured on: the sha256 of the listed files must match, else traffic is null.
-FETCH_SCALE, WRITE_SCALE = 1048576 / 524316, 1048576 / 1048576   # 1 GiB copy: FETCH 524316 KiB, WRITE 1048576 KiB
+FETCH_SCALE, WRITE_SCALE = 1048576 / 524318, 1048576 / 1048576   # 1 GiB copy: FETCH 524318 KiB, WRITE 1048576 KiB
 TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
-TRAFFIC_SHA256 = "a946a99b38e9846fe40c47ae97c55287ff9a258d3eb89e0466e986041a02ff2e"
-TRAFFIC_KIB = {"k_composite_bwd": (52019, 51901), "k_composite_fwd": (4815, 96136)}   # KiB per launch
+TRAFFIC_SHA256 = "60ecfcda9bc34635cfb47de745a3e3facc908c65b06647a9d29bdb283a28caa4"
+TRAFFIC_KIB = {"k_composite_bwd": (52023, 51901), "k_composite_fwd": (4815, 96131)}   # KiB per launch
 
 
 def parse():
@@ -153,9 +153,9 @@ def bench_train_step(args):
 
 # the same for the deformation network's kernels (k_mlp_dw: its three launches together)
 MLP_TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
-MLP_TRAFFIC_SHA256 = "fdf52f0f1d098d0d0713829107b723a32c12c4cf35a8561511aac01ce5cba235"
-MLP_TRAFFIC_KIB = {"k_mlp_fwd": (197822, 6718750), "k_mlp_bwd": (3407892, 6468750),
-                   "k_mlp_dw": (10819119, 278298)}   # KiB per launch, 1.6M rows
+MLP_TRAFFIC_SHA256 = "6c6f64f8b2576ccaa9de403414ec73afdcdfc88a5529a0ef594a9a3640080c59"
+MLP_TRAFFIC_KIB = {"k_mlp_fwd": (219584, 7156256), "k_mlp_bwd": (345844, 6468750),
+                   "k_mlp_dw": (6733589, 275818)}   # KiB per launch, 1.6M rows
 
 
 def traffic_bytes(name, files=TRAFFIC_FILES, sha=TRAFFIC_SHA256, table=TRAFFIC_KIB):
@@ -180,6 +180,16 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix peak
 def mlp_flop_per_row(n_in=84, width=256, depth=8, n_out=3):
     """Multiply-adds x 2 of one row through every linear layer (unpadded)."""
     return 2 * (n_in * width + (depth - 1) * width * width + width * n_out)
+
+
+def mlp_bytes_per_row(width=256, depth=8, k0=96, head_pad=16):
+    """HBM bytes per row that each network kernel must move in training mode
+    (bfloat16 saved activations h_0 .. h_7 and gradients gz_0 .. gz_8, ReLU
+    bits at 2 bytes per row and hidden layer, float32 offsets and centres)."""
+    h = 2 * (k0 + (depth - 1) * width) + 2 * width   # h_0 .. h_8 as stored (h_8 feeds the head's dW)
+    gz = 2 * (depth * width + head_pad)
+    bits = depth * width // 8                         # one ReLU bit per hidden unit and row
+    return {"k_mlp_fwd": h + bits + 12 + 12, "k_mlp_bwd": gz + bits + 12 + 12, "k_mlp_dw": gz + h}
 
 
 def bench_mlp(args):
@@ -223,20 +233,31 @@ def bench_mlp(args):
     rows = n * T
     flop = rows * mlp_flop_per_row()
     per_kernel = {}
+    bpr = mlp_bytes_per_row()
     for k in ("k_mlp_fwd", "k_mlp_bwd", "k_mlp_dw"):
         if k in kern:
             tf = flop / (kern[k] / 1e3) / 1e12
+            nbytes = rows * bpr[k]
+            gbs = nbytes / (kern[k] / 1e3) / 1e9
+            # the binding roofline: the larger of the two ideal times
+            bound = "hbm" if nbytes / (HBM_PEAK_GBS * 1e9) > flop / (MFMA_BF16_PEAK_TFLOPS * 1e12) else "mfma"
             per_kernel[k] = dict(avg_ms=round(kern[k], 4), tflops=round(tf, 1),
-                                 frac=round(tf / MFMA_BF16_PEAK_TFLOPS, 4))
+                                 frac=round(tf / MFMA_BF16_PEAK_TFLOPS, 4), hbm_gbs=round(gbs, 1),
+                                 hbm_frac=round(gbs / HBM_PEAK_GBS, 4), bound=bound)
     dominant = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"])
-    a = per_kernel[dominant]["tflops"]
+    pk = per_kernel[dominant]
     traffic = None
     if n == 200_000 and T == 8:   # the counters were taken on this shape
         traffic = traffic_bytes(dominant, MLP_TRAFFIC_FILES, MLP_TRAFFIC_SHA256, MLP_TRAFFIC_KIB)
-    roof = dict(bound="mfma", achieved=a, peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=round(a / MFMA_BF16_PEAK_TFLOPS, 4), traffic=traffic, kernel=dominant,
-                avg_ms=per_kernel[dominant]["avg_ms"],
-                work=f"{flop:.4g} FLOP per launch = {rows} rows x {mlp_flop_per_row()} (bf16 products)")
+    if pk["bound"] == "hbm":
+        roof = dict(bound="hbm", achieved=pk["hbm_gbs"], peak=HBM_PEAK_GBS, unit="GB/s", frac=pk["hbm_frac"],
+                    traffic=traffic, kernel=dominant, avg_ms=pk["avg_ms"],
+                    work=f"{rows * bpr[dominant]:.4g} B per launch = {rows} rows x {bpr[dominant]} B "
+                         f"(matrix cores: {pk['tflops']} TFLOP/s, {pk['frac']} of the bf16 peak)")
+    else:
+        roof = dict(bound="mfma", achieved=pk["tflops"], peak=MFMA_BF16_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=pk["frac"], traffic=traffic, kernel=dominant, avg_ms=pk["avg_ms"],
+                    work=f"{flop:.4g} FLOP per launch = {rows} rows x {mlp_flop_per_row()} (bf16 products)")
     print("# kernels: " + ", ".join(f"{k} {v * 1e3:.1f}us" for k, v in sorted(kern.items(), key=lambda kv: -kv[1])),
           file=sys.stderr, flush=True)
     if args.calibration_copy_mib > 0:   # a plain copy of known size for counter scaling
