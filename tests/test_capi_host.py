@@ -130,3 +130,22 @@ def test_mlp_sizes_and_argument_checks(lib):
     rc = lib.gftorf_mlp_fwd(ctypes.byref(good), ctypes.c_void_p(256), ctypes.c_void_p(256), 1000,
                             times, 2, ctypes.c_void_p(256), 1, ctypes.c_void_p(256), small, None)
     assert rc == _lib.ENOWS
+
+
+def test_mlp_device_time_entry_points_check_arguments(lib):
+    # the entry points that read the times from device frame descriptors refuse
+    # missing pointers, too many frames and a short workspace before any launch
+    from paper_2505_05356_amd import _lib
+    cfg = _lib.MlpConfigC(10, 10, 256, 8, 0.2, 4.0)
+    need = lib.gftorf_mlp_workspace_size(ctypes.byref(cfg), 1000, 2, 1)
+    dev = ctypes.c_void_p(256)
+    assert lib.gftorf_mlp_fwd_frames(ctypes.byref(cfg), dev, dev, 1000, None, 2, dev, 1,
+                                     dev, need, None) == _lib.EINVAL
+    assert lib.gftorf_mlp_fwd_frames(ctypes.byref(cfg), dev, dev, 1000, dev, 65, dev, 1,
+                                     dev, need, None) == _lib.EINVAL
+    assert lib.gftorf_mlp_fwd_frames(ctypes.byref(cfg), dev, dev, 1000, dev, 2, dev, 1,
+                                     dev, need - 256, None) == _lib.ENOWS
+    assert lib.gftorf_mlp_bwd_frames(ctypes.byref(cfg), dev, dev, 1000, None, 2, dev, dev, dev, 1,
+                                     dev, need, None) == _lib.EINVAL
+    assert lib.gftorf_mlp_bwd_frames(ctypes.byref(cfg), dev, dev, 1000, dev, 2, None, dev, dev, 1,
+                                     dev, need, None) == _lib.EINVAL
