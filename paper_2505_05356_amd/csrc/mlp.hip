@@ -401,6 +401,13 @@ template <int NO, int NI, int OG, int IG>
 __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
     constexpr int MT = NO / 16 / OG, NT = NI / 16 / IG;
     static_assert(OG * IG == 8 && MT * 16 * OG == NO && NT * 16 * IG == NI, "tiling");
+    // One k-step is 32 rows = 4 row blocks of gz (NO features) and h (NI
+    // features), 16 bytes per (row block, feature): staged once per workgroup
+    // in LDS, double-buffered, and read from there by the 8 waves (each
+    // gradient tile is read by IG waves and each activation tile by OG).
+    constexpr int NC = 4 * (NO + NI);
+    constexpr int PER = (NC + 511) / 512;
+    __shared__ bf16x8 sbuf[2][NC];
     const int l = l0 + blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int lr = lane & 15, lg = lane >> 4;
@@ -409,6 +416,7 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
     const bf16* __restrict__ H = d.H[l];
     const int64_t rs = (int64_t)blockIdx.x * d.rows_per_chunk;
     const int64_t re = min(rs + d.rows_per_chunk, d.rows_pad);   // both multiples of 32
+    const int nk = rs < re ? (int)((re - rs) / 32) : 0;          // uniform over the workgroup
     f32x4 acc[MT][NT];
     // db on the matrix cores: the product with a fragment of ones sums every
     // output row over the chunk's rows (the waves of the first input group)
@@ -422,20 +430,45 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    // one k-step (32 rows) of fragments in flight ahead of the products
-    bf16x8 av[MT], bv[NT], an[MT], bn[NT];
-    auto load = [&](int64_t kb, bf16x8 (&A)[MT], bf16x8 (&Bf)[NT]) {
-        const int64_t rb = kb + lg;
+    // chunk q < 4 NO: gz row block q / NO, feature q % NO; else h likewise
+    bf16x8 stg[PER];
+    auto fetch = [&](int64_t kb) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) A[m] = *(const bf16x8*)(GZ + ((size_t)rb * NO + o0 + 16 * m + lr) * 8);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) Bf[t] = *(const bf16x8*)(H + ((size_t)rb * NI + i0 + 16 * t + lr) * 8);
+        for (int p = 0; p < PER; ++p) {
+            const int q = tid + 512 * p;
+            if (q < NC) {
+                if (q < 4 * NO) {
+                    const int rb = q / NO, f = q - rb * NO;
+                    stg[p] = *(const bf16x8*)(GZ + ((size_t)(kb + rb) * NO + f) * 8);
+                } else {
+                    const int qh = q - 4 * NO, rb = qh / NI, f = qh - rb * NI;
+                    stg[p] = *(const bf16x8*)(H + ((size_t)(kb + rb) * NI + f) * 8);
+                }
+            }
+        }
     };
-    if (rs < re) load(rs / 8, av, bv);
-    for (int64_t kb = rs / 8; kb < re / 8; kb += 4) {
-        const bool more = kb + 4 < re / 8;
-        if (more) load(kb + 4, an, bn);
-        __builtin_amdgcn_sched_barrier(0);
+    auto stage = [&](int b) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int q = tid + 512 * p;
+            if (q < NC) sbuf[b][q] = stg[p];
+        }
+    };
+    const int64_t kb0 = rs / 8;
+    if (nk > 0) {
+        fetch(kb0);
+        stage(0);
+    }
+    __syncthreads();
+    for (int k = 0; k < nk; ++k) {
+        const int cur = k & 1;
+        const bool more = k + 1 < nk;
+        if (more) fetch(kb0 + 4 * (k + 1));   // in flight during this step's products
+        bf16x8 av[MT], bv[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) av[m] = sbuf[cur][lg * NO + o0 + 16 * m + lr];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bv[t] = sbuf[cur][4 * NO + lg * NI + i0 + 16 * t + lr];
 #pragma unroll
         for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -443,12 +476,8 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
         if (i0 == 0)
 #pragma unroll
             for (int m = 0; m < MT; ++m) ab[m] = mfma(av[m], ones, ab[m]);
-        if (more) {
-#pragma unroll
-            for (int m = 0; m < MT; ++m) av[m] = an[m];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) bv[t] = bn[t];
-        }
+        if (more) stage(cur ^ 1);   // the other buffer was last read before the previous barrier
+        __syncthreads();
     }
     float* P = d.part + (int64_t)blockIdx.x * d.part_stride + d.part_off[l];
 #pragma unroll
