@@ -401,11 +401,11 @@ template <int NO, int NI, int OG, int IG>
 __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
     constexpr int MT = NO / 16 / OG, NT = NI / 16 / IG;
     static_assert(OG * IG == 8 && MT * 16 * OG == NO && NT * 16 * IG == NI, "tiling");
-    // One k-step is 32 rows = 4 row blocks of gz (NO features) and h (NI
-    // features), 16 bytes per (row block, feature): staged once per workgroup
-    // in LDS, double-buffered, and read from there by the 8 waves (each
-    // gradient tile is read by IG waves and each activation tile by OG).
-    constexpr int NC = 4 * (NO + NI);
+    // One stage is two k-steps of 32 rows = 8 row blocks of gz (NO features)
+    // and h (NI features), 16 bytes per (row block, feature): staged once per
+    // workgroup in LDS, double-buffered, and read from there by the 8 waves
+    // (each gradient tile is read by IG waves and each activation tile by OG).
+    constexpr int NC = 8 * (NO + NI);
     constexpr int PER = (NC + 511) / 512;
     __shared__ bf16x8 sbuf[2][NC];
     const int l = l0 + blockIdx.y;
@@ -415,8 +415,8 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
     const bf16* __restrict__ GZ = d.GZ[l];
     const bf16* __restrict__ H = d.H[l];
     const int64_t rs = (int64_t)blockIdx.x * d.rows_per_chunk;
-    const int64_t re = min(rs + d.rows_per_chunk, d.rows_pad);   // both multiples of 32
-    const int nk = rs < re ? (int)((re - rs) / 32) : 0;          // uniform over the workgroup
+    const int64_t re = min(rs + d.rows_per_chunk, d.rows_pad);   // both multiples of 64
+    const int nk = rs < re ? (int)((re - rs) / 64) : 0;          // stages; chunks hold multiples of 64 rows
     f32x4 acc[MT][NT];
     // db on the matrix cores: the product with a fragment of ones sums every
     // output row over the chunk's rows (the waves of the first input group)
@@ -430,18 +430,18 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-    // chunk q < 4 NO: gz row block q / NO, feature q % NO; else h likewise
+    // chunk q < 8 NO: gz row block q / NO, feature q % NO; else h likewise
     bf16x8 stg[PER];
     auto fetch = [&](int64_t kb) {
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int q = tid + 512 * p;
             if (q < NC) {
-                if (q < 4 * NO) {
+                if (q < 8 * NO) {
                     const int rb = q / NO, f = q - rb * NO;
                     stg[p] = *(const bf16x8*)(GZ + ((size_t)(kb + rb) * NO + f) * 8);
                 } else {
-                    const int qh = q - 4 * NO, rb = qh / NI, f = qh - rb * NI;
+                    const int qh = q - 8 * NO, rb = qh / NI, f = qh - rb * NI;
                     stg[p] = *(const bf16x8*)(H + ((size_t)(kb + rb) * NI + f) * 8);
                 }
             }
@@ -463,19 +463,22 @@ __global__ void __launch_bounds__(512) k_mlp_dw(DwArgs d, int l0) {
     for (int k = 0; k < nk; ++k) {
         const int cur = k & 1;
         const bool more = k + 1 < nk;
-        if (more) fetch(kb0 + 4 * (k + 1));   // in flight during this step's products
-        bf16x8 av[MT], bv[NT];
+        if (more) fetch(kb0 + 8 * (k + 1));   // in flight during this stage's products
 #pragma unroll
-        for (int m = 0; m < MT; ++m) av[m] = sbuf[cur][lg * NO + o0 + 16 * m + lr];
+        for (int h = 0; h < 2; ++h) {
+            bf16x8 av[MT], bv[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) bv[t] = sbuf[cur][4 * NO + lg * NI + i0 + 16 * t + lr];
+            for (int m = 0; m < MT; ++m) av[m] = sbuf[cur][(4 * h + lg) * NO + o0 + 16 * m + lr];
 #pragma unroll
-        for (int m = 0; m < MT; ++m)
+            for (int t = 0; t < NT; ++t) bv[t] = sbuf[cur][8 * NO + (4 * h + lg) * NI + i0 + 16 * t + lr];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(av[m], bv[t], acc[m][t]);
-        if (i0 == 0)
+            for (int m = 0; m < MT; ++m)
 #pragma unroll
-            for (int m = 0; m < MT; ++m) ab[m] = mfma(av[m], ones, ab[m]);
+                for (int t = 0; t < NT; ++t) acc[m][t] = mfma(av[m], bv[t], acc[m][t]);
+            if (i0 == 0)
+#pragma unroll
+                for (int m = 0; m < MT; ++m) ab[m] = mfma(av[m], ones, ab[m]);
+        }
         if (more) stage(cur ^ 1);   // the other buffer was last read before the previous barrier
         __syncthreads();
     }
@@ -665,7 +668,7 @@ bool make_layout(int lx, int lt, int width, int depth, int64_t n, int n_times, b
     L->rows = n * n_times;
     L->rows_pad = (L->rows + kRows - 1) / kRows * kRows;
     int64_t rpc = (L->rows_pad + kMaxChunks - 1) / kMaxChunks;
-    rpc = (rpc + 31) / 32 * 32;
+    rpc = (rpc + 63) / 64 * 64;   // whole 64-row stages of the weight-gradient kernel
     L->rows_per_chunk = rpc;
     L->n_chunks = (int)((L->rows_pad + rpc - 1) / rpc);
     int64_t po = 0;
