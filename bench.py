@@ -153,9 +153,9 @@ def bench_train_step(args):
 
 # the same for the deformation network's kernels (k_mlp_dw: its three launches together)
 MLP_TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
-MLP_TRAFFIC_SHA256 = "6c6f64f8b2576ccaa9de403414ec73afdcdfc88a5529a0ef594a9a3640080c59"
-MLP_TRAFFIC_KIB = {"k_mlp_fwd": (219584, 7156256), "k_mlp_bwd": (345844, 6468750),
-                   "k_mlp_dw": (6733589, 275818)}   # KiB per launch, 1.6M rows
+MLP_TRAFFIC_SHA256 = "621562756dbd139ddc931f4f1063f0ea29488a8687ace19358cd3b11da45c14e"
+MLP_TRAFFIC_KIB = {"k_mlp_fwd": (212708, 7156257), "k_mlp_bwd": (348588, 6468750),
+                   "k_mlp_dw": (6575116, 275390)}   # KiB per launch, 1.6M rows
 
 
 def traffic_bytes(name, files=TRAFFIC_FILES, sha=TRAFFIC_SHA256, table=TRAFFIC_KIB):
