@@ -11,12 +11,16 @@
 //                 every layer's activations stay in LDS (128 x 256 bf16),
 //                 weights stream from L2; wave w computes output columns
 //                 64w .. 64w+63 of all 128 rows with v_mfma_f32_16x16x32_bf16.
-//                 Training mode also stores h_0 .. h_8 for the backward.
+//                 Two workgroups share a CU (two waves per SIMD), so one's
+//                 epilogue overlaps the other's products.  Training mode also
+//                 stores h_0 .. h_8 and the ReLU decisions as bits.
 //   k_mlp_bwd     the same tiling backwards: gz_8 = dL/d delta, then per layer
-//                 g_l = gz_l W_l, gz_{l-1} = g_l * [h_l > 0]; stores every gz_l
-//                 and, from g_0, the gradient of the scaled centre input.
+//                 g_l = gz_l W_l, gz_{l-1} = g_l * [h_l > 0] (the forward's
+//                 bits); stores every gz_l and, from g_0, the gradient of the
+//                 scaled centre input.  Two workgroups per CU, as the forward.
 //   k_mlp_dw      dW_l = sum_rows gz_l h_l^T, db_l = sum_rows gz_l: rows are the
-//                 contraction, split into fixed chunks, one partial per chunk.
+//                 contraction, split into fixed chunks, one partial per chunk;
+//                 each 64-row stage of gz_l and h_l passes once through LDS.
 //   k_mlp_reduce  sums the chunk partials in chunk order into the parameter
 //                 layout; k_mlp_dx0 sums the centre gradient over the times.
 //   k_blend       Eq. 7 with the network: per-frame offsets from the offsets
