@@ -43,6 +43,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 // LDS row stride in bf16: the 16-byte pad puts the 16 rows of one fragment
 // read in 16 distinct 4-bank groups.
@@ -318,12 +319,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 const size_t o = (size_t)r * (2 * kWidth * 8) + c * 128;
-                bf16x4 v;
+                // bfloat16 first, then the gates as 16-bit masks: shifting the
+                // word puts the bits of elements (0, 1), then (2, 3), at bits 15
+                // and 31, and an arithmetic shift of each half by 15 spreads them
+                uint2 z = __builtin_bit_cast(uint2, __builtin_convertvector(acc[r][c], bf16x4));
+                z.x &= __builtin_bit_cast(uint32_t, __builtin_bit_cast(s16x2, mw[c] << (15 - r)) >> (short)15);
+                z.y &= __builtin_bit_cast(uint32_t, __builtin_bit_cast(s16x2, mw[c] << (7 - r)) >> (short)15);
+                const bf16x4 v = __builtin_bit_cast(bf16x4, z);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    v[j] = (bf16)(((mw[c] >> mask_bit(r, j)) & 1u) ? acc[r][c][j] : 0.f);
-                    X[(16 * r + 4 * lg + j) * kLDX + col] = v[j];
-                }
+                for (int j = 0; j < 4; ++j) X[(16 * r + 4 * lg + j) * kLDX + col] = v[j];
                 *(bf16x4*)(gzb + o) = v;
             }
         }
