@@ -153,9 +153,9 @@ def bench_train_step(args):
 
 # the same for the deformation network's kernels (k_mlp_dw: its three launches together)
 MLP_TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
-MLP_TRAFFIC_SHA256 = "7d1d3756751d453f7fc41b9e53363e09ec7d765b544b6b1f8a2c91052cc045b3"
-MLP_TRAFFIC_KIB = {"k_mlp_fwd": (212708, 7156257), "k_mlp_bwd": (348588, 6468750),
-                   "k_mlp_dw": (6575116, 275390)}   # KiB per launch, 1.6M rows
+MLP_TRAFFIC_SHA256 = "f1b745f06183ff2d944649cbf7dd720bad7364413c623bf710699554d42ef79f"
+MLP_TRAFFIC_KIB = {"k_mlp_fwd": (218924, 7156260), "k_mlp_bwd": (364013, 6468750),
+                   "k_mlp_dw": (6575126, 275391)}   # KiB per launch, 1.6M rows
 
 
 def traffic_bytes(name, files=TRAFFIC_FILES, sha=TRAFFIC_SHA256, table=TRAFFIC_KIB):
