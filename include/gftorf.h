@@ -343,8 +343,8 @@ typedef struct gftorf_mlp_config {
 int64_t gftorf_mlp_param_count(const gftorf_mlp_config* cfg);
 
 /* Workspace bytes for n Gaussians at n_times times; with `training` it also
- * holds the activations and gradients gftorf_mlp_bwd reads (about
- * 9.2 KB per row).  0 if the arguments are invalid. */
+ * holds the activations, ReLU decisions and gradients gftorf_mlp_bwd reads
+ * (about 9.5 KB per row).  0 if the arguments are invalid. */
 size_t gftorf_mlp_workspace_size(const gftorf_mlp_config* cfg, int64_t n, int32_t n_times,
                                  int32_t training);
 
