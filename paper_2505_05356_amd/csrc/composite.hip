@@ -38,7 +38,9 @@ __device__ __forceinline__ float splat_q(const float4 c, const float4 r1, float 
 #pragma clang fp contract(off)
     dx = px - c.x;
     dy = py - c.y;
-    return __builtin_fmaf(dx, __builtin_fmaf(r1.y, dy, r1.x * dx), (r1.z * dy) * dy);
+    // dy (C dy + B dx) + A dx^2: the backward's pixels of one lane share a
+    // column, so B dx and A dx^2 are computed once per lane and entry
+    return __builtin_fmaf(dy, __builtin_fmaf(r1.z, dy, r1.y * dx), (r1.x * dx) * dx);
 }
 
 // Below this exponent (log2 units) alpha < alpha_min with room to spare for
