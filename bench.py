@@ -50,8 +50,8 @@ SORT_BYTES_PER_KEY_PASS = 16  # read key + value, write key + value (4 B each)
 # measured on: the sha256 of the listed files must match, else traffic is null.
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524318, 1048576 / 1048576   # 1 GiB copy: FETCH 524318 KiB, WRITE 1048576 KiB
 TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
-TRAFFIC_SHA256 = "60ecfcda9bc34635cfb47de745a3e3facc908c65b06647a9d29bdb283a28caa4"
-TRAFFIC_KIB = {"k_composite_bwd": (52023, 51901), "k_composite_fwd": (4815, 96131)}   # KiB per launch
+TRAFFIC_SHA256 = "c7d6b25f8a98437c5591d603b219aa47546d05ed64456dcdde89aaa3a85f209d"
+TRAFFIC_KIB = {"k_composite_bwd": (52022, 51901), "k_composite_fwd": (4815, 96136)}   # KiB per launch
 
 
 def parse():
