@@ -67,14 +67,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-frame", action="store_true")
     ap.add_argument("--workload", default="cfg3",
-                    choices=("cfg2", "cfg3", "cfg4", "cfg5", "cfg5net", "mlp", "fwd320"),
+                    choices=("cfg2", "cfg3", "cfg4", "cfg5", "cfg5net", "mlp", "fwd320", "cfg3sh", "cfg3async"),
                     help="cfg3 (default): the headline batched vs per-frame line; cfg2 / cfg4: the "
                          "same measurement on the static 100k / 1M-Gaussian 16-frame workloads; "
                          "cfg5: the graph-replayed optimisation step; cfg5net: the same step "
                          "with the deformation network's offsets in the loop; mlp: the deformation "
                          "network's forward + backward over (Gaussian, time) rows; fwd320: "
                          "forward-only rendering at 320x240 (cfg2's distributions), the "
-                         "resolution of the paper's rendering-rate statement")
+                         "resolution of the paper's rendering-rate statement; cfg3sh / cfg3async: "
+                         "cfg3's batched fwd+bwd with degree-3 spherical-harmonic colour and "
+                         "reflectivity / with the 8 frames as two asynchronous raw quartets (Eq. 7)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after timing, one device-to-device copy of this many MiB (for counter runs)")
     return ap.parse_args()
@@ -336,6 +338,63 @@ def bench_forward_320(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_cfg3_variant(args):
+    """cfg3's scene and batched forward + backward of 8 frames, with (cfg3sh)
+    spherical-harmonic colour and reflectivity of degree 3 (paper §3), or
+    (cfg3async) the 8 frames as two quartets of raw quads taken one offset at
+    a time, each rendering only its offset's channel at its own time with the
+    centres interpolated between the quartets' timesteps (Eq. 7).  Prints
+    one JSON line (frames/s, eager, HIP events)."""
+    import torch
+
+    import scenes
+    from paper_2505_05356_amd import raster
+
+    wl = scenes.cfg3()
+    g, frames, cfg = wl.gaussians, wl.frames, wl.cfg
+    if args.workload == "cfg3sh":
+        g = scenes.with_sh(g, 3, seed=1)
+        desc = "cfg3 with degree-3 spherical harmonics (48 colour + 16 reflectivity coefficients per Gaussian)"
+    else:
+        frames = scenes.async_quartet_frames(2, 0.125, frames[0])
+        desc = "cfg3 as two asynchronous quartets: 8 raw frames at t = (i + j/4) 0.125 s, one quad channel each"
+    F = len(frames)
+    params = raster.to_device_params(g, "cuda")
+    fdev = raster.pack_frames(frames, cfg, "cuda")
+    up = scenes.upstream_grads(F, cfg, seed=1)
+    d = {k: torch.from_numpy(v).cuda() for k, v in up.items()}
+    ws = raster.Workspace(g.n, F, cfg, device="cuda")
+    out = raster.alloc_outputs(F, cfg, "cuda")
+    raster.forward(params, fdev, cfg, ws, out=out, check=True)
+    grads = raster.backward(params, fdev, cfg, ws, out, d["rgb"], d["quad"], d["depth"])
+
+    def step():
+        raster.forward(params, fdev, cfg, ws, out=out, check=False)
+        raster.backward(params, fdev, cfg, ws, out, d["rgb"], d["quad"], d["depth"], grads=grads)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s_ev.record()
+    for _ in range(args.steps):
+        step()
+    e_ev.record()
+    torch.cuda.synchronize()
+    ms = s_ev.elapsed_time(e_ev) / args.steps
+    st = ws.status()
+    line = {
+        "metric": "fwd+bwd frames/s at 640x480, 200k Gaussians (batched, " + args.workload + ")",
+        "value": round(F * 1e3 / ms, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded dynamic Gaussian scene; no dataset)",
+        "config": {"workload": args.workload, "description": desc, "n_gaussians": g.n, "frames": F,
+                   "pairs": st["n_pairs"], "evals_fwd": st["n_evaluated"], "composited": st["n_composited"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -355,6 +414,8 @@ def main():
         return bench_mlp(args)
     if args.workload == "fwd320":
         return bench_forward_320(args)
+    if args.workload in ("cfg3sh", "cfg3async"):
+        return bench_cfg3_variant(args)
     if args.workload == "cfg2":
         wl = scenes.cfg2()
     elif args.workload == "cfg4":
