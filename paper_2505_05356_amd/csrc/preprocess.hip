@@ -227,19 +227,32 @@ __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g
             sh_basis((float)e0 * id, (float)e1 * id, (float)e2 * id, g.sh_degree, Y);
             const int K = sh_count(g.sh_degree);
             const int64_t n = P.n;
+            // degree 3 (all kMaxSH coefficients present): unguarded loads, so
+            // they issue together instead of one guarded load at a time
+            const bool full = K == kMaxSH;
             if (g.sh_rgb)
                 for (int c = 0; c < 3; ++c) {
                     float acc = 0.5f;
+                    if (full) {
 #pragma unroll
-                    for (int l = 0; l < kMaxSH; ++l)
-                        if (l < K) acc += Y[l] * g.sh_rgb[((int64_t)l * 3 + c) * n + k];
+                        for (int l = 0; l < kMaxSH; ++l) acc += Y[l] * g.sh_rgb[((int64_t)l * 3 + c) * n + k];
+                    } else {
+#pragma unroll
+                        for (int l = 0; l < kMaxSH; ++l)
+                            if (l < K) acc += Y[l] * g.sh_rgb[((int64_t)l * 3 + c) * n + k];
+                    }
                     rgb[c] = fmaxf(acc, 0.0f);
                 }
             if (g.sh_albedo) {
                 float acc = 0.5f;
+                if (full) {
 #pragma unroll
-                for (int l = 0; l < kMaxSH; ++l)
-                    if (l < K) acc += Y[l] * g.sh_albedo[(int64_t)l * n + k];
+                    for (int l = 0; l < kMaxSH; ++l) acc += Y[l] * g.sh_albedo[(int64_t)l * n + k];
+                } else {
+#pragma unroll
+                    for (int l = 0; l < kMaxSH; ++l)
+                        if (l < K) acc += Y[l] * g.sh_albedo[(int64_t)l * n + k];
+                }
                 albedo = (double)fmaxf(acc, 0.0f);
             }
         }
@@ -330,9 +343,44 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
         }
         for (int c = 0; c < 4; ++c) q0[c] = ld(g.quat, c * n + k);
         const float albedo = ld(g.albedo, k);
-        // SH coefficients of this Gaussian (re-read from cache where used)
-        auto kr = [&](int l, int c) { return (g.sh_rgb && l < K) ? g.sh_rgb[((int64_t)l * 3 + c) * n + k] : 0.f; };
-        auto ka = [&](int l) { return (g.sh_albedo && l < K) ? g.sh_albedo[(int64_t)l * n + k] : 0.f; };
+        // SH coefficients of this Gaussian, loaded once; at degree 3 (all
+        // kMaxSH present) unguarded, so the loads issue together
+        float shr[SH ? 3 * kMaxSH : 1], sha[SH ? kMaxSH : 1];
+        if constexpr (SH) {
+            const bool full = K == kMaxSH;
+#pragma unroll
+            for (int i = 0; i < 3 * kMaxSH; ++i) shr[i] = 0.f;
+#pragma unroll
+            for (int l = 0; l < kMaxSH; ++l) sha[l] = 0.f;
+            if (g.sh_rgb) {
+                if (full) {
+#pragma unroll
+                    for (int i = 0; i < 3 * kMaxSH; ++i) shr[i] = g.sh_rgb[(int64_t)i * n + k];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 3 * kMaxSH; ++i)
+                        if (i < 3 * K) shr[i] = g.sh_rgb[(int64_t)i * n + k];
+                }
+            }
+            if (g.sh_albedo) {
+                if (full) {
+#pragma unroll
+                    for (int l = 0; l < kMaxSH; ++l) sha[l] = g.sh_albedo[(int64_t)l * n + k];
+                } else {
+#pragma unroll
+                    for (int l = 0; l < kMaxSH; ++l)
+                        if (l < K) sha[l] = g.sh_albedo[(int64_t)l * n + k];
+                }
+            }
+        }
+        auto kr = [&](int l, int c) {
+            if constexpr (SH) return shr[3 * l + c];
+            else return 0.f;
+        };
+        auto ka = [&](int l) {
+            if constexpr (SH) return sha[l];
+            else return 0.f;
+        };
         const int RS4 = record_float4s(P.nf);
         const int GF = grad_floats(P.nf);
         const float L2E = 1.4426950408889634f;
