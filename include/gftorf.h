@@ -378,6 +378,27 @@ int gftorf_mlp_bwd_frames(const gftorf_mlp_config* cfg, const float* params, con
                           const float* d_delta, float* d_params, float* d_x0, int32_t accumulate_x0,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * inference forward of gftorf_mlp_fwd (save = 0) without a workspace
+ * argument.  delta [n_times][3][n] (overwritten) for canonical centres
+ * x0 [3][n] at the host `times` (n_times <= GFTORF_MLP_MAX_TIMES); same
+ * kernels and same result, bit for bit, as gftorf_mlp_fwd with save = 0.
+ * The bfloat16 weight copies it needs live in a static device array of
+ * GFTORF_MLP_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held
+ * until the process ends; a configuration whose weight copies do not fit is
+ * rejected with GFTORF_ENOWS (the supported 8 x 256 network needs about
+ * 1.9 MB).  The call allocates nothing, does not synchronise, and resolves
+ * the array's device address once per GPU on its first call there.  Every
+ * call on one GPU shares that GPU's array: calls that overlap in time on one
+ * GPU (other streams, other threads) race and give undefined offsets.
+ * Errors: GFTORF_EINVAL (bad configuration, NULL pointer, non-finite scale),
+ * GFTORF_ENOWS, GFTORF_EHIP. */
+#define GFTORF_MLP_NOALLOC_SCRATCH_BYTES (4u << 20)
+int gftorf_mlp_fwd_noalloc(const gftorf_mlp_config* cfg, const float* params, const float* x0,
+                           int64_t n, const float* times, int32_t n_times, float* delta,
+                           void* stream);
+
 /* Eq. 7 with the deformation network (paper §4): the network is evaluated at
  * integer timesteps only, and a raw frame between two of them takes the
  * straight line between the deformed positions.  With delta_steps

@@ -109,6 +109,8 @@ _SIGS = {
                                  c_int32, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
     "gftorf_mlp_bwd": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, POINTER(c_float),
                                  c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gftorf_mlp_fwd_noalloc": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, POINTER(c_float),
+                                         c_int32, c_void_p, c_void_p]),
     "gftorf_mlp_fwd_frames": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, c_void_p, c_int32,
                                         c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
     "gftorf_mlp_bwd_frames": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, c_void_p, c_int32,

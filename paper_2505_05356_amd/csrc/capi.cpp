@@ -431,6 +431,28 @@ int gftorf_mlp_bwd(const gftorf_mlp_config* cfg, const float* params, const floa
     return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_mlp_bwd");
 }
 
+int gftorf_mlp_fwd_noalloc(const gftorf_mlp_config* cfg, const float* params, const float* x0,
+                           int64_t n, const float* times, int32_t n_times, float* delta,
+                           void* stream) {
+    gft::mlp::Layout L;
+    if (!mlp_layout(cfg, n, n_times, false, &L))
+        return fail(GFTORF_EINVAL, "unsupported network: width must be 256, depth 8, "
+                                   "3 (1 + 2 L_x) + 1 + 2 L_t <= 96, 1 <= n_times <= 64");
+    if (L.bytes > gft::mlp::kNoAllocScratchBytes)
+        return fail(GFTORF_ENOWS, "weight copies need " + std::to_string(L.bytes) +
+                                      " bytes, more than the static scratch holds");
+    if (!params || !x0 || !times || !delta) return fail(GFTORF_EINVAL, "NULL pointer");
+    char* scratch = nullptr;
+    hipError_t e = gft::mlp::noalloc_scratch(&scratch);
+    if (e != hipSuccess) return hip_fail(e, "gftorf_mlp_fwd_noalloc (static scratch address)");
+    gft::mlp::Call c;
+    const int rc = mlp_call(cfg, params, x0, n, times, nullptr, n_times, scratch, L.bytes, false, &L, &c);
+    if (rc != GFTORF_OK) return rc;
+    (void)hipGetLastError();
+    e = gft::mlp::launch_fwd(L, c, delta, false, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_mlp_fwd_noalloc");
+}
+
 int gftorf_mlp_fwd_frames(const gftorf_mlp_config* cfg, const float* params, const float* x0,
                           int64_t n, const gftorf_frame* frames, int32_t n_frames, float* delta,
                           int32_t save, void* ws, size_t ws_bytes, void* stream) {

@@ -52,6 +52,13 @@ struct Call {
 
 hipError_t launch_fwd(const Layout& L, const Call& c, float* delta, bool save, hipStream_t s);
 
+// Allocation-free inference forward: the packed weights go to a file-scope
+// device array of kNoAllocScratchBytes instead of a caller workspace.
+constexpr size_t kNoAllocScratchBytes = GFTORF_MLP_NOALLOC_SCRATCH_BYTES;
+// Device address of the current GPU's copy of that array, resolved with
+// hipGetSymbolAddress on the first call on each device and kept.
+hipError_t noalloc_scratch(char** out);
+
 constexpr int kMaxBlendFrames = GFTORF_MAX_BLEND_FRAMES;
 struct Blend {
     int32_t anchors[2 * kMaxBlendFrames];   // (lo, hi) step of every frame

@@ -32,11 +32,19 @@
 // forward also keeps the ReLU decisions of h_1 .. h_8 as bits, 16 bytes per
 // lane and layer in the lane's own accumulator order, so the backward gates
 // its gradients from 4 registers instead of re-reading the activations.
+#include <mutex>
+
 #include "mlp.h"
 
 namespace gft {
 namespace mlp {
 namespace {
+
+// Scratch of gftorf_mlp_fwd_noalloc: the bfloat16 weight copies of one
+// inference forward.  Every GPU the library runs on holds its own copy until
+// the process ends.  In host code this name is only a stand-in for the
+// symbol: kernels receive the device address that noalloc_scratch resolves.
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -650,6 +658,26 @@ Args make_args(const Layout& L, const Call& c) {
 }
 
 }  // namespace
+
+hipError_t noalloc_scratch(char** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static char* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256) return hipErrorInvalidValue;
+        addr[dev] = static_cast<char*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
 
 bool make_layout(int lx, int lt, int width, int depth, int64_t n, int n_times, bool training,
                  Layout* L) {

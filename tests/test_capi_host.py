@@ -149,3 +149,22 @@ def test_mlp_device_time_entry_points_check_arguments(lib):
                                      dev, need, None) == _lib.EINVAL
     assert lib.gftorf_mlp_bwd_frames(ctypes.byref(cfg), dev, dev, 1000, dev, 2, None, dev, dev, 1,
                                      dev, need, None) == _lib.EINVAL
+
+
+def test_mlp_noalloc_checks_arguments(lib):
+    # the allocation-free inference forward refuses bad shapes and missing
+    # pointers before it resolves its static scratch or launches anything,
+    # and the supported network's weight copies fit that scratch
+    from paper_2505_05356_amd import _lib
+    cfg = _lib.MlpConfigC(10, 10, 256, 8, 0.2, 4.0)
+    need = lib.gftorf_mlp_workspace_size(ctypes.byref(cfg), 1000, 2, 0)
+    assert 0 < need <= 4 << 20
+    times = (ctypes.c_float * 2)(0.0, 0.1)
+    dev = ctypes.c_void_p(256)
+    assert lib.gftorf_mlp_fwd_noalloc(ctypes.byref(cfg), None, dev, 1000, times, 2, dev, None) == _lib.EINVAL
+    assert lib.gftorf_mlp_fwd_noalloc(ctypes.byref(cfg), dev, dev, 1000, None, 2, dev, None) == _lib.EINVAL
+    assert lib.gftorf_mlp_fwd_noalloc(ctypes.byref(cfg), dev, dev, 1000, times, 2, None, None) == _lib.EINVAL
+    assert lib.gftorf_mlp_fwd_noalloc(ctypes.byref(cfg), dev, dev, 1000, times, 65, dev, None) == _lib.EINVAL
+    assert lib.gftorf_mlp_fwd_noalloc(ctypes.byref(cfg), dev, dev, 0, times, 2, dev, None) == _lib.EINVAL
+    bad = _lib.MlpConfigC(10, 10, 128, 8, 0.2, 4.0)
+    assert lib.gftorf_mlp_fwd_noalloc(ctypes.byref(bad), dev, dev, 1000, times, 2, dev, None) == _lib.EINVAL
