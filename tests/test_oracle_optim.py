@@ -53,6 +53,33 @@ def test_l2_loss_gradient_central_differences():
             assert (lp - lm) / (2 * h) == pytest.approx(grad[idx], rel=1e-6)
 
 
+def test_l2_loss_closed_forms():
+    # Eq. 9's L2 part, w_q mean((q - q*)^2) + mean((c - c*)^2), with the two
+    # means taken over tensors of different sizes (3 colour channels, 8 quad
+    # channels at two frequencies, unequal frame counts).
+    # (a) constant residuals c_r, c_q: L = w_q c_q^2 + c_r^2 whatever the sizes,
+    #     and every gradient element is 2 c / (elements of its tensor), the
+    #     quad one times w_q
+    rng = np.random.default_rng(3)
+    tr, tq = rng.normal(size=(2, 3, 7, 5)), rng.normal(size=(3, 8, 6, 4))
+    cr, cq, w = 0.375, -1.25, 3.0
+    loss, dr, dq = optim.l2_loss_grad(tr + cr, tq + cq, tr, tq, quad_weight=w)
+    assert loss == pytest.approx(w * cq * cq + cr * cr, rel=1e-13)
+    np.testing.assert_allclose(dr, 2 * cr / tr.size, rtol=1e-13)
+    np.testing.assert_allclose(dq, w * 2 * cq / tq.size, rtol=1e-13)
+    # (b) one non-zero residual d in each tensor: L = w_q d_q^2 / |q| + d_r^2 / |c|
+    pr, pq = tr.copy(), tq.copy()
+    pr[1, 2, 3, 4] += 0.5
+    pq[2, 7, 0, 1] -= 2.0
+    loss, dr, dq = optim.l2_loss_grad(pr, pq, tr, tq, quad_weight=w)
+    assert loss == pytest.approx(w * 4.0 / tq.size + 0.25 / tr.size, rel=1e-12)
+    assert np.count_nonzero(dr) == 1 and dr[1, 2, 3, 4] == pytest.approx(2 * 0.5 / tr.size, rel=1e-12)
+    assert np.count_nonzero(dq) == 1 and dq[2, 7, 0, 1] == pytest.approx(-w * 2 * 2.0 / tq.size, rel=1e-12)
+    # (c) zero quad weight: the quads do not enter
+    loss, _, dq = optim.l2_loss_grad(tr + cr, tq + cq, tr, tq, quad_weight=0.0)
+    assert loss == pytest.approx(cr * cr, rel=1e-13) and not np.any(dq)
+
+
 def test_paper_constants():
     g = _golden()
     assert [float(eval(x.replace("pi", "*math.pi").lstrip("*") if "pi" in x else x))
