@@ -43,15 +43,23 @@ FWD_FLOP_PER_COMP = 16
 BWD_FLOP_PER_COMP = 87
 SORT_BYTES_PER_KEY_PASS = 16  # read key + value, write key + value (4 B each)
 
-# HBM traffic per launch of the composite kernels from rocprofv3 counter runs
-# of this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled
-# by what the same counter reads for a plain device copy of known size
-# (--calibration-copy-mib).  A figure holds only for the kernel source it was
-# measured on: the sha256 of the listed files must match, else traffic is null.
+# HBM traffic per launch from rocprofv3 counter runs of this script
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same
+# counter reads for a plain device copy of known size (--calibration-copy-mib).
+# A figure holds only for the workload and the kernel source it was measured
+# on: it is keyed by the workload name of the JSON line and the kernel, and
+# the sha256 of the kernel's source files must match; otherwise traffic is null.
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524318, 1048576 / 1048576   # 1 GiB copy: FETCH 524318 KiB, WRITE 1048576 KiB
-TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
-TRAFFIC_SHA256 = "c7d6b25f8a98437c5591d603b219aa47546d05ed64456dcdde89aaa3a85f209d"
-TRAFFIC_KIB = {"k_composite_bwd": (52022, 51901), "k_composite_fwd": (4815, 96136)}   # KiB per launch
+COMPOSITE_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
+MLP_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
+# {workload: {kernel: (source files, sha256, (FETCH KiB, WRITE KiB) per launch)}};
+# k_mlp_dw counts its three launches together
+TRAFFIC = {
+    "deform-mlp-200k-x8-8x256-pe10": {
+        k: (MLP_FILES, "f1b745f06183ff2d944649cbf7dd720bad7364413c623bf710699554d42ef79f", kib)
+        for k, kib in (("k_mlp_fwd", (218924, 7156260)), ("k_mlp_bwd", (364013, 6468750)),
+                       ("k_mlp_dw", (6575126, 275391)))},
+}
 
 
 def parse():
@@ -137,6 +145,15 @@ def bench_train_step(args):
     e_ev.record(ts.stream)
     torch.cuda.synchronize()
     ms = s_ev.elapsed_time(e_ev)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_train(tr, seq, cfg, theta.cpu().numpy() if with_net else None, args.cpu_budget)
+    # every replayed forward (capture, warm-up and timed) must have rendered
+    # complete tile lists: the status keeps the OR of their overflow flags
+    st = ts.status()
+    if st["overflow_seen"]:
+        raise SystemExit(f"pair capacity overflowed in a replayed step (largest pair count "
+                         f"{st['n_pairs_seen']} > capacity {st['max_pairs']}): the timing is invalid")
     line = {
         "metric": ("optimisation steps/s (4-frame batch: deformation network fwd + render fwd + L2 loss + "
                    "render bwd + network bwd + Adam, one HIP graph)" if with_net else
@@ -148,32 +165,55 @@ def bench_train_step(args):
         "config": {"workload": f"train-{tr.n // 1000}k-{S}f-{W}x{H}-batch4" + ("-deform-mlp" if with_net else ""),
                    "n_gaussians": tr.n, "network_rows": 4 * tr.n if with_net else 0,
                    "sequence_frames": S, "batch": 4, "wall_s": round(time.perf_counter() - t0, 3),
-                   "loss_after_warmup": l0, "loss_last": ts.loss.item()},
+                   "loss_after_warmup": l0, "loss_last": ts.loss.item(),
+                   "pairs_max": st["n_pairs_seen"], "pair_capacity": st["max_pairs"]},
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
 
-# the same for the deformation network's kernels (k_mlp_dw: its three launches together)
-MLP_TRAFFIC_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
-MLP_TRAFFIC_SHA256 = "f1b745f06183ff2d944649cbf7dd720bad7364413c623bf710699554d42ef79f"
-MLP_TRAFFIC_KIB = {"k_mlp_fwd": (218924, 7156260), "k_mlp_bwd": (364013, 6468750),
-                   "k_mlp_dw": (6575126, 275391)}   # KiB per launch, 1.6M rows
 
 
-def traffic_bytes(name, files=TRAFFIC_FILES, sha=TRAFFIC_SHA256, table=TRAFFIC_KIB):
-    """Counter-measured HBM bytes per launch of `name`, or None when there is
-    no measurement for the kernel source as it is now."""
+def source_sha256(files):
     import hashlib
-    if name not in table or sha is None or FETCH_SCALE is None:
-        return None
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != sha:
+    return h.hexdigest()
+
+
+def traffic_bytes(workload, name):
+    """Counter-measured HBM bytes per launch of kernel `name` on `workload`,
+    or None when there is no measurement of that workload with the kernel
+    source as it is now."""
+    entry = TRAFFIC.get(workload, {}).get(name)
+    if entry is None:
         return None
-    fetch, write = table[name]
+    files, sha, (fetch, write) = entry
+    if source_sha256(files) != sha:
+        return None
     return int(round((fetch * FETCH_SCALE + write * WRITE_SCALE) * 1024))
+
+
+def host_info():
+    """CPUs this process may run on (nproc) and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def oracle_threads():
+    """Threads the FP64 oracle's numpy / torch-CPU arithmetic may use."""
+    import torch
+    return max(torch.get_num_threads(), int(os.environ.get("OMP_NUM_THREADS", "1") or 1))
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix peak
@@ -248,9 +288,7 @@ def bench_mlp(args):
                                  hbm_frac=round(gbs / HBM_PEAK_GBS, 4), bound=bound)
     dominant = max(per_kernel, key=lambda k: per_kernel[k]["avg_ms"])
     pk = per_kernel[dominant]
-    traffic = None
-    if n == 200_000 and T == 8:   # the counters were taken on this shape
-        traffic = traffic_bytes(dominant, MLP_TRAFFIC_FILES, MLP_TRAFFIC_SHA256, MLP_TRAFFIC_KIB)
+    traffic = traffic_bytes(f"deform-mlp-{n // 1000}k-x{T}-8x256-pe10", dominant)
     if pk["bound"] == "hbm":
         roof = dict(bound="hbm", achieved=pk["hbm_gbs"], peak=HBM_PEAK_GBS, unit="GB/s", frac=pk["hbm_frac"],
                     traffic=traffic, kernel=dominant, avg_ms=pk["avg_ms"],
@@ -282,8 +320,9 @@ def bench_mlp(args):
             omlp.backward(th, cache, rng.normal(size=(R, 3)))
             reps += 1
         dt = time.perf_counter() - t0
-        cpu = {"value": round(reps * R / dt, 1), "unit": "rows/s", "cores": torch.get_num_threads(),
-               "kind": "oracle", "sample": f"{reps} x {R} rows forward + backward (FP64 numpy)"}
+        cpu = {"value": round(reps * R / dt, 1), "unit": "rows/s", "cores": oracle_threads(),
+               "kind": "oracle", "sample": f"{reps} x {R} rows forward + backward (FP64 numpy)",
+               **host_info()}
     line = {
         "metric": "deformation MLP fwd+bwd rows/s (200k Gaussians x 8 times)",
         "value": round(rows / (ms / 1e3), 1), "unit": "rows/s", "n_gpus": 1,
@@ -550,7 +589,11 @@ def main():
     work = dict(P=P, E_fwd=st["n_evaluated"], C=st["n_composited"],
                 E_bwd=int(out["n_contrib"].sum().item()))   # backward walks up to n_contrib
     roof = roofline(dominant, kern[dominant]["avg_ms"], **work)
-    roof["traffic"] = traffic_bytes(dominant)
+    workload = (wl.name if args.workload != "cfg3" else
+                f"dynamic-{g.n // 1000}k-gaussians-{F}f-{cfg.width}x{cfg.height}")
+    if args.tile != "16x16":
+        workload += f"-{args.tile}"
+    roof["traffic"] = traffic_bytes(workload, dominant)
     print("# kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f}ms x{v['launches'] // args.steps}"
                                     for k, v in sorted(kern.items(), key=lambda kv: -kv[1]["total_ms"])),
           file=sys.stderr, flush=True)
@@ -580,9 +623,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded dynamic Gaussian scene; no dataset)",
-        "config": {"workload": wl.name if args.workload != "cfg3" else
-                   f"dynamic-{g.n // 1000}k-gaussians-{F}f-{cfg.width}x{cfg.height}",
-                   "n_gaussians": g.n, "frames": F, "width": cfg.width, "height": cfg.height,
+        "config": {"workload": workload, "n_gaussians": g.n, "frames": F, "width": cfg.width, "height": cfg.height,
                    "tile": args.tile, "freqs_hz": list(cfg.freqs), "quads": cfg.n_quad,
                    "outputs": "rgb+quad+depth", "pairs": P, "evals_fwd": work["E_fwd"],
                    "evals_bwd": work["E_bwd"], "composited": work["C"],
@@ -596,6 +637,51 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_train(g, seq, cfg, theta, budget_s):
+    """The FP64 oracle as it stands for one optimisation step of the 4-frame
+    batch: forward + backward of one frame on a bounded tile sample
+    (cpu_baseline), times 4; the L2 loss and its gradient over the batch and
+    Adam over every parameter, timed in full; with the network, its forward +
+    backward on a 512-row sample extrapolated to the batch's rows."""
+    import scenes
+    from oracle import optim as oopt
+    wl = scenes.Workload("train", g, list(seq[:1]), cfg)
+    frame = cpu_baseline(wl, cfg, scenes.upstream_grads(1, cfg, seed=1), budget_s)
+    t_frame = 1.0 / frame["value"]
+    rng = np.random.default_rng(0)
+    H, W, B = cfg.height, cfg.width, 4
+    pr, tr_ = rng.normal(size=(B, 3, H, W)), rng.normal(size=(B, 3, H, W))
+    pq, tq = rng.normal(size=(B, cfg.n_quad, H, W)), rng.normal(size=(B, cfg.n_quad, H, W))
+    t0 = time.perf_counter()
+    oopt.l2_loss_grad(pr, pq, tr_, tq)
+    t_loss = time.perf_counter() - t0
+    P = 24 * g.n
+    p, gr = rng.normal(size=P), rng.normal(size=P)
+    t0 = time.perf_counter()
+    oopt.adam_step(p, gr, np.zeros(P), np.zeros(P), 1, 1e-3)
+    t_adam = time.perf_counter() - t0
+    t_net, net_note = 0.0, ""
+    if theta is not None:
+        from oracle import mlp as omlp
+        R = 512
+        xs, ts = rng.uniform(-0.5, 0.5, (R, 3)), rng.uniform(0, 1, R)
+        t0, reps = time.perf_counter(), 0
+        while time.perf_counter() - t0 < min(budget_s, 10.0) or reps == 0:
+            _, cache = omlp.forward(theta, xs, ts)
+            omlp.backward(theta, cache, rng.normal(size=(R, 3)))
+            reps += 1
+        t_row = (time.perf_counter() - t0) / (reps * R)
+        t0 = time.perf_counter()
+        oopt.adam_step(theta, theta, np.zeros_like(theta), np.zeros_like(theta), 1, 1e-3)
+        t_net = B * g.n * t_row + time.perf_counter() - t0
+        net_note = f" + network fwd+bwd {B * g.n} rows at {t_row * 1e6:.1f} us/row ({reps} x {R}-row sample)"
+    per_step = B * t_frame + t_loss + t_adam + t_net
+    return {"value": round(1.0 / per_step, 6), "unit": "steps/s", "cores": oracle_threads(),
+            **host_info(), "kind": "oracle",
+            "sample": f"{B} frames x ({frame['sample']}) + L2 loss {t_loss:.2f} s + Adam over {P} "
+                      f"parameters {t_adam:.2f} s{net_note}, extrapolated"}
 
 
 def roofline(name, avg_ms, P, E_fwd, E_bwd, C):
@@ -654,7 +740,7 @@ def cpu_baseline(wl, cfg, up, budget_s):
         step *= 2
     per_tile = t_tiles / max(done, 1)
     per_frame = t_fixed + per_tile * n_tiles
-    return {"value": round(1.0 / per_frame, 6), "unit": "frames/s", "cores": torch.get_num_threads(),
+    return {"value": round(1.0 / per_frame, 6), "unit": "frames/s", "cores": oracle_threads(), **host_info(),
             "kind": "oracle",
             "sample": f"frame 0 fwd+bwd on {done} of {n_tiles} tiles (seeded order); per frame = "
                       f"{t_fixed:.2f} s fixed (binning + per-Gaussian chain) + {per_tile:.4f} s/tile "

@@ -180,6 +180,12 @@ typedef struct gftorf_status {
     int32_t nonfinite;   /* Gaussians culled because an input was NaN / Inf                   */
     int64_t n_evaluated; /* (pixel, list entry) opacity evaluations of the last forward       */
     int64_t n_composited;/* (pixel, list entry) pairs composited by the last forward          */
+    /* sticky over every forward on ws since its first 64 bytes were last
+     * cleared (by the caller, or gftorf_clear_status): e.g. across replays
+     * of a captured optimisation step, whose parameters move between forwards */
+    int32_t overflow_seen;   /* 1 if any of those forwards overflowed                      */
+    int32_t reserved;
+    int64_t n_pairs_seen;    /* largest pair count among them                              */
 } gftorf_status;
 
 /* Bytes of workspace needed for n Gaussians, n_frames frames and cfg
@@ -222,6 +228,12 @@ int gftorf_render_bwd(const gftorf_gaussians* g, const gftorf_frame* frames, int
  * counts (zero if no forward has filled this workspace since its first 64
  * bytes were cleared). */
 int gftorf_read_status(const void* ws, gftorf_status* out, void* stream);
+
+/* Clears the status header of ws (its first 64 bytes: the last forward's
+ * fields and the sticky overflow_seen / n_pairs_seen) with a kernel on
+ * `stream`, so it may be captured in a graph.  Errors: GFTORF_EINVAL (NULL
+ * or misaligned ws), GFTORF_EHIP. */
+int gftorf_clear_status(void* ws, void* stream);
 
 /* Introspection of the forward's binning, for tests and tools: copies
  * (device to device, asynchronously on `stream`) from the workspace of the
@@ -364,6 +376,23 @@ int gftorf_mlp_fwd(const gftorf_mlp_config* cfg, const float* params, const floa
 int gftorf_mlp_bwd(const gftorf_mlp_config* cfg, const float* params, const float* x0, int64_t n,
                    const float* times, int32_t n_times, const float* d_delta, float* d_params,
                    float* d_x0, void* ws, size_t ws_bytes, void* stream);
+
+/* The ReLU decisions of the hidden layers (paper §4, "MLP": which units of
+ * h_1 .. h_depth are active, z > 0 as the forward decided it in its own
+ * precision), for tests and diagnostics.  decisions is a device array of
+ * bytes [n_times * n][depth][width], row t * n + k for time t and Gaussian k,
+ * 1 = active, 0 = inactive (any non-zero byte reads as active when set).
+ * gftorf_mlp_get_decisions copies out what the last gftorf_mlp_fwd with
+ * save = 1 recorded in ws; gftorf_mlp_set_decisions replaces them, so that
+ * the next gftorf_mlp_bwd on this ws gates its gradients with the given
+ * pattern (the saved activations stay the forward's).  ws, n and n_times are
+ * those of the training forward (ws sized with training = 1); the caller owns
+ * decisions.  Asynchronous on the stream.  Errors: GFTORF_EINVAL (bad
+ * configuration, NULL pointer, misaligned ws), GFTORF_ENOWS, GFTORF_EHIP. */
+int gftorf_mlp_get_decisions(const gftorf_mlp_config* cfg, int64_t n, int32_t n_times,
+                             uint8_t* decisions, void* ws, size_t ws_bytes, void* stream);
+int gftorf_mlp_set_decisions(const gftorf_mlp_config* cfg, int64_t n, int32_t n_times,
+                             const uint8_t* decisions, void* ws, size_t ws_bytes, void* stream);
 
 /* The same with the times read on the device from frames[0 .. n_frames)
  * (.time of each descriptor), so a replayed graph follows the frames that

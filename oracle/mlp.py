@@ -111,17 +111,52 @@ def round_bf16(x):
     return b.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def _decisions(W, b, x_in, t_in, lx, lt, depth):
+# A float32 evaluation with bfloat16 operands, in any accumulation order,
+# reaches pre-activations z close to the bfloat16 shadow's below: apart from
+# its own float32 rounding, an activation it passes on may round to the
+# neighbouring bfloat16 value, and such one-step differences spread over the
+# layers.  Measured over many accumulation orders of the 8 x 256 network, the
+# drift stays below 2.5e-3 of the unit's scale |b| + sum_k |h_k w_k|;
+# DECISION_MARGIN bounds it with headroom.  So two such evaluations can take
+# a unit's ReLU decision differently only where |z| <= DECISION_MARGIN scale.
+DECISION_MARGIN = 1e-2
+
+
+def _decisions(W, b, x_in, t_in, lx, lt, depth, margins: bool = False):
     """Active-unit masks of the hidden layers evaluated as the products are:
-    scaled inputs rounded to float32, bfloat16 operands."""
+    scaled inputs rounded to float32, bfloat16 operands.  With margins, also
+    |z| / scale of every hidden unit (scale = |b| + sum_k |h_k w_k|)."""
     x32 = np.asarray(x_in, np.float64).astype(np.float32).astype(np.float64)
     t32 = np.asarray(t_in, np.float64).astype(np.float32).astype(np.float64)
-    masks, h = [], round_bf16(network_input(x32, t32, lx, lt))
+    masks, ratios, h = [], [], round_bf16(network_input(x32, t32, lx, lt))
     for l in range(depth):
-        z = h @ round_bf16(W[l]).T + b[l]
+        w = round_bf16(W[l])
+        z = h @ w.T + b[l]
         masks.append(z > 0.0)
+        if margins:
+            scale = np.abs(h) @ np.abs(w).T + np.abs(b[l])
+            ratios.append(np.abs(z) / np.maximum(scale, 1e-300))
         h = round_bf16(np.maximum(z, 0.0))
-    return masks
+    return (masks, ratios) if margins else masks
+
+
+def decision_table(theta, x_in, t_in, lx: int = 10, lt: int = 10, width: int = 256,
+                   depth: int = 8):
+    """The decisions forward(..., decide="bf16") takes, as booleans
+    [R, depth, width], and each unit's |z| / scale in the same layout: a
+    float32 / bfloat16 evaluation may decide a unit differently only where
+    that ratio is at most DECISION_MARGIN."""
+    W, b = unpack(theta, layer_shapes(n_inputs(lx, lt), width, depth))
+    masks, ratios = _decisions(W, b, x_in, t_in, lx, lt, depth, margins=True)
+    return np.stack(masks, axis=1), np.stack(ratios, axis=1)
+
+
+def offsets_decision_table(theta, x0, times, s_x, s_t, lx: int = 10, lt: int = 10,
+                           width: int = 256, depth: int = 8):
+    """decision_table of the rows of offsets(...): row t N + k for time t and
+    Gaussian k."""
+    x_in, t_in, _, _ = _rows(x0, times, s_x, s_t)
+    return decision_table(theta, x_in, t_in, lx, lt, width, depth)
 
 
 def forward(theta, x_in, t_in, lx: int = 10, lt: int = 10, width: int = 256, depth: int = 8,
@@ -166,9 +201,12 @@ def backward(theta, cache, d_out):
     gt = d_enc[:, nx:] * encode_grad(cache["t_in"][:, None], lt)
     d_x = gx.reshape(len(gx), 1 + 2 * lx, 3).sum(axis=1)
     d_t = gt.sum(axis=1)
-    # magnitude of the terms d_x sums (it cancels: the encoding's derivatives
-    # reach 2^(L-1) pi), the scale of its rounding errors in any precision
-    cache["d_x_terms"] = np.abs(gx).reshape(len(gx), 1 + 2 * lx, 3).sum(axis=1)
+    # magnitude of the terms d_x sums: d_x = sum_f enc'_f sum_j g_j W_0[j, f]
+    # (g the first layer's pre-activation gradient), and both sums cancel (the
+    # encoding's derivatives reach 2^(L-1) pi), so the scale of its rounding
+    # errors in any precision is sum_f |enc'_f| sum_j |g_j W_0[j, f]|
+    terms = (np.abs(g) @ np.abs(W[0]))[:, :nx] * np.abs(encode_grad(cache["x_in"], lx))
+    cache["d_x_terms"] = terms.reshape(len(gx), 1 + 2 * lx, 3).sum(axis=1)
     flat = np.concatenate([np.concatenate([w.ravel(), c]) for w, c in zip(dW, db)])
     return flat, d_x, d_t
 

@@ -65,7 +65,8 @@ class OutputsC(ctypes.Structure):
 
 class StatusC(ctypes.Structure):
     _fields_ = [("n_pairs", c_int64), ("max_pairs", c_int64), ("overflow", c_int32),
-                ("nonfinite", c_int32), ("n_evaluated", c_int64), ("n_composited", c_int64)]
+                ("nonfinite", c_int32), ("n_evaluated", c_int64), ("n_composited", c_int64),
+                ("overflow_seen", c_int32), ("reserved", c_int32), ("n_pairs_seen", c_int64)]
 
 
 class AdamGroupC(ctypes.Structure):
@@ -86,6 +87,7 @@ _SIGS = {
                                     POINTER(OutputsC), c_void_p, c_void_p, c_void_p,
                                     POINTER(GaussiansGradC), c_void_p, c_void_p, c_size_t, c_void_p]),
     "gftorf_read_status": (c_int32, [c_void_p, POINTER(StatusC), c_void_p]),
+    "gftorf_clear_status": (c_int32, [c_void_p, c_void_p]),
     "gftorf_copy_lists": (c_int32, [c_void_p, c_int64, c_int32, POINTER(ConfigC), c_void_p,
                                     c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_void_p, c_void_p]),
@@ -109,6 +111,10 @@ _SIGS = {
                                  c_int32, c_void_p, c_int32, c_void_p, c_size_t, c_void_p]),
     "gftorf_mlp_bwd": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, POINTER(c_float),
                                  c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gftorf_mlp_get_decisions": (c_int32, [POINTER(MlpConfigC), c_int64, c_int32, c_void_p, c_void_p,
+                                           c_size_t, c_void_p]),
+    "gftorf_mlp_set_decisions": (c_int32, [POINTER(MlpConfigC), c_int64, c_int32, c_void_p, c_void_p,
+                                           c_size_t, c_void_p]),
     "gftorf_mlp_fwd_noalloc": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, POINTER(c_float),
                                          c_int32, c_void_p, c_void_p]),
     "gftorf_mlp_fwd_frames": (c_int32, [POINTER(MlpConfigC), c_void_p, c_void_p, c_int64, c_void_p, c_int32,

@@ -2,11 +2,15 @@
 shape (8x8, 16x16, 32x8) on the caller's problem and keeps the fastest.
 
 Results are cached per problem signature (Gaussians, frames, image size,
-frequencies, phases) in a JSON file, so a training loop tunes once.
+frequencies, phases) and per build (a hash of the loaded libgftorf.so, its
+version and the GPU architecture) in a JSON file, so a training loop tunes
+once and a rebuilt library or another GPU tunes again.
 """
 from __future__ import annotations
 
 import dataclasses
+import functools
+import hashlib
 import json
 import os
 from typing import Dict, Optional, Sequence, Tuple
@@ -18,8 +22,21 @@ from . import raster
 CANDIDATES = ((8, 8), (16, 16), (32, 8))
 
 
-def signature(n: int, n_frames: int, cfg) -> str:
-    return f"n{n}-f{n_frames}-{cfg.width}x{cfg.height}-nf{len(cfg.freqs)}-np{len(cfg.phases)}"
+@functools.lru_cache(maxsize=None)
+def build_id(device_index: int = 0) -> str:
+    """Library version, a hash of the loaded library file and the GPU
+    architecture: a tile choice holds only for the kernels and GPU it was
+    timed on."""
+    lib = raster._lib.load()
+    with open(lib._name, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()[:16]
+    arch = torch.cuda.get_device_properties(device_index).gcnArchName.split(":")[0]
+    return f"v{int(lib.gftorf_version())}-{digest}-{arch}"
+
+
+def signature(n: int, n_frames: int, cfg, device_index: int = 0) -> str:
+    return (f"n{n}-f{n_frames}-{cfg.width}x{cfg.height}-nf{len(cfg.freqs)}-np{len(cfg.phases)}-"
+            + build_id(device_index))
 
 
 def _time(params, frames_dev, cfg, upstream, reps: int, warmup: int) -> float:
@@ -54,7 +71,8 @@ def autotune(params: Dict[str, torch.Tensor], frames_dev: torch.Tensor, cfg,
              cache_path: Optional[str] = None):
     """Returns (cfg with the fastest tile shape, {"WxH": ms per fwd(+bwd)})."""
     n = params["opacity_logit"].shape[0]
-    key = signature(n, frames_dev.shape[0], cfg)
+    dev = frames_dev.device
+    key = signature(n, frames_dev.shape[0], cfg, dev.index if dev.index is not None else torch.cuda.current_device())
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as fh:

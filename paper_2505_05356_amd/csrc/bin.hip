@@ -478,6 +478,8 @@ __global__ void __launch_bounds__(1024) k_tile_keyscan(const uint32_t* __restric
         status->n_pairs = carry;
         status->cap = cap;
         status->overflow = carry > cap ? 1u : 0u;
+        status->overflow_seen |= carry > cap ? 1u : 0u;
+        if (carry > status->n_pairs_seen) status->n_pairs_seen = carry;
         status->nonfinite = nf_sum;
         status->wcount_off = wcount_off;
         status->n_items = (unsigned long long)K;

@@ -266,6 +266,9 @@ int gftorf_read_status(const void* ws, gftorf_status* out, void* stream) {
     out->max_pairs = (int64_t)st.cap;
     out->overflow = (int32_t)st.overflow;
     out->nonfinite = (int32_t)st.nonfinite;
+    out->overflow_seen = (int32_t)st.overflow_seen;
+    out->reserved = 0;
+    out->n_pairs_seen = (int64_t)st.n_pairs_seen;
     out->n_evaluated = out->n_composited = 0;
     // the forward's per-work-item counts, summed here (the stream is idle)
     if (st.magic == gft::kStatusMagic && st.n_items > 0 && st.n_items <= (1ull << 26) &&
@@ -284,6 +287,16 @@ int gftorf_read_status(const void* ws, gftorf_status* out, void* stream) {
     }
     if (st.overflow) return fail(GFTORF_EOVERFLOW, "pairs exceeded max_pairs: " + std::to_string(st.n_pairs));
     return GFTORF_OK;
+}
+
+int gftorf_clear_status(void* ws, void* stream) {
+    if (!ws) return fail(GFTORF_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GFTORF_EINVAL, "workspace must be 256-byte aligned");
+    (void)hipGetLastError();
+    gft::launch_fill_u32(static_cast<uint32_t*>(ws), 0u, (int64_t)(sizeof(gft::Status) / 4),
+                         static_cast<hipStream_t>(stream));
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_clear_status");
 }
 
 int gftorf_copy_lists(const void* ws, int64_t n, int32_t n_frames, const gftorf_config* cfg,
@@ -429,6 +442,34 @@ int gftorf_mlp_bwd(const gftorf_mlp_config* cfg, const float* params, const floa
     (void)hipGetLastError();
     const hipError_t e = gft::mlp::launch_bwd(L, c, d_delta, d_params, d_x0, false, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? GFTORF_OK : hip_fail(e, "gftorf_mlp_bwd");
+}
+
+namespace {
+int mlp_decisions(const gftorf_mlp_config* cfg, int64_t n, int32_t n_times, uint8_t* dec, bool write,
+                  void* ws, size_t ws_bytes, void* stream, const char* what) {
+    gft::mlp::Layout L;
+    if (!mlp_layout(cfg, n, n_times, true, &L))
+        return fail(GFTORF_EINVAL, "unsupported network: width must be 256, depth 8, "
+                                   "3 (1 + 2 L_x) + 1 + 2 L_t <= 96, 1 <= n_times <= 64");
+    if (!dec || !ws) return fail(GFTORF_EINVAL, "NULL pointer");
+    if (ws_bytes < L.bytes) return fail(GFTORF_ENOWS, "workspace too small for the training network");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(GFTORF_EINVAL, "workspace must be 256-byte aligned");
+    (void)hipGetLastError();
+    const hipError_t e = gft::mlp::launch_decisions(L, static_cast<char*>(ws), dec, write,
+                                                    static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GFTORF_OK : hip_fail(e, what);
+}
+}  // namespace
+
+int gftorf_mlp_get_decisions(const gftorf_mlp_config* cfg, int64_t n, int32_t n_times,
+                             uint8_t* decisions, void* ws, size_t ws_bytes, void* stream) {
+    return mlp_decisions(cfg, n, n_times, decisions, false, ws, ws_bytes, stream, "gftorf_mlp_get_decisions");
+}
+
+int gftorf_mlp_set_decisions(const gftorf_mlp_config* cfg, int64_t n, int32_t n_times,
+                             const uint8_t* decisions, void* ws, size_t ws_bytes, void* stream) {
+    return mlp_decisions(cfg, n, n_times, const_cast<uint8_t*>(decisions), true, ws, ws_bytes, stream,
+                         "gftorf_mlp_set_decisions");
 }
 
 int gftorf_mlp_fwd_noalloc(const gftorf_mlp_config* cfg, const float* params, const float* x0,

@@ -50,8 +50,13 @@ struct Status {
     unsigned long long wcount_off;   // byte offset of the forward's per-work-item counts
     unsigned long long n_items;      // work items (frames x tiles) of the last forward
     unsigned int magic;              // kStatusMagic once a forward has filled the fields
-    unsigned int pad[5];
+    // sticky over every forward since the header was last cleared: OR of the
+    // overflow flags and the largest pair count
+    unsigned int overflow_seen;
+    unsigned long long n_pairs_seen;
+    unsigned int pad[2];
 };
+static_assert(sizeof(Status) == 64, "the status header is the workspace's first 64 bytes");
 constexpr unsigned int kStatusMagic = 0x47465352u;
 // The (evaluations, composited) counts of every work item are summed on the
 // host by gftorf_read_status, which synchronises anyway, so no forward pays a

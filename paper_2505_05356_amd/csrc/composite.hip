@@ -18,9 +18,10 @@
 // quantities.  Per-entry gradients are summed over the wave with DPP and
 // added to the per-(frame, Gaussian) gradient record with one atomic per wave.
 //
-// Records of a batch of list entries are staged in LDS by the whole
-// workgroup (one coalesced 64-byte gather per entry), then every lane reads
-// them as LDS broadcasts.  No MFMA: per (pixel, entry) this is ~20 FP32 VALU
+// Records of 64 list entries at a time are staged in LDS by each wave, in
+// its own slice (the forward's waves walk their tile's list independently;
+// the backward is one wave per tile): one coalesced 64-byte gather per
+// entry, then every lane of the wave reads them as LDS broadcasts.  No MFMA: per (pixel, entry) this is ~20 FP32 VALU
 // operations and one v_exp_f32.
 #include "block_scan.h"
 #include "common.h"

@@ -69,6 +69,9 @@ hipError_t launch_blend(const Blend& b, const float* steps, const gftorf_frame* 
                         hipStream_t s);
 hipError_t launch_blend_bwd(const Blend& b, const float* d_frames, const gftorf_frame* frames,
                             float* d_steps, hipStream_t s);
+// The training forward's ReLU decisions in ws as bytes dec[rows][kDepth][kWidth]:
+// read them out (write = false) or replace them (write = true).
+hipError_t launch_decisions(const Layout& L, char* ws, uint8_t* dec, bool write, hipStream_t s);
 hipError_t launch_bwd(const Layout& L, const Call& c, const float* d_delta, float* d_params,
                       float* d_x0, bool accumulate_x0, hipStream_t s);
 

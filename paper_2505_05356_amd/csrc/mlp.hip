@@ -283,6 +283,41 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     }
 }
 
+// The ReLU decisions of the training forward as plain bytes, dec[row][layer][unit]
+// (1 = active), read from (WRITE = false) or written into (WRITE = true) the
+// bit words: one thread per word, i.e. per (128-row block, layer, forward
+// thread), which holds the thread's 4 column tiles x 8 row tiles x 4 rows.
+// Padding rows read nothing and are written inactive.
+template <bool WRITE>
+__global__ void __launch_bounds__(256) k_mlp_decisions(uint4* __restrict__ mask, uint8_t* __restrict__ dec,
+                                                       int64_t rows, int64_t words) {
+    const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (w >= words) return;
+    const int tid = (int)(w & 255);
+    const int l = (int)((w >> 8) % kDepth);
+    const int64_t blk = (w >> 8) / kDepth;
+    const int lane = tid & 63, wv = tid >> 6, lr = lane & 15, lg = lane >> 4;
+    uint32_t mw[4] = {0u, 0u, 0u, 0u};
+    if (!WRITE) {
+        const uint4 m = mask[w];
+        mw[0] = m.x, mw[1] = m.y, mw[2] = m.z, mw[3] = m.w;
+    }
+    for (int c = 0; c < 4; ++c) {
+        const int col = 64 * wv + 16 * c + lr;
+        for (int r = 0; r < 8; ++r)
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = blk * kRows + 16 * r + 4 * lg + j;
+                if (row >= rows) continue;
+                uint8_t* d = dec + (row * kDepth + l) * kWidth + col;
+                if (WRITE)
+                    mw[c] |= (*d != 0 ? 1u : 0u) << mask_bit(r, j);
+                else
+                    *d = (uint8_t)((mw[c] >> mask_bit(r, j)) & 1u);
+            }
+    }
+    if (WRITE) mask[w] = make_uint4(mw[0], mw[1], mw[2], mw[3]);
+}
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_mlp_bwd(Args a, const float* __restrict__ d_delta,
                                                  float* __restrict__ dxr) {
     __shared__ __attribute__((aligned(16))) bf16 X[kRows * kLDX];
@@ -825,6 +860,18 @@ hipError_t launch_bwd(const Layout& L, const Call& c, const float* d_delta, floa
             hipLaunchKernelGGL(k_mlp_dx0, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, s, dxr, L.n,
                                L.n_times, accumulate_x0 ? 1 : 0, d_x0);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_decisions(const Layout& L, char* ws, uint8_t* dec, bool write, hipStream_t s) {
+    if (!L.training) return hipErrorInvalidValue;
+    uint4* mask = reinterpret_cast<uint4*>(ws + L.mask);
+    const int64_t words = L.rows_pad / kRows * kDepth * 256;
+    const unsigned blocks = (unsigned)((words + 255) / 256);
+    if (write)
+        hipLaunchKernelGGL(k_mlp_decisions<true>, dim3(blocks), dim3(256), 0, s, mask, dec, L.rows, words);
+    else
+        hipLaunchKernelGGL(k_mlp_decisions<false>, dim3(blocks), dim3(256), 0, s, mask, dec, L.rows, words);
     return hipGetLastError();
 }
 

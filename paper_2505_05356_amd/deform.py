@@ -55,6 +55,7 @@ class DeformNet:
             raise ValueError("unsupported network configuration")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.nbytes = nbytes
+        self.generation = 0   # training forwards enqueued on ws (their saved state replaces the last)
 
     def _times(self, times: Sequence[float]):
         if not 1 <= len(times) <= self.n_times:
@@ -73,6 +74,8 @@ class DeformNet:
         if out is None:
             out = torch.empty((T, 3, self.n), device=x0.device)
         _f32dev(out, "out", (T, 3, self.n))
+        if save:
+            self.generation += 1
         _lib.check(lib.gftorf_mlp_fwd(ctypes.byref(self.cfg), _ptr(params), _ptr(x0), self.n,
                                       self._times(times), T, _ptr(out), int(save),
                                       _ptr(self.ws), self.nbytes, _stream(stream)))
@@ -95,20 +98,52 @@ class DeformNet:
         return d_params, d_x0
 
 
+    def decisions(self, n_times: int, stream=None) -> torch.Tensor:
+        """The ReLU decisions the last training forward over n_times times
+        recorded: uint8 [n_times * n, 8, 256], row t * n + k, 1 = active."""
+        lib = _lib.load()
+        if not self.training:
+            raise ValueError("decisions are kept by a training workspace only")
+        dec = torch.empty((n_times * self.n, 8, 256), dtype=torch.uint8, device=self.ws.device)
+        _lib.check(lib.gftorf_mlp_get_decisions(ctypes.byref(self.cfg), self.n, n_times, _ptr(dec),
+                                                _ptr(self.ws), self.nbytes, _stream(stream)))
+        return dec
+
+    def set_decisions(self, dec: torch.Tensor, stream=None) -> None:
+        """Replaces the recorded decisions (same layout as decisions()); the
+        next backward gates its gradients with them."""
+        lib = _lib.load()
+        if not self.training:
+            raise ValueError("decisions are kept by a training workspace only")
+        if not (dec.is_cuda and dec.dtype == torch.uint8 and dec.is_contiguous() and dec.dim() == 3
+                and tuple(dec.shape[1:]) == (8, 256) and dec.shape[0] % self.n == 0):
+            raise ValueError("decisions must be a contiguous uint8 CUDA tensor [T * n, 8, 256]")
+        n_times = dec.shape[0] // self.n
+        _lib.check(lib.gftorf_mlp_set_decisions(ctypes.byref(self.cfg), self.n, n_times, _ptr(dec),
+                                                _ptr(self.ws), self.nbytes, _stream(stream)))
+
+
 class DeformOffsets(torch.autograd.Function):
     """delta [T, 3, n] = network(params, x0, times) as an autograd node: its
     backward is gftorf_mlp_bwd on the same workspace, so it composes with
-    raster.RasterizeCToF (pass the result as the Gaussians' `delta`)."""
+    raster.RasterizeCToF (pass the result as the Gaussians' `delta`).  The
+    backward raises if another training forward used the network's workspace
+    in between (its saved activations would not be this forward's)."""
 
     @staticmethod
     def forward(ctx, net: DeformNet, times, params, x0):
         params, x0 = params.contiguous(), x0.contiguous()
         ctx.net, ctx.times = net, list(times)
         ctx.save_for_backward(params, x0)
-        return net.forward(params, x0, ctx.times, save=True)
+        out = net.forward(params, x0, ctx.times, save=True)
+        ctx.generation = net.generation
+        return out
 
     @staticmethod
     def backward(ctx, d_delta):
+        if ctx.net.generation != ctx.generation:
+            raise RuntimeError("DeformOffsets: the network's workspace was used by another training "
+                               "forward after this one; give every pending backward its own DeformNet")
         params, x0 = ctx.saved_tensors
         d_params, d_x0 = ctx.net.backward(params, x0, ctx.times, d_delta.contiguous(),
                                           want_x0=ctx.needs_input_grad[3])

@@ -156,17 +156,21 @@ def gaussians_struct(params: Dict[str, torch.Tensor]) -> _lib.GaussiansC:
 class Workspace:
     """Device workspace of a (N, F, cfg) problem; keeps the forward's sorted
     lists and records for the backward.  Grows when the pair capacity
-    overflows."""
+    overflows.  `generation` counts the forwards enqueued on it and its
+    reallocations, so a pending backward can tell that its forward's state
+    was overwritten."""
 
     def __init__(self, n: int, n_frames: int, cfg, max_pairs: Optional[int] = None,
                  device="cuda"):
         self.n, self.n_frames, self.cfg, self.device = n, n_frames, cfg, device
+        self.generation = 0
         if max_pairs is None:
             max_pairs = max(1 << 16, 48 * n * n_frames)
         self._alloc(max_pairs)
 
     def _alloc(self, max_pairs):
         lib = _lib.load()
+        self.generation = getattr(self, "generation", 0) + 1
         self.max_pairs = int(min(max_pairs, 0xF0000000))
         self.cstruct = config_struct(self.cfg, self.max_pairs)
         size = lib.gftorf_workspace_size(self.n, self.n_frames, ctypes.byref(self.cstruct))
@@ -189,7 +193,13 @@ class Workspace:
             _lib.check(rc)
         return dict(n_pairs=st.n_pairs, max_pairs=st.max_pairs, overflow=bool(st.overflow),
                     nonfinite=st.nonfinite, n_evaluated=st.n_evaluated,
-                    n_composited=st.n_composited)
+                    n_composited=st.n_composited, overflow_seen=bool(st.overflow_seen),
+                    n_pairs_seen=st.n_pairs_seen)
+
+    def clear_status(self, stream=None):
+        """Clears the status header, including the sticky overflow_seen and
+        n_pairs_seen, with a kernel on the stream (capturable)."""
+        _lib.check(_lib.load().gftorf_clear_status(ctypes.c_void_p(self.ptr), _stream(stream)))
 
 
 def alloc_outputs(n_frames, cfg, device="cuda", channels=("rgb", "quad", "depth")):
@@ -231,6 +241,7 @@ def forward(params, frames_dev, cfg, ws: Workspace, out=None, stream=None, check
     _check_offsets(params, frames_dev.shape[0])
     o = outputs_struct(out)
     while True:
+        ws.generation += 1
         _lib.check(lib.gftorf_render_fwd(ctypes.byref(g), _ptr(frames_dev), F,
                                          ctypes.byref(ws.cstruct), ctypes.byref(o),
                                          ctypes.c_void_p(ws.ptr), ws.nbytes, _stream(stream)))
@@ -274,23 +285,35 @@ class RasterizeCToF(torch.autograd.Function):
     """Differentiable render of RGB, raw quads and depth for a batch of frames.
 
     forward(ctx, ws, frames_dev, cfg, *params) -> (rgb, quad, depth)
+
+    The backward reads the tile lists and records that this forward left in
+    `ws`; it raises if another forward has used `ws` since (or `ws` was
+    regrown), and autograd's version check raises if a parameter or the
+    frame descriptors were modified in place in between.
     """
 
     @staticmethod
     def forward(ctx, ws, frames_dev, cfg, *plist):
         params = {k: (p.contiguous() if p is not None else None) for k, p in zip(ALL_FIELDS, plist)}
         out = forward(params, frames_dev, cfg, ws)
-        ctx.ws, ctx.cfg, ctx.frames = ws, cfg, frames_dev
-        ctx.params = params
-        ctx.saved_out = {k: out[k] for k in ("T_final", "n_contrib")}
+        ctx.ws, ctx.cfg, ctx.generation = ws, cfg, ws.generation
         ctx.present = [p is not None for p in plist]
+        ctx.save_for_backward(frames_dev, out["T_final"], out["n_contrib"],
+                              *[p for p in params.values() if p is not None])
         ctx.mark_non_differentiable(out["T_final"], out["n_contrib"])
         return out["rgb"], out["quad"], out["depth"], out["T_final"], out["n_contrib"]
 
     @staticmethod
     def backward(ctx, g_rgb, g_quad, g_depth, _gT, _gn):
+        if ctx.ws.generation != ctx.generation:
+            raise RuntimeError("RasterizeCToF: the workspace was used by another forward (or regrown) "
+                               "after this one, so its tile lists and records are not this forward's; "
+                               "give every pending backward its own Workspace")
+        frames, T_final, n_contrib, *plist = ctx.saved_tensors
+        it = iter(plist)
+        params = {k: (next(it) if present else None) for k, present in zip(ALL_FIELDS, ctx.present)}
         c = lambda t: None if t is None else t.contiguous()
-        grads = backward(ctx.params, ctx.frames, ctx.cfg, ctx.ws, ctx.saved_out,
+        grads = backward(params, frames, ctx.cfg, ctx.ws, dict(T_final=T_final, n_contrib=n_contrib),
                          c(g_rgb), c(g_quad), c(g_depth))
         res = [grads[k] if present else None for k, present in zip(ALL_FIELDS, ctx.present)]
         return (None, None, None, *res)

@@ -151,6 +151,24 @@ def test_mlp_device_time_entry_points_check_arguments(lib):
                                      dev, need, None) == _lib.EINVAL
 
 
+def test_mlp_decisions_check_arguments(lib):
+    # reading or replacing the recorded ReLU decisions needs a training
+    # workspace of the forward's size and both pointers
+    from paper_2505_05356_amd import _lib
+    cfg = _lib.MlpConfigC(10, 10, 256, 8, 0.2, 4.0)
+    need = lib.gftorf_mlp_workspace_size(ctypes.byref(cfg), 1000, 2, 1)
+    infer = lib.gftorf_mlp_workspace_size(ctypes.byref(cfg), 1000, 2, 0)
+    assert 0 < infer < need
+    dev = ctypes.c_void_p(256)
+    for fn in (lib.gftorf_mlp_get_decisions, lib.gftorf_mlp_set_decisions):
+        assert fn(ctypes.byref(cfg), 1000, 2, None, dev, need, None) == _lib.EINVAL
+        assert fn(ctypes.byref(cfg), 1000, 2, dev, None, need, None) == _lib.EINVAL
+        assert fn(ctypes.byref(cfg), 1000, 2, dev, dev, infer, None) == _lib.ENOWS
+        assert fn(ctypes.byref(cfg), 1000, 65, dev, dev, need, None) == _lib.EINVAL
+        assert fn(ctypes.byref(cfg), 1000, 2, dev, ctypes.c_void_p(512 + 16), need, None) == _lib.EINVAL
+        assert fn(None, 1000, 2, dev, dev, need, None) == _lib.EINVAL
+
+
 def test_mlp_noalloc_checks_arguments(lib):
     # the allocation-free inference forward refuses bad shapes and missing
     # pointers before it resolves its static scratch or launches anything,

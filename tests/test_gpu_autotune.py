@@ -24,3 +24,15 @@ def test_autotune_picks_a_supported_shape_and_caches(tmp_path):
     assert os.path.exists(cache)
     cfg2, times2 = autotune.autotune(params, fdev, wl.cfg, upstream=up, cache_path=cache)
     assert (cfg2.tile_w, cfg2.tile_h) == (cfg.tile_w, cfg.tile_h) and times2 == times
+    # the cache key names the build and the GPU: another library build tunes again
+    key = autotune.signature(wl.gaussians.n, 2, wl.cfg)
+    assert autotune.build_id() in key and "gfx950" in key
+    import json
+    with open(cache) as fh:
+        stored = json.load(fh)
+    assert list(stored) == [key]
+    stale = {key.replace(autotune.build_id(), "v1-0000000000000000-gfx950"): stored[key]}
+    with open(cache, "w") as fh:
+        json.dump(stale, fh)
+    cfg3, times3 = autotune.autotune(params, fdev, wl.cfg, upstream=up, reps=1, warmup=1, cache_path=cache)
+    assert times3 != times and key in json.load(open(cache))

@@ -4,7 +4,11 @@ sampled tiles against the FP64 oracle (needs an MI355X).
 The GPU renders every frame of the batch; the oracle evaluates a seeded
 sample of tiles of the first and last frame.  Gradients are compared for the
 scalar sum(upstream * outputs) with the upstream gradient restricted to the
-sampled, unflagged pixels, which the oracle differentiates exactly."""
+sampled, unflagged pixels, which the oracle differentiates exactly.  A frame
+that renders only some quad channels (an asynchronous raw quad) is compared
+on those, and the oracle is given zero upstream gradient on the others."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -15,11 +19,32 @@ from tests.gpu_common import assert_grads_close, assert_images_close, gpu_lists,
 
 pytestmark = pytest.mark.gpu
 
+
+def _cfg3_sh():
+    wl = scenes.cfg3()
+    return dataclasses.replace(wl, gaussians=scenes.with_sh(wl.gaussians, 3, seed=1))
+
+
+def _cfg3_async():
+    wl = scenes.cfg3()
+    return dataclasses.replace(wl, frames=scenes.async_quartet_frames(2, 0.125, wl.frames[0]))
+
+
 WORKLOADS = {
     "static-100k-640x480": lambda: scenes.cfg2(),
     "dynamic-200k-8f-640x480": lambda: scenes.cfg3(),
+    "dynamic-200k-8f-640x480-sh3": _cfg3_sh,
+    "dynamic-200k-8f-640x480-async-quartets": _cfg3_async,
     "dynamic-1M-16f-1024x768-2freq": lambda: scenes.cfg4(),
+    "dynamic-1M-16f-1024x768-2freq-8x8": lambda: scenes.cfg4(tile=(8, 8)),
+    "dynamic-1M-16f-1024x768-2freq-32x8": lambda: scenes.cfg4(tile=(32, 8)),
 }
+
+
+def _channels(frame, cfg):
+    """Quad channels the frame renders (all when its quad_mask is 0)."""
+    m = getattr(frame, "quad_mask", 0)
+    return np.array([m == 0 or bool(m >> c & 1) for c in range(cfg.n_quad)])
 
 
 def _sample(wl, k=3, seed=0):
@@ -54,8 +79,11 @@ def test_fullsize_sampled_tiles(name):
 
     for i, f in enumerate(sel_frames):
         m = ok[i][None]
-        for k in ("rgb", "quad", "depth", "T_final"):
+        for k in ("rgb", "depth", "T_final"):
             assert_images_close(res[k][f:f + 1], np.nan_to_num(ref[k][i:i + 1]), m, f"{name}/f{f}/{k}")
+        ch = _channels(wl.frames[f], wl.cfg)
+        assert_images_close(res["quad"][f:f + 1, ch], np.nan_to_num(ref["quad"][i:i + 1, ch]), m,
+                            f"{name}/f{f}/quad")
         np.testing.assert_array_equal(res["n_contrib"][f][ok[i]], ref["n_contrib"][i][ok[i]])
 
     # tile lists of the sampled tiles, bit-exact
@@ -70,7 +98,9 @@ def test_fullsize_sampled_tiles(name):
             got = lists["pair_item_dev"][int(a):int(b)].cpu().numpy().view(np.uint32)
             np.testing.assert_array_equal(got, (f * wl.gaussians.n + lst).astype(np.uint32))
 
-    up_sel = {k: v[sel_frames] for k, v in up.items()}
+    up_sel = {k: v[sel_frames].copy() for k, v in up.items()}
+    for i, f in enumerate(sel_frames):
+        up_sel["quad"][i, ~_channels(wl.frames[f], wl.cfg)] = 0.0
     gref = oref.render(wl.gaussians, frames, wl.cfg, tiles=tiles, upstream=up_sel)
     dynamic = np.any(wl.gaussians.vel)
     for k, r in gref["grads"].items():

@@ -307,3 +307,165 @@ def test_backward_twice_after_one_forward():
             continue
         # equal up to the float32 atomic summation order of the composite backward
         assert_grads_close(v.cpu().numpy(), res["grads"][k], f"twice/{k}", rtol=1e-4)
+
+
+def test_depth_key_ties_bit_exact():
+    # Many Gaussians share one camera-space depth, so their float32 depth keys
+    # tie and the order inside a tile list falls to the Gaussian index (the
+    # ascending-index tie-break): lists bit-exact against the oracle, ties
+    # present in them, and the forward composited in that order.
+    g = scenes.draw_gaussians(1500, 64, 48, 60.0, 60.0, seed=21)
+    z_new = np.array([1.5, 2.0, 2.5], np.float32)[np.random.default_rng(22).integers(0, 3, g.n)]
+    s = z_new.astype(np.float64) / g.mean[2].astype(np.float64)
+    g.mean[0] = (g.mean[0] * s).astype(np.float32)
+    g.mean[1] = (g.mean[1] * s).astype(np.float32)
+    g.mean[2] = z_new
+    frames = scenes.identity_frames([0.0], 64, 48, 60.0, 60.0, 4, bg_seed=1)
+    cfg = scenes.RenderConfig(width=64, height=48)
+    res = run_gpu(g, frames, cfg)
+    lists = gpu_lists(res, g, frames, cfg)
+    ref = binning.sorted_pairs(g, frames, cfg)
+    n_tiles = cfg.tiles_x * cfg.tiles_y
+    np.testing.assert_array_equal(lists["pair_key"], (ref["frame"] * n_tiles + ref["tile"]).astype(np.uint32))
+    np.testing.assert_array_equal(lists["pair_item"], (ref["frame"] * g.n + ref["index"]).astype(np.uint32))
+    # ties really occur inside tile lists, and the items of every tie ascend
+    key = ref["key"]
+    same = (np.diff(ref["tile"]) == 0) & (np.diff(key.astype(np.int64)) == 0)
+    assert same.sum() > 1000
+    assert np.all(np.diff(ref["index"].astype(np.int64))[same] > 0)
+    ref_img = oref.render(g, frames, cfg)
+    ok = ~ref_img["flagged"]
+    for k in ("rgb", "quad", "depth", "T_final"):
+        assert_images_close(res[k], ref_img[k], ok, f"ties/{k}")
+    np.testing.assert_array_equal(res["n_contrib"][ok], ref_img["n_contrib"][ok])
+
+
+@pytest.mark.parametrize("n_freq,phases", [
+    (3, scenes.QUAD_PHASES), (4, scenes.QUAD_PHASES),
+    (1, (0.3,)), (2, (0.0, 2 * np.pi / 3, 4 * np.pi / 3)), (4, (0.1, 2.0, 4.0))])
+def test_frequencies_and_phase_offsets(n_freq, phases):
+    # every frequency count up to the maximum of 4 and phase-offset counts
+    # other than the four-tap camera: forward, backward and the background
+    # gradients against the oracle (16 quad channels at 4 x 4)
+    freqs = (20e6, 30e6, 45e6, 60e6)[:n_freq]
+    g = scenes.draw_gaussians(1500, 72, 56, 65.0, 65.0, seed=23, dynamic=True)
+    nq = n_freq * len(phases)
+    frames = scenes.identity_frames([0.0, 0.12], 72, 56, 65.0, 65.0, nq, bg_seed=24, n_freq=n_freq)
+    cfg = scenes.RenderConfig(width=72, height=56, freqs=freqs, phases=tuple(phases))
+    ref = oref.render(g, frames, cfg)
+    ok = ~ref["flagged"]
+    res = run_gpu(g, frames, cfg)
+    for k in ("rgb", "quad", "depth", "T_final"):
+        assert_images_close(res[k], ref[k], ok, f"{n_freq}x{len(phases)}/{k}")
+    up = mask_upstream(scenes.upstream_grads(len(frames), cfg, seed=25), ok)
+    ref_b = oref.render(g, frames, cfg, upstream=up)
+    res_b = run_gpu(g, frames, cfg, upstream=up, want_bg=True)
+    for k, r in ref_b["grads"].items():
+        assert_grads_close(res_b["grads"][k], r, f"{n_freq}x{len(phases)}/{k}")
+    bg_ref = np.concatenate([ref_b["grad_bg_rgb"], ref_b["grad_bg_quad"]], 1)
+    assert_grads_close(res_b["grad_bg"], bg_ref, f"{n_freq}x{len(phases)}/bg")
+
+
+def _fd_scene():
+    # strict mode (no skip or stop thresholds, every Gaussian in every tile),
+    # opacities <= 0.82 (below alpha_max), depths 0.08 m apart and slow in z,
+    # so that no discrete decision changes under the perturbations
+    wl = scenes.tiny_scene(24, 32, 24, seed=26, dynamic=True)
+    g = wl.gaussians
+    z = 1.0 + 0.08 * np.random.default_rng(27).permutation(g.n)
+    s = z / g.mean[2].astype(np.float64)
+    g.mean[0] = (g.mean[0] * s).astype(np.float32)
+    g.mean[1] = (g.mean[1] * s).astype(np.float32)
+    g.mean[2] = z.astype(np.float32)
+    g.vel[2] *= 0.1
+    g.acc[2] *= 0.1
+    g.opacity_logit[:] = np.clip(g.opacity_logit, -2.0, 1.5)
+    frames = scenes.identity_frames([0.0, 0.1], 32, 24, 38.4, 38.4, 4, bg_seed=28)
+    cfg = dataclasses.replace(wl.cfg, tile_w=16, tile_h=16).strict()
+    return g, frames, cfg
+
+
+def test_backward_directional_finite_differences():
+    # The HIP backward against central differences of the HIP forward
+    # (supplement C, Eqs. S1-S3 plus the background term): for random
+    # directions d per parameter field, L(theta + d) - L(theta - d) of
+    # L = sum(upstream * outputs) equals <grad, 2 d> to first order with a
+    # third-order remainder.  The steps move each field by about 1e-3 of its
+    # scale or of its effect on the centre; the float32 rounding of the two
+    # renders' outputs, independent between them, moves L by far less than
+    # 1e-6 sqrt(sum (upstream * out)^2) (16 units in the last place per
+    # element).
+    from paper_2505_05356_amd import raster
+    g, frames, cfg = _fd_scene()
+    up = scenes.upstream_grads(len(frames), cfg, seed=29)
+    res = run_gpu(g, frames, cfg, upstream=up)
+    step = dict(mean=1e-3, vel=1e-2, acc=1e-1, scale=1e-4, quat=1e-3, omega=1e-2,
+                opacity_logit=1e-2, rgb=1e-3, albedo=1e-2)
+
+    def loss(gg):
+        params = raster.to_device_params(gg, "cuda")
+        fdev = raster.pack_frames(frames, cfg, "cuda")
+        ws = raster.Workspace(gg.n, len(frames), cfg, device="cuda")
+        out = raster.forward(params, fdev, cfg, ws)
+        o = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+        terms = [up[k].astype(np.float64) * o[k] for k in ("rgb", "quad", "depth")]
+        return sum(t.sum() for t in terms), sum((t * t).sum() for t in terms)
+
+    rng = np.random.default_rng(30)
+    checked = 0
+    for field, h in step.items():
+        for _ in range(2):
+            base = getattr(g, field).astype(np.float64)
+            d = rng.normal(size=base.shape) * h
+            gp, gm = g.copy(), g.copy()
+            setattr(gp, field, (base + d).astype(np.float32))
+            setattr(gm, field, (base - d).astype(np.float32))
+            dtheta = getattr(gp, field).astype(np.float64) - getattr(gm, field).astype(np.float64)
+            lp, sp = loss(gp)
+            lm, sm = loss(gm)
+            pred = float((res["grads"][field].astype(np.float64) * dtheta).sum())
+            noise = 1e-6 * np.sqrt(sp + sm)
+            assert abs(pred) > 20 * noise, f"{field}: step too small for float32 ({pred:.3g} vs {noise:.3g})"
+            assert abs((lp - lm) - pred) <= 1e-2 * abs(pred) + noise, \
+                f"{field}: finite difference {lp - lm:.6g} vs gradient {pred:.6g}"
+            checked += 1
+    assert checked == 18
+
+
+def test_status_keeps_overflow_across_forwards():
+    # the sticky status fields: an overflowing forward, then one that fits
+    # the same workspace; the second clears `overflow` but `overflow_seen` and
+    # `n_pairs_seen` remember the first until the header is cleared
+    from paper_2505_05356_amd import raster
+    wl = CASES["cfg1"]
+    params = raster.to_device_params(wl.gaussians, "cuda")
+    fdev = raster.pack_frames(wl.frames, wl.cfg, "cuda")
+    ws = raster.Workspace(wl.gaussians.n, len(wl.frames), wl.cfg, max_pairs=100, device="cuda")
+    raster.forward(params, fdev, wl.cfg, ws, check=False)
+    first = ws.status()
+    assert first["overflow"] and first["overflow_seen"] and first["n_pairs_seen"] == first["n_pairs"] > 100
+    behind = wl.gaussians.copy()
+    behind.mean[2] = -1.0                                   # every Gaussian behind the camera
+    raster.forward(raster.to_device_params(behind, "cuda"), fdev, wl.cfg, ws, check=False)
+    second = ws.status()
+    assert not second["overflow"] and second["n_pairs"] <= 100
+    assert second["overflow_seen"] and second["n_pairs_seen"] == first["n_pairs"]
+    ws.clear_status()
+    cleared = ws.status()
+    assert not cleared["overflow_seen"] and cleared["n_pairs_seen"] == 0
+
+
+def test_autograd_backward_refuses_a_reused_workspace():
+    # a second forward on the same workspace replaces the tile lists the first
+    # forward's backward needs: that backward raises instead of using them
+    from paper_2505_05356_amd import raster
+    wl = CASES["cfg1"]
+    params = {k: (v.requires_grad_(True) if v is not None else None)
+              for k, v in raster.to_device_params(wl.gaussians, "cuda").items()}
+    ws = raster.Workspace(wl.gaussians.n, len(wl.frames), wl.cfg, device="cuda")
+    a = raster.render(params, wl.frames, wl.cfg, ws=ws)
+    b = raster.render(params, wl.frames, wl.cfg, ws=ws)
+    with pytest.raises(RuntimeError, match="another forward"):
+        a["rgb"].sum().backward(retain_graph=True)
+    b["rgb"].sum().backward()
+    assert params["mean"].grad is not None and torch.isfinite(params["mean"].grad).all()

@@ -237,3 +237,63 @@ def test_eq7_blend_of_offsets():
     lhs = (out * y).sum()
     rhs = (steps * mlp.blend_offsets_backward(y, frames, anchors, 3)).sum()
     assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def _float32_decisions(theta, x_in, t_in, order, seed):
+    # a float32 evaluation with bfloat16 operands, as a matrix-core kernel
+    # might run it: the encoding within one float32 ulp (as a sinpi of float32
+    # accuracy gives it), then per layer the products accumulated in float32
+    # in the given order, ReLU and rounding to bfloat16
+    import torch
+    lx = lt = 10
+    W, b = mlp.unpack(theta, mlp.layer_shapes())
+    x32 = np.asarray(x_in, np.float64).astype(np.float32).astype(np.float64)
+    t32 = np.asarray(t_in, np.float64).astype(np.float32).astype(np.float64)
+    v = mlp.network_input(x32, t32, lx, lt).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    step = np.where(rng.random(v.shape) < 0.5, np.float32(np.inf), np.float32(-np.inf))
+    v[:, 3:63] = np.nextafter(v[:, 3:63], step[:, 3:63])          # sin / cos blocks of x
+    v[:, 64:] = np.nextafter(v[:, 64:], step[:, 64:])              # sin / cos blocks of t
+    h = torch.from_numpy(mlp.round_bf16(v).astype(np.float32))
+    masks = []
+    for l in range(8):
+        w = torch.from_numpy(mlp.round_bf16(W[l]).astype(np.float32))
+        bias = torch.from_numpy(b[l].astype(np.float32))
+        K = w.shape[1]
+        if order == "matmul, bias last":
+            z = h @ w.T + bias
+        else:
+            chunks = [(k, min(k + 32, K)) for k in range(0, K, 32)]
+            if order == "k-steps of 32 descending":
+                chunks = chunks[::-1]
+            z = bias.expand(h.shape[0], -1).clone()
+            if order == "sequential":
+                for k in range(K):
+                    z = z + h[:, k:k + 1] * w[:, k]
+            else:
+                for k0, k1 in chunks:
+                    z = z + h[:, k0:k1] @ w[:, k0:k1].T
+        masks.append((z > 0).numpy())
+        h = torch.from_numpy(mlp.round_bf16(np.maximum(z.numpy(), 0.0)).astype(np.float32))
+    return np.stack(masks, axis=1)
+
+
+@pytest.mark.parametrize("order", ["k-steps of 32", "k-steps of 32 descending", "matmul, bias last",
+                                   "sequential"])
+def test_float32_decisions_differ_only_within_the_margin(order):
+    # the ReLU decisions of a float32 / bfloat16 evaluation in any of several
+    # accumulation orders equal the shadow's except at units whose |z| is
+    # within DECISION_MARGIN of their scale; the drift behind such a flip
+    # stays well inside the margin, and flips are rare
+    theta = scenes.mlp_params(seed=1, last_std=0.05, bias_std=0.1)
+    x0, times = scenes.mlp_rows(200, 3, seed=101)
+    sx, st = float(np.float32(2 * 30e6 / 299_792_458.0)), 4.0
+    x_in, t_in, _, _ = mlp._rows(x0, times, sx, st)
+    masks, ratio = mlp.decision_table(theta, x_in, t_in)
+    got = _float32_decisions(theta, x_in, t_in, order, seed=len(order))
+    differ = got != masks
+    assert differ.mean() < 1e-4
+    assert np.all(ratio[differ] <= 2.5e-3), ratio[differ].max()
+    assert 2.5e-3 * 4 <= mlp.DECISION_MARGIN
+    # the margin is not vacuous: most units sit far outside it
+    assert (ratio <= mlp.DECISION_MARGIN).mean() < 0.1
