@@ -497,11 +497,13 @@ def main():
         raster.forward(params, fdev, cfg, ws, out=out, check=False)
         raster.backward(params, fdev, cfg, ws, out, d["rgb"], d["quad"], d["depth"], grads=grads)
 
-    # per-frame path: the same entry points with n_frames = 1
+    # per-frame path: the same entry points with n_frames = 1 (set up only
+    # when it is timed, so that a profile of the batched path holds only its calls)
     ws1 = raster.Workspace(g.n, 1, cfg, device=dev)
     out1 = raster.alloc_outputs(1, cfg, dev)
-    for f in range(F):
-        raster.forward(params, fdev1[f], cfg, ws1, out=out1, check=True)
+    if not args.no_per_frame:
+        for f in range(F):
+            raster.forward(params, fdev1[f], cfg, ws1, out=out1, check=True)
     flat1 = torch.zeros_like(flat)
     flat_acc = torch.zeros_like(flat)
     grads1, o = {}, 0
@@ -697,6 +699,12 @@ def roofline(name, avg_ms, P, E_fwd, E_bwd, C):
     if name == "k_composite_bwd":
         return alu(E_bwd * FLOP_PER_EVAL + C * BWD_FLOP_PER_COMP,
                    f"{E_bwd} evals x {FLOP_PER_EVAL} + {C} composited x {BWD_FLOP_PER_COMP}")
+    if name == "k_tile_place":
+        b = P * 4   # every (tile, Gaussian) entry written once, 4 B; its group-list reads are extra
+        a = b / t / 1e9
+        return dict(bound="hbm", achieved=round(a, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(a / HBM_PEAK_GBS, 4), traffic=None, kernel=name,
+                    avg_ms=round(avg_ms, 4), work=f"{b:.4g} B per launch = {P} pairs x 4 B written")
     if name == "k_sort_downsweep<pairs>":
         b = P * SORT_BYTES_PER_KEY_PASS
         a = b / t / 1e9

@@ -152,7 +152,8 @@ __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
     uint64_t* y_lo = x_hi + G.ngx;     // [ngy] same for rows
     uint64_t* y_hi = y_lo + G.ngy;
     uint32_t* cursor = reinterpret_cast<uint32_t*>(y_hi + G.ngy);   // [ng]
-    const int chunk = blockIdx.x;
+    // consecutive chunks write adjacent runs of every group list: one XCD
+    const int chunk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int f = chunk / QC, q = chunk - f * QC;
     const int lane = threadIdx.x;
     const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
@@ -355,7 +356,12 @@ __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32
     const uint32_t nseg = seg_start[K];
     const int lane = threadIdx.x;
     const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
-    for (uint32_t b = blockIdx.x; b < nseg; b += gridDim.x) {
+    // consecutive segments end and start runs in the same cache lines: each
+    // XCD takes one contiguous eighth of the segments, so those partial lines
+    // meet in one L2 (the grid is a multiple of 8 workgroups)
+    const uint32_t per_xcd = gridDim.x / kXcds, xcd = blockIdx.x % kXcds;
+    const uint32_t seg_hi = (uint32_t)((uint64_t)nseg * (xcd + 1) / kXcds);
+    for (uint32_t b = (uint32_t)((uint64_t)nseg * xcd / kXcds) + blockIdx.x / kXcds; b < seg_hi; b += per_xcd) {
         const Segment sg = find_segment((int)b, seg_start, K, S, granges);
         const LaneTile lt = lane_tile(P, G, sg.fg, lane);
         uint32_t cur = 0;   // next list position of this lane's tile
@@ -555,8 +561,9 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
         hipLaunchKernelGGL(k_group_place, dim3(chunks), dim3(64), lds, s, P, g.C, g.QC, w.dval[dbuf],
                            w.dkey[dbuf], w.drect[dbuf], w.cntA, w.granges, w.gval, w.gloc);
     }
-    // persistent level-B grid: every wave loops over segments
-    const unsigned segs = (unsigned)(g.max_segments < 16384 ? g.max_segments : 16384);
+    // persistent level-B grid: every wave loops over segments (a multiple of
+    // 8 workgroups, as k_tile_place's split of the segments over the XCDs needs)
+    const unsigned segs = (unsigned)((g.max_segments < 16384 ? g.max_segments : 16384) + 7) / 8 * 8;
     {
         ProfScope _p("k_tile_count", s);
         hipLaunchKernelGGL(k_tile_count, dim3(segs), dim3(64), 0, s, P, g.S, w.seg_start, w.granges,

@@ -150,8 +150,9 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nt
 // Block -> work-item remap so that each of the 8 XCDs (which receive blocks
 // round-robin) processes one contiguous range of work items, keeping the
 // records of neighbouring tiles and of one frame in that XCD's L2.
+constexpr int kXcds = 8;   // accelerator complex dies, each with its own L2
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
-    constexpr int kX = 8;
+    constexpr int kX = kXcds;
     const int q = nb / kX, r = nb % kX;
     const int x = b % kX, i = b / kX;
     return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;

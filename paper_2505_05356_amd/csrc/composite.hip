@@ -33,15 +33,27 @@ namespace {
 // Base-2 exponent q of the 2-D Gaussian at (px, py): the conic is stored
 // prescaled by -log2(e) / 2 (-log2(e) for the cross term), so o G = o 2^q.
 // One definition shared by the forward and the backward kernels, with
-// contraction pinned, so both take identical skip / stop / clamp decisions.
-__device__ __forceinline__ float splat_q(const float4 c, const float4 r1, float px, float py, float& dx,
-                                         float& dy) {
+// contraction pinned, so both take identical skip / stop / clamp decisions:
+// q = dy (C dy + B dx) + A dx^2, where the column terms B dx and A dx^2 are
+// formed once per pixel column (splat_col) and reused by every pixel of it.
+struct SplatCol {
+    float dx, bdx, adx2;
+};
+
+__device__ __forceinline__ SplatCol splat_col(const float4 c, const float4 r1, float px) {
 #pragma clang fp contract(off)
-    dx = px - c.x;
+    SplatCol k;
+    k.dx = px - c.x;
+    k.bdx = r1.y * k.dx;
+    k.adx2 = (r1.x * k.dx) * k.dx;
+    return k;
+}
+
+__device__ __forceinline__ float splat_row(const SplatCol& k, const float4 c, const float4 r1, float py,
+                                           float& dy) {
+#pragma clang fp contract(off)
     dy = py - c.y;
-    // dy (C dy + B dx) + A dx^2: the backward's pixels of one lane share a
-    // column, so B dx and A dx^2 are computed once per lane and entry
-    return __builtin_fmaf(dy, __builtin_fmaf(r1.z, dy, r1.y * dx), (r1.x * dx) * dx);
+    return __builtin_fmaf(dy, __builtin_fmaf(r1.z, dy, k.bdx), k.adx2);
 }
 
 // Below this exponent (log2 units) alpha < alpha_min with room to spare for
@@ -199,8 +211,8 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
             if (done) continue;
             ++n_eval;
             const float4 c = srec[0][k], r1 = srec[1][k];
-            float dx, dy;
-            const float qe = splat_q(c, r1, fpx, fpy, dx, dy);
+            float dy;
+            const float qe = splat_row(splat_col(c, r1, fpx), c, r1, fpy, dy);
             const float a = fminf(r1.w * __builtin_amdgcn_exp2f(qe), amax);
             if (a < amin) continue;
             const float nT = T * (1.0f - a);
@@ -428,9 +440,11 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
             float dx[PPT], dy[PPT], qe[PPT];
             bool pass[PPT];
             bool anyp = false;
+            const SplatCol col = splat_col(c, r1, fpx[0]);   // the lane's pixels share a column
 #pragma unroll
             for (int i = 0; i < PPT; ++i) {
-                qe[i] = splat_q(c, r1, fpx[i], fpy[i], dx[i], dy[i]);
+                dx[i] = col.dx;
+                qe[i] = splat_row(col, c, r1, fpy[i], dy[i]);
                 pass[i] = kidx < last[i] && !(qe[i] < c.z);
                 anyp |= pass[i];
             }

@@ -109,7 +109,9 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
     const int lane = tid % 64;
     long long cur_f = -1;
 
-    for (long long g = blockIdx.x; g < ntiles; g += gridDim.x) {
+    // consecutive tiles write adjacent runs of every digit: one XCD
+    const long long g0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    for (long long g = g0; g < ntiles; g += gridDim.x) {
         const SortTile st = sort_tile(g, n, tpf);
         if (st.f != cur_f) {   // start of each digit inside this frame's segment
             __syncthreads();
