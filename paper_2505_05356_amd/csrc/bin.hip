@@ -100,30 +100,38 @@ __global__ void __launch_bounds__(256) k_group_colscan(Params P, int QC, uint32_
 // Single workgroup: group-list ranges (exclusive scan of the lengths) and the
 // first level-B segment of every group.  The level-A lists are bounded by the
 // pair capacity (every group entry yields at least one pair).
-__global__ void __launch_bounds__(1024) k_group_scan(const uint32_t* __restrict__ lenA, int K, int S,
+__global__ void __launch_bounds__(1024) k_group_scan(const uint32_t* __restrict__ lenA, int K, int S, int R,
                                                      unsigned long long cap, uint2* __restrict__ granges,
-                                                     uint32_t* __restrict__ seg_start) {
+                                                     uint32_t* __restrict__ seg_start,
+                                                     uint32_t* __restrict__ chunk_start) {
     __shared__ unsigned long long scratch[17];
     __shared__ uint32_t scratch32[17];
     unsigned long long carry = 0;
-    uint32_t scarry = 0;
+    uint32_t scarry = 0, ccarry = 0;
     for (int base = 0; base < K; base += 1024) {
         const int i = base + threadIdx.x;
         const unsigned long long v = i < K ? lenA[i] : 0ull;
         const uint32_t nsg = (uint32_t)((v + S - 1) / S);
+        const uint32_t nch = (nsg + R - 1) / R;
         unsigned long long tot;
-        uint32_t stot;
+        uint32_t stot, ctot;
         const unsigned long long ex = block_exclusive_scan<unsigned long long, 1024>(v, scratch, &tot);
         const uint32_t sex = block_exclusive_scan<uint32_t, 1024>(nsg, scratch32, &stot);
+        const uint32_t cex = block_exclusive_scan<uint32_t, 1024>(nch, scratch32, &ctot);
         if (i < K) {
             const unsigned long long a = carry + ex, b = a + v;
             granges[i] = make_uint2((uint32_t)(a < cap ? a : cap), (uint32_t)(b < cap ? b : cap));
             seg_start[i] = scarry + sex;
+            chunk_start[i] = ccarry + cex;
         }
         carry += tot;
         scarry += stot;
+        ccarry += ctot;
     }
-    if (threadIdx.x == 0) seg_start[K] = scarry;
+    if (threadIdx.x == 0) {
+        seg_start[K] = scarry;
+        chunk_start[K] = ccarry;
+    }
 }
 
 // Rank of this lane among the lanes of `peers` below it.
@@ -319,32 +327,17 @@ __global__ void __launch_bounds__(64) k_tile_count(Params P, int S, const uint32
     }
 }
 
-// Tiles t0 .. t0 + 31 of the group for one batch of 64 entries: `bits` holds
-// this lane's coverage of those tiles, lane t of `cur` the cursor of tile t.
-__device__ __forceinline__ void place_half(uint64_t tiles, int t0, uint32_t bits, uint32_t item, uint32_t& cur,
-                                           uint32_t cap, uint32_t* __restrict__ tval) {
-    uint32_t todo = (uint32_t)(tiles >> t0);
-    while (todo) {
-        const int i = __builtin_ctz(todo);
-        todo &= todo - 1;
-        const uint64_t peers = __ballot((bits >> i) & 1u);
-        if (peers == 0ull) continue;
-        const int t = t0 + i;
-        const uint32_t base = __builtin_amdgcn_readlane(cur, t);
-        if ((peers >> __lane_id()) & 1ull) {
-            const uint32_t pos = base + rank_below(peers);
-            if (pos < cap) tval[pos] = item;
-        }
-        if ((int)__lane_id() == t) cur = base + (uint32_t)__popcll(peers);
-    }
-}
-
-// Placing pass, 64 entries at a time (lane = entry).  For every tile of the
-// group that some entry covers, a ballot gives the covering lanes; each
-// writes at the tile's cursor plus its rank among them, so one store
-// instruction fills a contiguous run of that tile's list.  Lane t holds the
-// cursor of tile t.
-__global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32_t* __restrict__ seg_start,
+// Placing pass.  Work item = (chunk of R segments of one group list, tile row
+// r of the group); one wave walks the chunk's entries 64 at a time (lane =
+// entry) and places the entries covering each of the row's 8 tiles: a ballot
+// gives the covering lanes, and each writes at the tile's cursor plus its
+// rank among them, so one store instruction appends a contiguous run to that
+// tile's list.  The 8 cursors are wave-uniform (scalar registers, the tile
+// loop unrolled), and one wave appends each tile's run over R * S entries, so
+// the runs span whole cache lines except at their two ends.
+__global__ void __launch_bounds__(64) k_tile_place(Params P, int S, int R,
+                                                   const uint32_t* __restrict__ seg_start,
+                                                   const uint32_t* __restrict__ chunk_start,
                                                    const uint2* __restrict__ granges,
                                                    const uint32_t* __restrict__ gval,
                                                    const uint16_t* __restrict__ gloc,
@@ -353,39 +346,73 @@ __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, const uint32
                                                    uint32_t* __restrict__ tval) {
     const Groups G = groups_of(P);
     const int K = P.F * G.ng;
-    const uint32_t nseg = seg_start[K];
+    const uint32_t nitems = chunk_start[K] * (uint32_t)kGroupH;
     const int lane = threadIdx.x;
     const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
-    // consecutive segments end and start runs in the same cache lines: each
-    // XCD takes one contiguous eighth of the segments, so those partial lines
-    // meet in one L2 (the grid is a multiple of 8 workgroups)
+    // consecutive chunks of a group end and start runs in the same cache
+    // lines: each XCD takes one contiguous eighth of the work items, so those
+    // partial lines meet in one L2 (the grid is a multiple of 8 workgroups)
     const uint32_t per_xcd = gridDim.x / kXcds, xcd = blockIdx.x % kXcds;
-    const uint32_t seg_hi = (uint32_t)((uint64_t)nseg * (xcd + 1) / kXcds);
-    for (uint32_t b = (uint32_t)((uint64_t)nseg * xcd / kXcds) + blockIdx.x / kXcds; b < seg_hi; b += per_xcd) {
-        const Segment sg = find_segment((int)b, seg_start, K, S, granges);
-        const LaneTile lt = lane_tile(P, G, sg.fg, lane);
-        uint32_t cur = 0;   // next list position of this lane's tile
-        if (lt.mine) cur = ranges[(size_t)lt.f * P.n_tiles + lt.tile].x + cntB[(size_t)b * 64 + lane];
-        // tiles of this group inside the frame (wave-uniform)
-        const uint64_t tiles = __ballot(lt.mine);
+    const uint32_t hi = (uint32_t)((uint64_t)nitems * (xcd + 1) / kXcds);
+    for (uint32_t wi = (uint32_t)((uint64_t)nitems * xcd / kXcds) + blockIdx.x / kXcds; wi < hi; wi += per_xcd) {
+        const uint32_t ch = wi / kGroupH;
+        const uint32_t r = wi - ch * kGroupH;   // tile row of the group
+        int lo = 0, up = K;                      // chunk_start[lo] <= ch < chunk_start[up]
+        while (up - lo > 1) {
+            const int mid = (lo + up) >> 1;
+            if (chunk_start[mid] <= ch) lo = mid; else up = mid;
+        }
+        const int fg = lo;
+        const int f = fg / G.ng, gi = fg - f * G.ng;
+        const uint32_t gy = gi / G.ngx, gx = gi - gy * G.ngx;
+        const uint32_t ty = gy * kGroupH + r;
+        if (ty >= (uint32_t)P.nty) continue;   // the row lies below the frame
+        const uint32_t b0 = seg_start[fg] + (ch - chunk_start[fg]) * (uint32_t)R;   // first segment
+        const uint2 gr = granges[fg];
+        const uint32_t beg = gr.x + (b0 - seg_start[fg]) * (uint32_t)S;
+        const uint32_t end = min(beg + (uint32_t)(R * S), gr.y);
+        // cursors of the row's tiles (lane c < 8 loads tile c's), then wave-uniform
+        uint32_t cl = 0;
+        const uint32_t txl = gx * kGroupW + (uint32_t)lane;
+        if (lane < kGroupW && txl < (uint32_t)P.ntx)
+            cl = ranges[(size_t)f * P.n_tiles + ty * P.ntx + txl].x + cntB[(size_t)b0 * 64 + r * kGroupW + lane];
+        uint32_t cur[kGroupW];
+#pragma unroll
+        for (int c = 0; c < kGroupW; ++c) cur[c] = (uint32_t)__builtin_amdgcn_readlane((int)cl, c);
+        const uint32_t ncol = min((uint32_t)kGroupW, (uint32_t)P.ntx - gx * kGroupW);   // tiles inside the frame
         // the next batch's entries are loaded while this batch is placed
         uint32_t nitem = 0, nloc = 0;
-        bool nvalid = sg.beg + lane < sg.end;
+        bool nvalid = beg + lane < end;
         if (nvalid) {
-            nitem = gval[sg.beg + lane];
-            nloc = gloc[sg.beg + lane];
+            nitem = gval[beg + lane];
+            nloc = gloc[beg + lane];
         }
-        for (uint32_t j0 = sg.beg; j0 < sg.end; j0 += 64) {
+        for (uint32_t j0 = beg; j0 < end; j0 += 64) {
             const uint32_t item = nitem;
-            const uint64_t mask = nvalid ? cover_mask(local_rect(nloc)) : 0ull;
+            uint32_t row = 0;   // bit c: the entry covers tile (c, r) of the group
+            if (nvalid) {
+                const LocalRect lr = local_rect(nloc);
+                if (lr.y0 <= r && r <= lr.y1) row = ((2u << lr.x1) - (1u << lr.x0)) & 0xffu;
+            }
             const uint32_t jn = j0 + 64 + lane;
-            nvalid = jn < sg.end;
+            nvalid = jn < end;
             if (nvalid) {
                 nitem = gval[jn];
                 nloc = gloc[jn];
             }
-            place_half(tiles, 0, (uint32_t)mask, item, cur, cap, tval);
-            place_half(tiles, 32, (uint32_t)(mask >> 32), item, cur, cap, tval);
+#pragma unroll
+            for (int c = 0; c < kGroupW; ++c) {
+                if ((uint32_t)c >= ncol) break;
+                const bool mine = (row >> c) & 1u;
+                const uint64_t peers = __ballot(mine);
+                if (peers == 0ull) continue;
+                const uint32_t cnt = (uint32_t)__popcll(peers);
+                if (mine) {
+                    const uint32_t pos = cur[c] + rank_below(peers);
+                    if (cur[c] + cnt <= cap || pos < cap) tval[pos] = item;
+                }
+                cur[c] += cnt;
+            }
         }
     }
 }
@@ -525,6 +552,9 @@ BinGeom bin_geometry(int64_t n, int32_t n_frames, int ntx, int nty, uint64_t cap
     // level-B segment: 128 entries (two batches of 64) -- short segments give
     // enough waves to hide the load latency of the placing pass
     g.S = 128;
+    // placement chunk: 8 segments, so a wave appends 1024 entries' worth of
+    // each tile's run
+    g.R = 8;
     // every segment but the last of each group list holds S entries, and the
     // group lists hold at most min(cap, M * groups) entries
     uint64_t entries = cap;
@@ -551,8 +581,8 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     {
         ProfScope _p("k_group_scan", s);
-        hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, s, w.lenA, K, g.S,
-                           (unsigned long long)P.cap, w.granges, w.seg_start);
+        hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(1024), 0, s, w.lenA, K, g.S, g.R,
+                           (unsigned long long)P.cap, w.granges, w.seg_start, w.chunk_start);
     }
     if (chunks) {
         ProfScope _p("k_group_place", s);
@@ -561,9 +591,12 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
         hipLaunchKernelGGL(k_group_place, dim3(chunks), dim3(64), lds, s, P, g.C, g.QC, w.dval[dbuf],
                            w.dkey[dbuf], w.drect[dbuf], w.cntA, w.granges, w.gval, w.gloc);
     }
-    // persistent level-B grid: every wave loops over segments (a multiple of
-    // 8 workgroups, as k_tile_place's split of the segments over the XCDs needs)
-    const unsigned segs = (unsigned)((g.max_segments < 16384 ? g.max_segments : 16384) + 7) / 8 * 8;
+    // persistent level-B grids: every wave loops over segments (counting) or
+    // over (chunk, tile row) work items (placing; a multiple of 8 workgroups,
+    // as its split of the work items over the XCDs needs)
+    const unsigned segs = (unsigned)(g.max_segments < 16384 ? g.max_segments : 16384);
+    const int64_t max_items = ((g.max_segments + g.R - 1) / g.R + K) * kGroupH;
+    const unsigned place_grid = (unsigned)((max_items < 16384 ? max_items : 16384) + 7) / 8 * 8;
     {
         ProfScope _p("k_tile_count", s);
         hipLaunchKernelGGL(k_tile_count, dim3(segs), dim3(64), 0, s, P, g.S, w.seg_start, w.granges,
@@ -583,8 +616,8 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     {
         ProfScope _p("k_tile_place", s);
-        hipLaunchKernelGGL(k_tile_place, dim3(segs), dim3(64), 0, s, P, g.S, w.seg_start, w.granges,
-                           w.gval, w.gloc, w.cntB, w.ranges, w.tval);
+        hipLaunchKernelGGL(k_tile_place, dim3(place_grid), dim3(64), 0, s, P, g.S, g.R, w.seg_start,
+                           w.chunk_start, w.granges, w.gval, w.gloc, w.cntB, w.ranges, w.tval);
     }
     return hipGetLastError();
 }

@@ -27,16 +27,21 @@ struct BinGeom {
     int QC;                // chunks per frame
     int ng;                // groups of 8x8 tiles per frame
     int S;                 // group-list entries per level-B segment
+    int R;                 // segments per placement chunk (R * S entries)
     int64_t max_segments;  // bound on the level-B segments
 };
 BinGeom bin_geometry(int64_t n, int32_t n_frames, int ntx, int nty, uint64_t cap);
 
 // Per-(frame, Gaussian) record in float4 units.
 //   r0 = {u_hi, v_hi, u_lo, v_lo}   pixel centre as an unevaluated float pair
-//   r1 = {cA, cB, cC, o}           conic pre-scaled by -log2(e) (x 1/2 on A, C)
-//   r2 = {red, green, blue, d}     colour and range to the optical centre
-//   r3.. = {a sin psi_f, a cos psi_f} for each frequency f (two per float4)
-__host__ __device__ constexpr int record_float4s(int nf) { return 3 + (nf + 1) / 2; }
+//   r1 = {red, green, blue, d}     colour and range to the optical centre
+//   r2.. = {a sin psi_f, a cos psi_f} for each frequency f (two per float4)
+// and, in an array of its own (the preprocess backward reads only it),
+//   conic = {cA, cB, cC, o}        conic pre-scaled by -log2(e) (x 1/2 on A, C)
+__host__ __device__ constexpr int record_float4s(int nf) { return 2 + (nf + 1) / 2; }
+// The composite kernels stage an entry as float4 slots: 0 the centre
+// relative to the tile, 1 the conic, 2 colour and range, 3.. the phasors.
+__host__ __device__ constexpr int staged_float4s(int nf) { return record_float4s(nf) + 1; }
 // Gradient record per (frame, Gaussian), in floats:
 //   du, dv, dcA, dcB, dcC, do, dred, dgreen, dblue, dd, {d(a sin), d(a cos)} x nf
 __host__ __device__ constexpr int grad_floats(int nf) { return ((10 + 2 * nf) + 3) / 4 * 4; }
@@ -80,6 +85,7 @@ struct Params {
 struct Workspace {
     Status* status;
     float4* rec;            // [M][record_float4s]
+    float4* conic;          // [M]
     uint32_t* cnt;          // [M] tiles covered
     uint32_t* nf_block;     // [ceil(n / 256)] non-finite Gaussians per preprocess block
     uint32_t* dkey[2];      // [M] depth keys (double buffer)
@@ -91,6 +97,7 @@ struct Workspace {
     uint32_t* lenA;         // [F * ng] group-list lengths
     uint2* granges;         // [F * ng] group-list ranges in gval
     uint32_t* seg_start;    // [F * ng + 1] first level-B segment of each group
+    uint32_t* chunk_start;  // [F * ng + 1] first placement chunk (R segments) of each group
     uint32_t* gval;         // [cap] item ids of the group lists
     uint16_t* gloc;         // [cap] their rectangles clipped to the group, 3 bits per bound
     uint32_t* cntB;         // [max_segments][64] per-segment tile counts, then prefixes
@@ -123,6 +130,7 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nt
     const int64_t K = (int64_t)F * n_tiles;
     w.status = reinterpret_cast<Status*>(take(sizeof(Status)));
     w.rec = reinterpret_cast<float4*>(take(sizeof(float4) * record_float4s(nf) * M));
+    w.conic = reinterpret_cast<float4*>(take(sizeof(float4) * M));
     w.cnt = reinterpret_cast<uint32_t*>(take(4 * M));
     w.nf_block = reinterpret_cast<uint32_t*>(take(4 * (size_t)((n + 255) / 256 + 1)));
     for (int i = 0; i < 2; ++i) w.dkey[i] = reinterpret_cast<uint32_t*>(take(4 * M));
@@ -135,6 +143,7 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nt
     w.lenA = reinterpret_cast<uint32_t*>(take(4 * KG));
     w.granges = reinterpret_cast<uint2*>(take(sizeof(uint2) * KG));
     w.seg_start = reinterpret_cast<uint32_t*>(take(4 * (KG + 1)));
+    w.chunk_start = reinterpret_cast<uint32_t*>(take(4 * (KG + 1)));
     w.gval = reinterpret_cast<uint32_t*>(take(4 * cap));
     w.gloc = reinterpret_cast<uint16_t*>(take(2 * cap));
     w.cntB = reinterpret_cast<uint32_t*>(take(4 * 64 * (size_t)g.max_segments));

@@ -151,6 +151,7 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
                                                            const uint2* __restrict__ ranges,
                                                            const uint32_t* __restrict__ tval,
                                                            const float4* __restrict__ rec,
+                                                           const float4* __restrict__ conic,
                                                            gftorf_outputs out, uint2* __restrict__ wcount) {
     constexpr int BS = TW * TH;
     static_assert(BS % 64 == 0, "a tile is a whole number of waves");
@@ -160,7 +161,8 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
     // ~100-200 entries, so short batches also waste few record loads.
     constexpr int NWV = BS / 64;
     constexpr int RS4 = record_float4s(NF);
-    __shared__ float4 srec_w[NWV][RS4][64];
+    constexpr int SS4 = staged_float4s(NF);
+    __shared__ float4 srec_w[NWV][SS4][64];
 
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     const int f = w / P.n_tiles;
@@ -194,12 +196,13 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (j < rg.y) {
-            const float4* r = rec + (size_t)tval[j] * RS4;
-            const float4 r1 = r[1];
+            const uint32_t item = tval[j];
+            const float4* r = rec + (size_t)item * RS4;
+            const float4 r1 = conic[item];
             srec[0][lane] = stage_centre(r[0], r1.w, ox, oy, lamin);
             srec[1][lane] = r1;
 #pragma unroll
-            for (int q = 2; q < RS4; ++q) srec[q][lane] = r[q];
+            for (int q = 1; q < RS4; ++q) srec[q + 1][lane] = r[q];
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -328,19 +331,20 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
 template <int TW, int TH, int NF>
 __global__ void __launch_bounds__(64) k_composite_bwd(
     Params P, const gftorf_frame* __restrict__ frames, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ tval, const float4* __restrict__ rec,
+    const uint32_t* __restrict__ tval, const float4* __restrict__ rec, const float4* __restrict__ conic,
     const float* __restrict__ T_final, const int32_t* __restrict__ n_contrib,
     const float* __restrict__ d_rgb, const float* __restrict__ d_quad, const float* __restrict__ d_depth,
     float* __restrict__ grec, float* __restrict__ d_bg) {
     constexpr int PPT = TW * TH / 64;          // pixels per lane
     constexpr int B = 64;                      // list entries staged per batch
     constexpr int RS4 = record_float4s(NF);
+    constexpr int SS4 = staged_float4s(NF);
     constexpr int GS = grad_floats(NF);
     constexpr int NG = 10 + 2 * NF;            // gradient fields per entry
     constexpr int NGP = NG <= 16 ? 16 : 32;    // padded to a power of two
     static_assert(field_of_lane<NGP>(0) == 0 && field_of_lane<NGP>(NGP / 2) == 1,
                   "lanes 0 and NGP / 2 hold the totals of fields 0 and 1");
-    __shared__ float4 srec[RS4][B];
+    __shared__ float4 srec[SS4][B];
     __shared__ uint32_t sitem[B];
 
     const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -424,11 +428,11 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
             const uint32_t item = tval[hi - 1 - lane];
             sitem[lane] = item;
             const float4* r = rec + (size_t)item * RS4;
-            const float4 r1 = r[1];
+            const float4 r1 = conic[item];
             srec[0][lane] = stage_centre(r[0], r1.w, ox, oy, lamin);
             srec[1][lane] = r1;
 #pragma unroll
-            for (int q = 2; q < RS4; ++q) srec[q][lane] = r[q];
+            for (int q = 1; q < RS4; ++q) srec[q + 1][lane] = r[q];
         }
         __syncthreads();
         for (int s = 0; s < cnt; ++s) {
@@ -546,7 +550,7 @@ hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& 
     const unsigned blocks = (unsigned)(P.F * P.n_tiles);
 #define GFT_FWD(NF_)                                                                             \
     hipLaunchKernelGGL((k_composite_fwd<TW, TH, NF_>), dim3(blocks), dim3(TW * TH), 0, s, P, frames, \
-                       w.ranges, w.tval, w.rec, out, w.wcount)
+                       w.ranges, w.tval, w.rec, w.conic, out, w.wcount)
     {
         ProfScope _p("k_composite_fwd", s);
         switch (P.nf) {
@@ -568,7 +572,7 @@ hipError_t bwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& 
     ProfScope _p("k_composite_bwd", s);
 #define GFT_BWD(NF_)                                                                             \
     hipLaunchKernelGGL((k_composite_bwd<TW, TH, NF_>), dim3(blocks), dim3(64), 0, s, P, frames,    \
-                       w.ranges, w.tval, w.rec, sv.T_final, sv.n_contrib, dr, dq, dd, w.grec, dbg)
+                       w.ranges, w.tval, w.rec, w.conic, sv.T_final, sv.n_contrib, dr, dq, dd, w.grec, dbg)
     switch (P.nf) {
         case 1: GFT_BWD(1); break;
         case 2: GFT_BWD(2); break;

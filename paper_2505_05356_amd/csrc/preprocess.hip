@@ -179,7 +179,8 @@ __device__ __forceinline__ void optical_centre(const gftorf_frame& fr, double c[
 template <bool SH>
 __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g,
                                                     const gftorf_frame* __restrict__ frames,
-                                                    float4* __restrict__ rec, uint2* __restrict__ rect,
+                                                    float4* __restrict__ rec, float4* __restrict__ conic,
+                                                    uint2* __restrict__ rect,
                                                     uint32_t* __restrict__ cnt, uint32_t* __restrict__ dkey,
                                                     uint32_t* __restrict__ dval, uint32_t* __restrict__ nf_block) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,8 +213,8 @@ __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g
         const float u_hi = (float)b.u, v_hi = (float)b.v;
         float4* r = rec + item * RS4;
         r[0] = make_float4(u_hi, v_hi, (float)(b.u - (double)u_hi), (float)(b.v - (double)v_hi));
-        r[1] = make_float4((float)(-0.5 * L2E * A), (float)(-L2E * B), (float)(-0.5 * L2E * C),
-                           (float)o);
+        conic[item] = make_float4((float)(-0.5 * L2E * A), (float)(-L2E * B), (float)(-0.5 * L2E * C),
+                                  (float)o);
         double cc[3];
         optical_centre(fr, cc);
         const double e0 = b.m[0] - cc[0], e1 = b.m[1] - cc[1], e2 = b.m[2] - cc[2];
@@ -256,24 +257,26 @@ __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g
                 albedo = (double)fmaxf(acc, 0.0f);
             }
         }
-        r[2] = make_float4(rgb[0], rgb[1], rgb[2], (float)d);
+        r[1] = make_float4(rgb[0], rgb[1], rgb[2], (float)d);
         const double amp = (double)P.s_int * albedo / (d * d);
         float ph[2 * GFTORF_MAX_FREQ];
         for (int fi = 0; fi < P.nf; ++fi) {
-            // psi = 4 pi f d / c = 2 pi * cycles; reduce to the fractional cycle first
+            // psi = 4 pi f d / c = 2 pi * cycles; the fractional cycle is taken in
+            // binary64 (psi reaches tens of radians), then one float32 sine and
+            // cosine of 2 pi * frac (the hardware instructions take revolutions)
             double cyc = 2.0 * P.freq[fi] * d / kSpeedOfLight;
             cyc -= floor(cyc);
-            double sn, cs;
-            sincos(2.0 * M_PI * cyc, &sn, &cs);
-            ph[2 * fi] = (float)(amp * sn);
-            ph[2 * fi + 1] = (float)(amp * cs);
+            const float cf = (float)cyc;
+            const float sn = __builtin_amdgcn_sinf(cf), cs = __builtin_amdgcn_cosf(cf);
+            ph[2 * fi] = (float)amp * sn;
+            ph[2 * fi + 1] = (float)amp * cs;
         }
         for (int fi = P.nf; fi < 2 * ((P.nf + 1) / 2); ++fi) {
             ph[2 * fi] = 0.f;
             ph[2 * fi + 1] = 0.f;
         }
         for (int j = 0; j < (P.nf + 1) / 2; ++j)
-            r[3 + j] = make_float4(ph[4 * j], ph[4 * j + 1], ph[4 * j + 2], ph[4 * j + 3]);
+            r[2 + j] = make_float4(ph[4 * j], ph[4 * j + 1], ph[4 * j + 2], ph[4 * j + 3]);
     }
 }
 
@@ -311,7 +314,7 @@ template <int GS, bool SH>
 __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussians g,
                                                         const gftorf_frame* __restrict__ frames,
                                                         const uint32_t* __restrict__ cnt,
-                                                        const float4* __restrict__ rec,
+                                                        const float4* __restrict__ conic,
                                                         const float* __restrict__ grec,
                                                         gftorf_gaussians_grad out) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -381,7 +384,6 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
             if constexpr (SH) return sha[l];
             else return 0.f;
         };
-        const int RS4 = record_float4s(P.nf);
         const int GF = grad_floats(P.nf);
         const float L2E = 1.4426950408889634f;
         for (int f = f0; f < P.F; f += GS) {
@@ -393,7 +395,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
             }
             const gftorf_frame& fr = frames[f];
             const float* gr = grec + item * GF;
-            const float4 r1 = rec[item * RS4 + 1];
+            const float4 r1 = conic[item];
             const float t = fr.time;
 
             // trajectory and rotation at the frame time (as in the forward): the
@@ -633,10 +635,10 @@ void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_
     { ProfScope _p("k_preprocess", s);
     if (g.sh_rgb || g.sh_albedo)
         hipLaunchKernelGGL(k_preprocess<true>, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec,
-                           w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.nf_block);
+                           w.conic, w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.nf_block);
     else
         hipLaunchKernelGGL(k_preprocess<false>, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec,
-                           w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.nf_block);
+                           w.conic, w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.nf_block);
     }
 }
 
@@ -653,10 +655,10 @@ void launch_preprocess_bwd(const Params& P, const gftorf_gaussians& g, const gft
 #define GFT_PRE_BWD(G)                                                                                      \
     if (sh)                                                                                                  \
         hipLaunchKernelGGL((k_preprocess_bwd<G, true>), dim3(blocks), dim3(threads), 0, s, P, g, frames,      \
-                           w.cnt, w.rec, w.grec, grad);                                            \
+                           w.cnt, w.conic, w.grec, grad);                                            \
     else                                                                                                     \
         hipLaunchKernelGGL((k_preprocess_bwd<G, false>), dim3(blocks), dim3(threads), 0, s, P, g, frames,     \
-                           w.cnt, w.rec, w.grec, grad)
+                           w.cnt, w.conic, w.grec, grad)
     switch (gs) {
         case 1: GFT_PRE_BWD(1); break;
         case 2: GFT_PRE_BWD(2); break;
