@@ -29,10 +29,14 @@ builds on (§3, "GS image formation model"; §4 "Implementation details"):
 * camera space p = R x + t; culled unless p_z > near.
 * EWA projection: Sigma' = J R Rq S^2 Rq^T R^T J^T + dilation I, with the
   pinhole Jacobian J at p.
-* radius r = ceil(k sqrt(lambda_max(Sigma'))), k = extent_sigma (3 by default),
-  lambda_max = mid + sqrt(max(mid^2 - det, 0)).
-* tile rectangle: tiles x in [max(0, floor((u - r)/Tw)), min(nTx - 1,
-  floor((u + r)/Tw))], same for y; culled if empty or det <= 0.
+* extent: the ellipse (p - c)^T Sigma'^-1 (p - c) <= k^2, k = extent_sigma
+  (3 by default), whose axis-aligned bounding box has the half-widths
+  hx = k sqrt(Sigma'_xx), hy = k sqrt(Sigma'_yy).
+* tile rectangle: the tiles whose pixel centres reach into that box, i.e.
+  whose centre range [tx Tw + 1/2, (tx + 1) Tw - 1/2] meets [u - hx, u + hx]:
+  x in [max(0, floor((u - hx + 1/2)/Tw)), min(nTx - 1, floor((u + hx - 1/2)/Tw))],
+  same for y; culled if empty or det <= 0.  (Unbounded support with k <= 0:
+  every tile.)
 * depth key: the float32 rounding of p_z, compared as its bit pattern.
 * pair order: ascending (frame, tile, depth key, Gaussian index).
 
@@ -58,7 +62,8 @@ def project(g, frame, cfg, f=0):
     arrays); f selects the frame's row of the optional centre offsets.
 
     Returns a dict with u, v (pixel centre), S00, S01, S11 (2D covariance incl.
-    dilation), det, radius, rect (x_lo, x_hi, y_lo, y_hi as int64), count
+    dilation), det, half (the extent box's half-widths hx, hy), rect (x_lo,
+    x_hi, y_lo, y_hi as int64), count
     (tiles covered, 0 if culled), key (uint32 depth bits), pz, valid.
     """
     with np.errstate(all="ignore"):
@@ -142,10 +147,6 @@ def project(g, frame, cfg, f=0):
         S01 = (U0[0] * U1[0] + U0[1] * U1[1]) + U0[2] * U1[2]
         S11 = ((U1[0] * U1[0] + U1[1] * U1[1]) + U1[2] * U1[2]) + dil
         det = S00 * S11 - S01 * S01
-        mid = 0.5 * (S00 + S11)
-        disc = mid * mid - det
-        disc = np.where(disc > 0.0, disc, 0.0)
-        lam = mid + np.sqrt(disc)
 
         u = (fx * px) * iz + cx
         v = (fy * py) * iz + cy
@@ -154,15 +155,16 @@ def project(g, frame, cfg, f=0):
         nty = cfg.tiles_y
         ext = _d(cfg.extent_sigma)
         if ext > 0.0:
-            radius = np.ceil(ext * np.sqrt(lam))
+            hx = ext * np.sqrt(S00)
+            hy = ext * np.sqrt(S11)
             tw = float(cfg.tile_w)
             th = float(cfg.tile_h)
-            x_lo = np.maximum(np.floor((u - radius) / tw), 0.0)
-            x_hi = np.minimum(np.floor((u + radius) / tw), float(ntx - 1))
-            y_lo = np.maximum(np.floor((v - radius) / th), 0.0)
-            y_hi = np.minimum(np.floor((v + radius) / th), float(nty - 1))
+            x_lo = np.maximum(np.floor(((u - hx) + 0.5) / tw), 0.0)
+            x_hi = np.minimum(np.floor(((u + hx) - 0.5) / tw), float(ntx - 1))
+            y_lo = np.maximum(np.floor(((v - hy) + 0.5) / th), 0.0)
+            y_hi = np.minimum(np.floor(((v + hy) - 0.5) / th), float(nty - 1))
         else:  # unbounded support: every tile
-            radius = np.full_like(u, np.inf)
+            hx = hy = np.full_like(u, np.inf)
             x_lo = np.zeros_like(u)
             x_hi = np.full_like(u, float(ntx - 1))
             y_lo = np.zeros_like(u)
@@ -175,7 +177,7 @@ def project(g, frame, cfg, f=0):
         count = np.where(valid, (xh - xl + 1) * (yh - yl + 1), 0)
         key = pz.astype(np.float32).view(np.uint32)
         key = np.where(valid, key, np.uint32(0xFFFFFFFF)).astype(np.uint32)
-    return dict(u=u, v=v, S00=S00, S01=S01, S11=S11, det=det, radius=radius,
+    return dict(u=u, v=v, S00=S00, S01=S01, S11=S11, det=det, half=(hx, hy),
                 rect=np.stack([xl, xh, yl, yh]), count=count.astype(np.int64),
                 key=key, pz=pz, px=px, py=py, valid=valid)
 

@@ -5,7 +5,10 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 For every pixel: compute every Gaussian's screen-space quantities from the
 standard formulas (normalised quaternion rotation, EWA covariance with the
 pinhole Jacobian), keep those whose support reaches the pixel's tile (or all
-of them with unbounded support), order them by (float32 depth bits, index)
+of them with unbounded support: some pixel centre of the tile lies within the
+axis-aligned box around the extent ellipse, tested here by the distance from
+the centre to the tile's nearest pixel-centre row and column), order them by
+(float32 depth bits, index)
 and walk them one by one applying Eqs. 2, 4 and 5 of paper §3 with the skip /
 clamp / stop rules stated in oracle.render.  No vectorisation, no tiles
 shared between pixels: an independent check of oracle.render.
@@ -61,6 +64,7 @@ def gaussian_2d(g, k, frame, cfg):
     logit = _f32(g.opacity_logit[k])
     return dict(u=fx * p[0] / p[2] + cx, v=fy * p[1] / p[2] + cy,
                 A=c / det, B=-b / det, C=a / det, det=det, pz=p[2], lam=lam, d=d,
+                S2=[[a, b], [b, c]],
                 o=1.0 / (1.0 + math.exp(-logit)),
                 rgb=[_f32(g.rgb[i, k]) for i in range(3)],
                 amp=_f32(cfg.source_intensity) * _f32(g.albedo[k]) / (d * d),
@@ -90,9 +94,12 @@ def render_frame(g, frame, cfg):
                 if not (q["pz"] > cfg.near_z and q["det"] > 0):
                     continue
                 if cfg.extent_sigma > 0:
-                    r = math.ceil(cfg.extent_sigma * math.sqrt(q["lam"]))
-                    if not (math.floor((q["u"] - r) / cfg.tile_w) <= tx <= math.floor((q["u"] + r) / cfg.tile_w)
-                            and math.floor((q["v"] - r) / cfg.tile_h) <= ty <= math.floor((q["v"] + r) / cfg.tile_h)):
+                    # nearest pixel-centre column / row of the tile to the centre
+                    nx = min(max(q["u"], tx * cfg.tile_w + 0.5), (tx + 1) * cfg.tile_w - 0.5)
+                    ny = min(max(q["v"], ty * cfg.tile_h + 0.5), (ty + 1) * cfg.tile_h - 0.5)
+                    hx = cfg.extent_sigma * math.sqrt(q["S2"][0][0])
+                    hy = cfg.extent_sigma * math.sqrt(q["S2"][1][1])
+                    if abs(nx - q["u"]) > hx or abs(ny - q["v"]) > hy:
                         continue
                 cand.append((_f32bits(q["pz"]), k))
             cand.sort()

@@ -142,22 +142,21 @@ __device__ Binned bin(const Gauss& G, const gftorf_frame& fr, const Params& P,
     b.S01 = (U0[0] * U1[0] + U0[1] * U1[1]) + U0[2] * U1[2];
     b.S11 = ((U1[0] * U1[0] + U1[1] * U1[1]) + U1[2] * U1[2]) + dil;
     b.det = b.S00 * b.S11 - b.S01 * b.S01;
-    const double mid = 0.5 * (b.S00 + b.S11);
-    double disc = mid * mid - b.det;
-    disc = disc > 0.0 ? disc : 0.0;
-    const double lam = mid + sqrt(disc);
     b.u = (fx * px) * iz + (double)fr.cx;
     b.v = (fy * py) * iz + (double)fr.cy;
 
+    // tiles whose pixel-centre ranges [t T + 1/2, (t + 1) T - 1/2] meet the
+    // axis-aligned box of the extent ellipse, half-widths k sqrt(S00), k sqrt(S11)
     double xlo, xhi, ylo, yhi;
     const double ext = (double)P.extent;
     if (ext > 0.0) {
-        const double r = ceil(ext * sqrt(lam));
+        const double hx = ext * sqrt(b.S00);
+        const double hy = ext * sqrt(b.S11);
         const double tw = (double)P.tw, th = (double)P.th;
-        xlo = fmax(floor((b.u - r) / tw), 0.0);
-        xhi = fmin(floor((b.u + r) / tw), (double)(P.ntx - 1));
-        ylo = fmax(floor((b.v - r) / th), 0.0);
-        yhi = fmin(floor((b.v + r) / th), (double)(P.nty - 1));
+        xlo = fmax(floor(((b.u - hx) + 0.5) / tw), 0.0);
+        xhi = fmin(floor(((b.u + hx) - 0.5) / tw), (double)(P.ntx - 1));
+        ylo = fmax(floor(((b.v - hy) + 0.5) / th), 0.0);
+        yhi = fmin(floor(((b.v + hy) - 0.5) / th), (double)(P.nty - 1));
     } else {
         xlo = 0.0; xhi = (double)(P.ntx - 1);
         ylo = 0.0; yhi = (double)(P.nty - 1);

@@ -33,12 +33,50 @@ def test_axis_aligned_on_optical_axis_closed_form():
     assert p["S11"][0] == pytest.approx(s11, rel=1e-14)
     assert p["S01"][0] == 0.0
     assert (p["u"][0], p["v"][0]) == (32.0, 24.0)
-    r = math.ceil(3.0 * math.sqrt(max(s00, s11)))
-    assert p["radius"][0] == r
-    # rect by hand: tiles of 16 px
-    assert list(p["rect"][:, 0]) == [max(0, (32 - r) // 16), min(3, (32 + r) // 16),
-                                     max(0, (24 - r) // 16), min(2, (24 + r) // 16)]
+    # the extent box: half-widths 3 sqrt(S00), 3 sqrt(S11); its tiles are those
+    # whose pixel-centre range [16 t + 1/2, 16 t + 15.5] reaches into it
+    hx, hy = 3.0 * math.sqrt(p["S00"][0]), 3.0 * math.sqrt(p["S11"][0])
+    assert (p["half"][0][0], p["half"][1][0]) == (hx, hy)
+    assert hx == pytest.approx(3.0 * math.sqrt(s00), rel=1e-14)
+    tiles_x = [t for t in range(4) if 16 * t + 0.5 <= 32 + hx and 16 * t + 15.5 >= 32 - hx]
+    tiles_y = [t for t in range(3) if 16 * t + 0.5 <= 24 + hy and 16 * t + 15.5 >= 24 - hy]
+    assert list(p["rect"][:, 0]) == [tiles_x[0], tiles_x[-1], tiles_y[0], tiles_y[-1]]
+    assert tiles_x != [0, 1, 2, 3] or tiles_y != [0, 1, 2]   # not the whole frame
     assert p["key"][0] == np.float32(z).view(np.uint32)
+
+
+def test_extent_box_is_the_tight_box_of_the_ellipse():
+    # The tile rectangle is the set of tiles whose pixel-centre ranges meet
+    # the axis-aligned bounding box of the 3 sigma ellipse: for random
+    # ellipses (covariances from random scales and rotations) the box's
+    # half-widths equal the ellipse's extreme x and y (by dense sampling of
+    # its boundary), and every tile of the rectangle has a pixel centre in
+    # the box while its neighbours outside the rectangle have none
+    rng = np.random.default_rng(3)
+    cfg = scenes.RenderConfig(width=256, height=192)
+    fr = scenes.Frame(fx=120.0, fy=120.0, cx=128.0, cy=96.0)
+    n = 200
+    g = scenes.draw_gaussians(n, 256, 192, 120.0, 120.0, seed=4, z_range=(1.0, 3.0),
+                              log_scale_mean=float(np.log(0.08)), log_scale_std=0.6)
+    p = binning.project(g, fr, cfg)
+    th = np.linspace(0, 2 * np.pi, 20001)
+    checked = 0
+    for k in np.nonzero(p["valid"])[0]:
+        S = np.array([[p["S00"][k], p["S01"][k]], [p["S01"][k], p["S11"][k]]])
+        L = np.linalg.cholesky(S)
+        pts = 3.0 * (L @ np.stack([np.cos(th), np.sin(th)]))
+        hx, hy = p["half"][0][k], p["half"][1][k]
+        assert np.abs(pts[0]).max() == pytest.approx(hx, rel=1e-6)
+        assert np.abs(pts[1]).max() == pytest.approx(hy, rel=1e-6)
+        xl, xh, yl, yh = p["rect"][:, k]
+        u, v = p["u"][k], p["v"][k]
+        meets_x = lambda t: 16 * t + 0.5 <= u + hx and 16 * t + 15.5 >= u - hx
+        meets_y = lambda t: 16 * t + 0.5 <= v + hy and 16 * t + 15.5 >= v - hy
+        assert all(meets_x(t) for t in range(xl, xh + 1)) and all(meets_y(t) for t in range(yl, yh + 1))
+        assert (xl == 0 or not meets_x(xl - 1)) and (xh == cfg.tiles_x - 1 or not meets_x(xh + 1))
+        assert (yl == 0 or not meets_y(yl - 1)) and (yh == cfg.tiles_y - 1 or not meets_y(yh + 1))
+        checked += 1
+    assert checked > 100
 
 
 def test_rotation_about_z_closed_form():
