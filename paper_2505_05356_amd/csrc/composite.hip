@@ -312,7 +312,9 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
     out.n_contrib[(size_t)f * HW + pix] = (int32_t)last;
 }
 
-// Backward: one wave per (frame, tile); each lane owns PPT pixels of the tile
+// Backward: WPT waves per (frame, tile) (1 for large batches; 2 or 4 when
+// the batch has too few tiles to fill the chip), each walking the tile's list
+// for its own pixels; each lane owns PPT pixels of the tile
 // (pixel p = lane + 64 i), so the per-entry cross-lane reduction of the
 // gradient fields is paid once for PPT pixels.
 //
@@ -328,14 +330,14 @@ __global__ void __launch_bounds__(TW * TH) k_composite_fwd(Params P, const gftor
 //   dL/dalpha_k = T_k u_k + T_k^2 v_k - (A1 + 2 A2 + bg) / (1 - alpha_k),
 // so one running sum A = A1 + 2 A2 + bg per pixel suffices:
 //   A <- A + u_k alpha_k T_k + 2 v_k alpha_k T_k^2.
-template <int TW, int TH, int NF>
+template <int TW, int TH, int NF, int WPT>
 __global__ void __launch_bounds__(64) k_composite_bwd(
     Params P, const gftorf_frame* __restrict__ frames, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ tval, const float4* __restrict__ rec, const float4* __restrict__ conic,
     const float* __restrict__ T_final, const int32_t* __restrict__ n_contrib,
     const float* __restrict__ d_rgb, const float* __restrict__ d_quad, const float* __restrict__ d_depth,
     float* __restrict__ grec, float* __restrict__ d_bg) {
-    constexpr int PPT = TW * TH / 64;          // pixels per lane
+    constexpr int PPT = TW * TH / (64 * WPT);   // pixels per lane
     constexpr int B = 64;                      // list entries staged per batch
     constexpr int RS4 = record_float4s(NF);
     constexpr int SS4 = staged_float4s(NF);
@@ -347,7 +349,9 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
     __shared__ float4 srec[SS4][B];
     __shared__ uint32_t sitem[B];
 
-    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    // the WPT waves of a work item are consecutive after the remap: one XCD
+    const int wl = xcd_remap(blockIdx.x, gridDim.x);
+    const int w = wl / WPT, sub = wl - w * WPT;
     const int f = w / P.n_tiles;
     const int tile = w - f * P.n_tiles;
     const int ty = tile / P.ntx, tx = tile - ty * P.ntx;
@@ -368,7 +372,7 @@ __global__ void __launch_bounds__(64) k_composite_bwd(
     uint32_t maxl = 0;
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
-        const int pidx = lane + 64 * i;
+        const int pidx = lane + 64 * (sub + WPT * i);   // same column for all i
         const int x = tx * TW + pidx % TW, y = ty * TH + pidx / TW;
         const bool inside = x < P.W && y < P.H;
         fpx[i] = (float)(pidx % TW) + 0.5f;   // relative to the tile origin
@@ -564,14 +568,13 @@ hipError_t fwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& 
     return hipGetLastError();
 }
 
-template <int TW, int TH>
-hipError_t bwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w,
-                  const gftorf_outputs& sv, const float* dr, const float* dq, const float* dd,
-                  float* dbg, hipStream_t s) {
-    const unsigned blocks = (unsigned)(P.F * P.n_tiles);
-    ProfScope _p("k_composite_bwd", s);
-#define GFT_BWD(NF_)                                                                             \
-    hipLaunchKernelGGL((k_composite_bwd<TW, TH, NF_>), dim3(blocks), dim3(64), 0, s, P, frames,    \
+template <int TW, int TH, int WPT>
+hipError_t bwd_wpt(const Params& P, const gftorf_frame* frames, const Workspace& w,
+                   const gftorf_outputs& sv, const float* dr, const float* dq, const float* dd,
+                   float* dbg, hipStream_t s) {
+    const unsigned blocks = (unsigned)(P.F * P.n_tiles * WPT);
+#define GFT_BWD(NF_)                                                                                  \
+    hipLaunchKernelGGL((k_composite_bwd<TW, TH, NF_, WPT>), dim3(blocks), dim3(64), 0, s, P, frames,     \
                        w.ranges, w.tval, w.rec, w.conic, sv.T_final, sv.n_contrib, dr, dq, dd, w.grec, dbg)
     switch (P.nf) {
         case 1: GFT_BWD(1); break;
@@ -581,6 +584,26 @@ hipError_t bwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& 
     }
 #undef GFT_BWD
     return hipGetLastError();
+}
+
+// Waves per work item of the backward: one while the batch's tiles give at
+// least kBwdWaves waves (several per SIMD, 1024 SIMDs), else 2 (4 below a
+// quarter of that) sharing each tile's list, so a small batch still fills
+// the chip.  Measured on one 640 x 480 frame (1200 tiles): 133 us with one
+// wave per tile, 108 us with two, 107 us with four.
+constexpr int64_t kBwdWaves = 4096;
+
+template <int TW, int TH>
+hipError_t bwd_nf(const Params& P, const gftorf_frame* frames, const Workspace& w,
+                  const gftorf_outputs& sv, const float* dr, const float* dq, const float* dd,
+                  float* dbg, hipStream_t s) {
+    ProfScope _p("k_composite_bwd", s);
+    const int64_t items = (int64_t)P.F * P.n_tiles;
+    if constexpr (TW * TH >= 256) {
+        if (items * 4 <= kBwdWaves) return bwd_wpt<TW, TH, 4>(P, frames, w, sv, dr, dq, dd, dbg, s);
+        if (items < kBwdWaves) return bwd_wpt<TW, TH, 2>(P, frames, w, sv, dr, dq, dd, dbg, s);
+    }
+    return bwd_wpt<TW, TH, 1>(P, frames, w, sv, dr, dq, dd, dbg, s);
 }
 
 }  // namespace
