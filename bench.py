@@ -51,14 +51,25 @@ SORT_BYTES_PER_KEY_PASS = 16  # read key + value, write key + value (4 B each)
 # the sha256 of the kernel's source files must match; otherwise traffic is null.
 FETCH_SCALE, WRITE_SCALE = 1048576 / 524318, 1048576 / 1048576   # 1 GiB copy: FETCH 524318 KiB, WRITE 1048576 KiB
 COMPOSITE_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
+BIN_FILES = ("paper_2505_05356_amd/csrc/bin.hip", "paper_2505_05356_amd/csrc/common.h")
 MLP_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
+_COMPOSITE_SHA = "f23ac1235992e26d083b2d846450b4a26cc839e57c7310dc3fe29ddbd92d7073"
+_BIN_SHA = "8e98b244e8c1cb07e7265f46138f1d5a954b7573fe5088756fcfd202292179a6"
 # {workload: {kernel: (source files, sha256, (FETCH KiB, WRITE KiB) per launch)}};
 # k_mlp_dw counts its three launches together
 TRAFFIC = {
+    "dynamic-200k-gaussians-8f-640x480": {
+        "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (52204, 50919)),
+        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (5290, 96166)),
+        "k_tile_place": (BIN_FILES, _BIN_SHA, (9758, 164188))},
+    "dynamic-1000k-1024x768-16f-2freq": {
+        "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (361238, 247936)),
+        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (19685, 690577)),
+        "k_tile_place": (BIN_FILES, _BIN_SHA, (121890, 2351202))},
     "deform-mlp-200k-x8-8x256-pe10": {
-        k: (MLP_FILES, "f1b745f06183ff2d944649cbf7dd720bad7364413c623bf710699554d42ef79f", kib)
-        for k, kib in (("k_mlp_fwd", (218924, 7156260)), ("k_mlp_bwd", (364013, 6468750)),
-                       ("k_mlp_dw", (6575126, 275391)))},
+        k: (MLP_FILES, "758fb7db4681d89e83ed8c3e0ed2175bdec48243246efba660bfe0392d4a448f", kib)
+        for k, kib in (("k_mlp_fwd", (219623, 7156258)), ("k_mlp_bwd", (375813, 6468750)),
+                       ("k_mlp_dw", (6575106, 275395)))},
 }
 
 
