@@ -314,7 +314,8 @@ int gftorf_graph_destroy(void* graph_exec);
  * launches beyond that are not timed.  collect waits for the recorded events,
  * adds their durations to per-kernel totals and frees the slots; end collects,
  * copies up to max_entries totals to `out` (host) and switches timing off.
- * Profiling state is process-wide; use it from one thread at a time. */
+ * Profiling state belongs to the calling thread: a thread's begin times only
+ * the launches that thread makes, and collect / end see only its records. */
 typedef struct gftorf_profile_entry {
     char name[48];       /* kernel name                      */
     int64_t launches;    /* timed launches                   */

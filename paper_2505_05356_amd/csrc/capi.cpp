@@ -113,7 +113,9 @@ struct Profiler {
     std::vector<ProfRec> recs;
     std::map<std::string, std::pair<int64_t, double>> totals;
 };
-Profiler g_prof;
+// One profiler per calling thread, like the error string: a thread times the
+// launches it makes itself, and threads never share timing state.
+thread_local Profiler g_prof;
 
 }  // namespace
 

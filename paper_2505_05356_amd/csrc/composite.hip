@@ -1,6 +1,7 @@
 // Front-to-back compositing (forward) and back-to-front gradient recursion
 // (backward) of RGB, mean depth and raw C-ToF quads, one workgroup per
-// (frame, tile) work item and one thread per pixel.
+// (frame, tile) work item: one thread per pixel in the forward, 4 pixels per
+// lane in the backward.
 //
 // Forward (paper §3): for each pixel walk the tile's depth-sorted list and
 //   alpha = min(alpha_max, o G(x)),  skip if alpha < alpha_min,
@@ -20,8 +21,10 @@
 //
 // Records of 64 list entries at a time are staged in LDS by each wave, in
 // its own slice (the forward's waves walk their tile's list independently;
-// the backward is one wave per tile): one coalesced 64-byte gather per
-// entry, then every lane of the wave reads them as LDS broadcasts.  No MFMA: per (pixel, entry) this is ~20 FP32 VALU
+// the backward has one wave per tile in large batches and 2 or 4 waves, each
+// with its own pixels, in small ones): one coalesced gather per entry of its
+// 48-byte record and 16-byte conic, then every lane of the wave reads them as
+// LDS broadcasts.  No MFMA: per (pixel, entry) this is ~20 FP32 VALU
 // operations and one v_exp_f32.
 #include "block_scan.h"
 #include "common.h"
