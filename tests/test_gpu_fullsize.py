@@ -107,3 +107,22 @@ def test_fullsize_sampled_tiles(name):
         if not dynamic and k in ("vel", "acc", "omega"):
             continue
         assert_grads_close(res["grads"][k], r, f"{name}/{k}")
+
+
+@pytest.mark.parametrize("max_pairs", [20_000_000, 200_000_000])
+def test_large_batch_overflow_is_recovered(max_pairs):
+    """1M Gaussians x 16 frames, whose level-A chunks of 1024 items are placed
+    by (chunk, group row), with a pair capacity below the need: 20M cuts
+    through the group lists, 200M only through the tile lists, so some lists
+    take the capacity-checked stores and the others the unchecked ones.  The
+    status reports the overflow, and the forward regrows the workspace and
+    renders exactly what a sufficient capacity renders."""
+    wl = scenes.cfg4()
+    res = run_gpu(wl.gaussians, wl.frames, wl.cfg, max_pairs=max_pairs, channels=("rgb",))
+    st = res["status"]
+    assert st["n_pairs"] > max_pairs and res["_ws"].max_pairs >= st["n_pairs"]
+    rgb = res["rgb"]
+    del res
+    ref = run_gpu(wl.gaussians, wl.frames, wl.cfg, channels=("rgb",))
+    assert not ref["status"]["overflow"]
+    np.testing.assert_array_equal(rgb, ref["rgb"])
