@@ -76,8 +76,8 @@ TRAFFIC = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=200_000)
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--tile", default="16x16", help="WxH (8x8, 16x16, 32x8) or auto")
@@ -542,6 +542,17 @@ def main():
         wall = time.perf_counter() - t0
         return s.elapsed_time(e), wall
 
+    def median_step(step, k):
+        """Median of k single-step times (an event after every step)."""
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for i in range(k):
+            step()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        return float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(k)]))
+
     for _ in range(args.warmup):
         step_batched()
     ms_b, wall_b = timed(step_batched, args.steps)
@@ -581,12 +592,16 @@ def main():
     print(f"# batched, graph-replayed: {ms_g:.3f} ms/step, {graph_value:.1f} frames/s",
           file=sys.stderr, flush=True)
 
-    per_frame = None
+    med_b = median_step(step_batched, args.steps)
+    print(f"# batched, median of {args.steps} steps: {med_b:.3f} ms/step", file=sys.stderr, flush=True)
+
+    per_frame = med_p = None
     if not args.no_per_frame:
         for _ in range(args.warmup):
             step_per_frame()
         ms_p, _ = timed(step_per_frame, args.steps)
         per_frame = F * args.steps / (ms_p / 1e3)
+        med_p = median_step(step_per_frame, args.steps)
         print(f"# per-frame: {ms_p / args.steps:.3f} ms/step, {per_frame:.1f} frames/s",
               file=sys.stderr, flush=True)
 
@@ -645,6 +660,9 @@ def main():
         "graph_ms_per_step": round(ms_g, 4),
         "per_frame_value": None if per_frame is None else round(per_frame, 2),
         "batched_over_per_frame": None if per_frame is None else round(value / per_frame, 3),
+        "median_ms_per_step": round(med_b, 4),
+        "median_value": round(F / (med_b / 1e3), 2),
+        "per_frame_median_value": None if med_p is None else round(F / (med_p / 1e3), 2),
         "roofline": roof,
         "kernels_ms": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
         "cpu_baseline": cpu,
