@@ -53,19 +53,21 @@ FETCH_SCALE, WRITE_SCALE = 1048576 / 524318, 1048576 / 1048576   # 1 GiB copy: F
 COMPOSITE_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
 BIN_FILES = ("paper_2505_05356_amd/csrc/bin.hip", "paper_2505_05356_amd/csrc/common.h")
 MLP_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
-_COMPOSITE_SHA = "f23ac1235992e26d083b2d846450b4a26cc839e57c7310dc3fe29ddbd92d7073"
-_BIN_SHA = "8e98b244e8c1cb07e7265f46138f1d5a954b7573fe5088756fcfd202292179a6"
+_COMPOSITE_SHA = "00c0986837c56de4efd0f3e9aec1d2328c9cce34094f5deb57a74fd8f8b13688"
+_BIN_SHA = "f57bf280b710c793bc9c823fe32b68de94bf66b7bb4d1e146e81e82e5bdca1a3"
 # {workload: {kernel: (source files, sha256, (FETCH KiB, WRITE KiB) per launch)}};
 # k_mlp_dw counts its three launches together
 TRAFFIC = {
     "dynamic-200k-gaussians-8f-640x480": {
-        "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (52204, 50919)),
-        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (5290, 96166)),
-        "k_tile_place": (BIN_FILES, _BIN_SHA, (9758, 164188))},
+        "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (52205, 50919)),
+        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (5291, 96150)),
+        "k_tile_place": (BIN_FILES, _BIN_SHA, (9659, 155244)),
+        "k_group_place": (BIN_FILES, _BIN_SHA, (12914, 22728))},
     "dynamic-1000k-1024x768-16f-2freq": {
-        "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (361238, 247936)),
-        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (19685, 690577)),
-        "k_tile_place": (BIN_FILES, _BIN_SHA, (121890, 2351202))},
+        "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (361227, 247936)),
+        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (19684, 690600)),
+        "k_tile_place": (BIN_FILES, _BIN_SHA, (90602, 2047298)),
+        "k_group_place": (BIN_FILES, _BIN_SHA, (130321, 513953))},
     "deform-mlp-200k-x8-8x256-pe10": {
         k: (MLP_FILES, "758fb7db4681d89e83ed8c3e0ed2175bdec48243246efba660bfe0392d4a448f", kib)
         for k, kib in (("k_mlp_fwd", (219623, 7156258)), ("k_mlp_bwd", (375813, 6468750)),
