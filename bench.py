@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # them disabled): 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz.
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
-# Algorithmic work per unit (measurement section), NF = 1:
+# Algorithmic work per unit, NF = 1 (the FLOP that the method's arithmetic
+# needs per evaluated and per composited (pixel, Gaussian) pair):
 #   alpha evaluation: dx, dy (4 sub), quadratic form (3 mul + 2 fma), exp2, o*G  -> 12
 #   forward composite: 1 - a, T(1 - a), w1, w2 (4) + 6 FMA (rgb 3, depth 1, S, C) -> 16
 #   backward composite: T / (1 - a), S2 terms for rgb and depth (16), S3 terms (11),
@@ -450,7 +451,7 @@ def bench_cfg3_variant(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
