@@ -55,7 +55,7 @@ COMPOSITE_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_
 BIN_FILES = ("paper_2505_05356_amd/csrc/bin.hip", "paper_2505_05356_amd/csrc/common.h")
 MLP_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
 _COMPOSITE_SHA = "00c0986837c56de4efd0f3e9aec1d2328c9cce34094f5deb57a74fd8f8b13688"
-_BIN_SHA = "f57bf280b710c793bc9c823fe32b68de94bf66b7bb4d1e146e81e82e5bdca1a3"
+_BIN_SHA = "2c8aaee64a9b161bd303190c923adf85584c40f7f44a33bf44cf67d435ee75ee"
 # {workload: {kernel: (source files, sha256, (FETCH KiB, WRITE KiB) per launch)}};
 # k_mlp_dw counts its three launches together
 TRAFFIC = {

@@ -146,9 +146,9 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t peers) {
 // writes at the group's cursor plus its rank among them, so one store appends
 // a contiguous run to the group list and depth order holds inside every list.
 // A wave appends each group's run over the whole chunk, so its stores fill
-// whole cache lines instead of scattering a few entries per group and batch.  FAST: the row's
-// group lists all end strictly below the capacity (their ranges are clamped
-// to it), so the stores need no check.
+// whole cache lines instead of scattering a few entries per group and batch.
+// FAST: the row's group lists all end strictly below the capacity (their
+// ranges are clamped to it), so the stores need no check.
 template <bool FAST>
 __device__ __forceinline__ void place_group_row(const Groups& G, long long beg, long long end, uint32_t gy, int lane,
                                                 uint32_t* cursor, uint32_t cap,
