@@ -46,11 +46,29 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_upsweep(const uint32_t* _
     for (long long g = blockIdx.x; g < ntiles; g += gridDim.x) {
         const SortTile st = sort_tile(g, n, tpf);
         for (int i = threadIdx.x; i < 4 * kSortBuckets; i += kSortThreads) (&hist[0][0])[i] = 0;
+        // a histogram needs no element order: each thread loads its 8 keys
+        // as two 16-byte vectors where the tile is whole and 16-byte aligned,
+        // all loads in flight before the first count
+        uint32_t kv[kSortItems];
+        const long long i0 = st.beg + (long long)threadIdx.x * 4;
+        const bool vec = st.end - st.beg == kSortTile && (st.beg & 3) == 0;
+        if (vec) {
+            const uint4 a = *reinterpret_cast<const uint4*>(keys + i0);
+            const uint4 b = *reinterpret_cast<const uint4*>(keys + i0 + 4 * kSortThreads);
+            kv[0] = a.x, kv[1] = a.y, kv[2] = a.z, kv[3] = a.w;
+            kv[4] = b.x, kv[5] = b.y, kv[6] = b.z, kv[7] = b.w;
+        } else {
+#pragma unroll
+            for (int it = 0; it < kSortItems; ++it) {
+                const long long idx = st.beg + it * kSortThreads + threadIdx.x;
+                kv[it] = idx < st.end ? keys[idx] : 0u;
+            }
+        }
         __syncthreads();
-#pragma unroll 4
+#pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
-            const long long idx = st.beg + it * kSortThreads + threadIdx.x;
-            if (idx < st.end) atomicAdd(&hist[wave][(keys[idx] >> shift) & 0xffu], 1u);
+            const bool ok = vec || st.beg + it * kSortThreads + threadIdx.x < st.end;
+            if (ok) atomicAdd(&hist[wave][(kv[it] >> shift) & 0xffu], 1u);
         }
         __syncthreads();
         const int d = threadIdx.x;
