@@ -451,12 +451,13 @@ __global__ void __launch_bounds__(64) k_tile_count(Params P, int S, const uint32
 template <bool FAST>
 __device__ __forceinline__ void place_batch(uint32_t row, uint32_t item, uint32_t (&cur)[kGroupW], uint32_t ncol,
                                             uint32_t cap, uint32_t* __restrict__ tval) {
+    // no branch per tile: an empty ballot stores nothing and leaves the
+    // cursor, and the row bits of tiles beyond the frame's edge are cleared
+    row &= (1u << ncol) - 1u;
 #pragma unroll
     for (int c = 0; c < kGroupW; ++c) {
-        if ((uint32_t)c >= ncol) break;
         const bool mine = (row >> c) & 1u;
         const uint64_t peers = __ballot(mine);
-        if (peers == 0ull) continue;
         const uint32_t cnt = (uint32_t)__popcll(peers);
         if (mine) {
             const uint32_t pos = cur[c] + rank_below(peers);
