@@ -148,10 +148,13 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t peers) {
 // A wave appends each group's run over the whole chunk, so its stores fill
 // whole cache lines instead of scattering a few entries per group and batch.
 // FAST: the row's group lists all end strictly below the capacity (their
-// ranges are clamped to it), so the stores need no check.
-template <bool FAST>
+// ranges are clamped to it), so the stores need no check.  REG: the row has
+// at most kGroupW groups, whose cursors stay in scalar registers under an
+// unrolled, branch-free column loop (an empty ballot stores nothing);
+// otherwise they live in LDS.
+template <bool FAST, bool REG>
 __device__ __forceinline__ void place_group_row(const Groups& G, long long beg, long long end, uint32_t gy, int lane,
-                                                uint32_t* cursor, uint32_t cap,
+                                                uint32_t* cursor, uint32_t (&cur)[kGroupW], uint32_t cap,
                                                 const uint32_t* __restrict__ dval,
                                                 const uint32_t* __restrict__ dkey,
                                                 const uint2* __restrict__ drect,
@@ -187,13 +190,9 @@ __device__ __forceinline__ void place_group_row(const Groups& G, long long beg, 
         // the rows of the rectangle clipped to this group row
         const uint32_t y0 = max(ylo, oy) - oy, y1 = min(yhi, oy + kGroupH - 1) - oy;
         const uint32_t ybits = (y0 << 6) | (y1 << 9);
-        for (int c = 0; c < G.ngx; ++c) {
-            const bool mine = gx0 <= c && c <= gx1;
-            const uint64_t peers = __ballot(mine);
-            if (peers == 0ull) continue;
-            const uint32_t cur = cursor[c];
+        auto place = [&](int c, uint32_t at, uint64_t peers, bool mine) {
             if (mine) {
-                const uint32_t pos = cur + rank_below(peers);
+                const uint32_t pos = at + rank_below(peers);
                 const uint32_t ox = (uint32_t)c * kGroupW;
                 const uint32_t x0 = max(xlo, ox) - ox, x1 = min(xhi, ox + kGroupW - 1) - ox;
                 if (FAST || pos < cap) {
@@ -201,11 +200,28 @@ __device__ __forceinline__ void place_group_row(const Groups& G, long long beg, 
                     gloc[pos] = (uint16_t)(x0 | (x1 << 3) | ybits);
                 }
             }
-            if (lane == 0) cursor[c] = cur + (uint32_t)__popcll(peers);
+        };
+        if constexpr (REG) {
+#pragma unroll
+            for (int c = 0; c < kGroupW; ++c) {   // columns past the frame never match
+                const bool mine = gx0 <= c && c <= gx1;
+                const uint64_t peers = __ballot(mine);
+                place(c, cur[c], peers, mine);
+                cur[c] = (uint32_t)__builtin_amdgcn_readfirstlane((int)(cur[c] + (uint32_t)__popcll(peers)));
+            }
+        } else {
+            for (int c = 0; c < G.ngx; ++c) {
+                const bool mine = gx0 <= c && c <= gx1;
+                const uint64_t peers = __ballot(mine);
+                if (peers == 0ull) continue;
+                const uint32_t at = cursor[c];
+                place(c, at, peers, mine);
+                if (lane == 0) cursor[c] = at + (uint32_t)__popcll(peers);
+            }
+            // lane 0's cursor writes precede the next batch's reads by every lane
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
-        // lane 0's cursor writes precede the next batch's reads by every lane
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -237,6 +253,24 @@ __global__ void __launch_bounds__(64) k_group_place_rows(Params P, int C, int QC
         const size_t g0 = (size_t)f * G.ng + (size_t)gy * G.ngx;
         const uint32_t* pre = cntA + (size_t)chunk * G.ng + (size_t)gy * G.ngx;
         uint32_t el = 0;
+        uint32_t cur[kGroupW];
+        // the ranges are clamped to the capacity, so only an end strictly
+        // below it proves that the whole list fits
+        if (G.ngx <= kGroupW) {   // cursors of lanes 0 .. ngx-1, then wave-uniform
+            uint32_t cl = 0;
+            if (lane < G.ngx) {
+                const uint2 gr = granges[g0 + lane];
+                cl = gr.x + pre[lane];
+                el = gr.y;
+            }
+#pragma unroll
+            for (int c = 0; c < kGroupW; ++c) cur[c] = (uint32_t)__builtin_amdgcn_readlane((int)cl, c);
+            if (__ballot(el >= cap) == 0ull)
+                place_group_row<true, true>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
+            else
+                place_group_row<false, true>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
+            continue;
+        }
         __syncthreads();   // the previous work item's cursor reads are done
         for (int c = lane; c < G.ngx; c += 64) {
             const uint2 gr = granges[g0 + c];
@@ -244,12 +278,10 @@ __global__ void __launch_bounds__(64) k_group_place_rows(Params P, int C, int QC
             el = max(el, gr.y);
         }
         __syncthreads();
-        // the ranges are clamped to the capacity, so only an end strictly
-        // below it proves that the whole list fits
         if (__ballot(el >= cap) == 0ull)
-            place_group_row<true>(G, beg, end, gy, lane, cursor, cap, dval, dkey, drect, gval, gloc);
+            place_group_row<true, false>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
         else
-            place_group_row<false>(G, beg, end, gy, lane, cursor, cap, dval, dkey, drect, gval, gloc);
+            place_group_row<false, false>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
     }
 }
 
