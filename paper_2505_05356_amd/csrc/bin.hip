@@ -139,8 +139,8 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t peers) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
 }
 
-// Placing pass of level A for large batches (k_group_place_rows, used with
-// chunks of 1024 items).  Work item = (chunk, group row gy); one wave walks
+// Placing pass of level A for large and for small batches (k_group_place_rows;
+// the launch chooses).  Work item = (chunk, group row gy); one wave walks
 // the chunk's depth-ordered items 64 at a time (lane = item) and, for each
 // group column, ballots the lanes whose rectangle covers that group: each
 // writes at the group's cursor plus its rank among them, so one store appends
@@ -769,10 +769,12 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     if (chunks) {
         ProfScope _p("k_group_place", s);
         const int ngx = (P.ntx + kGroupW - 1) / kGroupW, ngy = (P.nty + kGroupH - 1) / kGroupH;
-        if (g.C >= 1024) {
-            // large batches: one wave per (chunk, group row), runs of whole
-            // lines (measured at 1M Gaussians x 16 frames: 622 -> 477 us);
-            // smaller ones keep one wave per chunk (200k x 8: 27 against 30 us)
+        if (g.C >= 1024 || chunks < 4096) {
+            // large batches (1024-item chunks) and small ones (fewer than 4096
+            // one-wave chunks, e.g. one 640 x 480 frame): one wave per (chunk,
+            // group row), runs of whole lines (1M x 16 frames: 622 -> 394 us;
+            // 100k x 1 frame: 13.8 -> 7.3 us); in between, one wave per chunk
+            // (200k x 8 frames: 27 against 30 us)
             const int64_t items = (int64_t)P.F * g.QC * ngy;
             const unsigned grid = (unsigned)((items < 16384 ? items : 16384) + 7) / 8 * 8;
             hipLaunchKernelGGL(k_group_place_rows, dim3(grid), dim3(64), 4 * (size_t)ngx, s, P, g.C, g.QC,
