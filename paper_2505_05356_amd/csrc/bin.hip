@@ -139,14 +139,14 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t peers) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
 }
 
-// Placing pass of level A for large and for small batches (k_group_place_rows;
-// the launch chooses).  Work item = (chunk, group row gy); one wave walks
-// the chunk's depth-ordered items 64 at a time (lane = item) and, for each
-// group column, ballots the lanes whose rectangle covers that group: each
-// writes at the group's cursor plus its rank among them, so one store appends
-// a contiguous run to the group list and depth order holds inside every list.
-// A wave appends each group's run over the whole chunk, so its stores fill
-// whole cache lines instead of scattering a few entries per group and batch.
+// Placing pass of level A.  Work item = (run of RA consecutive chunks of one
+// frame, group row gy); one wave walks the run's depth-ordered items 64 at a
+// time (lane = item) and, for each group column, ballots the lanes whose
+// rectangle covers that group: each writes at the group's cursor plus its
+// rank among them, so one store appends a contiguous run to the group list
+// and depth order holds inside every list.  A wave appends each group's run
+// over the whole run of chunks, so its stores fill whole cache lines instead
+// of scattering a few entries per group and batch.
 // FAST: the row's group lists all end strictly below the capacity (their
 // ranges are clamped to it), so the stores need no check.  REG: the row has
 // at most kGroupW groups, whose cursors stay in scalar registers under an
@@ -225,7 +225,7 @@ __device__ __forceinline__ void place_group_row(const Groups& G, long long beg, 
     }
 }
 
-__global__ void __launch_bounds__(64) k_group_place_rows(Params P, int C, int QC,
+__global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC, int RA,
                                                          const uint32_t* __restrict__ dval,
                                                          const uint32_t* __restrict__ dkey,
                                                          const uint2* __restrict__ drect,
@@ -237,18 +237,20 @@ __global__ void __launch_bounds__(64) k_group_place_rows(Params P, int C, int QC
     const Groups G = groups_of(P);
     const int lane = threadIdx.x;
     const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
-    const uint32_t nitems = (uint32_t)P.F * (uint32_t)QC * (uint32_t)G.ngy;
-    // the rows of one chunk are consecutive work items, so they read the
-    // chunk's items through one L2; each XCD takes one contiguous eighth of
-    // the work items
+    const uint32_t nrun = ((uint32_t)QC + (uint32_t)RA - 1) / (uint32_t)RA;   // runs of RA chunks per frame
+    const uint32_t nitems = (uint32_t)P.F * nrun * (uint32_t)G.ngy;
+    // the rows of one run are consecutive work items, so they read the run's
+    // items through one L2; each XCD takes one contiguous eighth of the work
+    // items
     const uint32_t per_xcd = gridDim.x / kXcds, xcd = blockIdx.x % kXcds;
     const uint32_t hi = (uint32_t)((uint64_t)nitems * (xcd + 1) / kXcds);
     for (uint32_t wi = (uint32_t)((uint64_t)nitems * xcd / kXcds) + blockIdx.x / kXcds; wi < hi; wi += per_xcd) {
-        const uint32_t chunk = wi / (uint32_t)G.ngy;
-        const uint32_t gy = wi - chunk * (uint32_t)G.ngy;
-        const uint32_t f = chunk / (uint32_t)QC, q = chunk - f * (uint32_t)QC;
+        const uint32_t fr = wi / (uint32_t)G.ngy;
+        const uint32_t gy = wi - fr * (uint32_t)G.ngy;
+        const uint32_t f = fr / nrun, q = (fr - f * nrun) * (uint32_t)RA;   // the run's first chunk
+        const uint32_t chunk = f * (uint32_t)QC + q;
         const long long beg = (long long)f * P.n + (long long)q * C;
-        const long long end = min(beg + C, (long long)(f + 1) * P.n);
+        const long long end = min(beg + (long long)RA * C, (long long)(f + 1) * P.n);
         // cursors: the group list start plus the items of earlier chunks
         const size_t g0 = (size_t)f * G.ng + (size_t)gy * G.ngx;
         const uint32_t* pre = cntA + (size_t)chunk * G.ng + (size_t)gy * G.ngx;
@@ -282,88 +284,6 @@ __global__ void __launch_bounds__(64) k_group_place_rows(Params P, int C, int QC
             place_group_row<true, false>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
         else
             place_group_row<false, false>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
-    }
-}
-
-// One wave per chunk, 64 depth-ordered items at a time (lane = item).  Every
-// (item, group) entry takes the position cursor[group] + (number of lanes
-// below it whose group rectangle also contains that group); the set of such
-// lanes is the AND of four ballot masks looked up by column and row, so all
-// lanes place their entries at once and the depth order inside every group
-// list is kept.  The leaders (lowest lane per group) then advance the cursors.
-__global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC,
-                                                    const uint32_t* __restrict__ dval,
-                                                    const uint32_t* __restrict__ dkey,
-                                                    const uint2* __restrict__ drect,
-                                                    const uint32_t* __restrict__ cntA,
-                                                    const uint2* __restrict__ granges,
-                                                    uint32_t* __restrict__ gval,
-                                                    uint16_t* __restrict__ gloc) {
-    extern __shared__ uint64_t dyn_[];
-    const Groups G = groups_of(P);
-    uint64_t* x_lo = dyn_;             // [ngx] lanes whose first group column <= v
-    uint64_t* x_hi = x_lo + G.ngx;     // [ngx] lanes whose last group column >= v
-    uint64_t* y_lo = x_hi + G.ngx;     // [ngy] same for rows
-    uint64_t* y_hi = y_lo + G.ngy;
-    uint32_t* cursor = reinterpret_cast<uint32_t*>(y_hi + G.ngy);   // [ng]
-    // consecutive chunks write adjacent runs of every group list: one XCD
-    const int chunk = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int f = chunk / QC, q = chunk - f * QC;
-    const int lane = threadIdx.x;
-    const uint32_t cap = (uint32_t)(P.cap < 0xffffffffull ? P.cap : 0xffffffffull);
-    const uint32_t* pre = cntA + (size_t)chunk * G.ng;
-    for (int t = lane; t < G.ng; t += 64) cursor[t] = granges[(size_t)f * G.ng + t].x + pre[t];
-    const long long beg = (long long)f * P.n + (long long)q * C;
-    const long long end = min(beg + C, (long long)(f + 1) * P.n);
-    const int nv = max(G.ngx, G.ngy);
-    for (long long j0 = beg; j0 < end; j0 += 64) {
-        int gx0 = 1, gx1 = 0, gy0 = 1, gy1 = 0;   // empty: never in a ballot
-        uint32_t item = 0, xlo = 0, xhi = 0, ylo = 0, yhi = 0;
-        if (j0 + lane < end && dkey[j0 + lane] != kCulledKey) {
-            item = dval[j0 + lane];
-            unpack_rect(drect[j0 + lane], xlo, xhi, ylo, yhi);
-            gx0 = (int)(xlo / kGroupW);
-            gx1 = (int)(xhi / kGroupW);
-            gy0 = (int)(ylo / kGroupH);
-            gy1 = (int)(yhi / kGroupH);
-        }
-        __syncthreads();   // the previous round's table and cursor reads are done
-        for (int v = 0; v < nv; ++v) {
-            const uint64_t a = __ballot(gx0 <= v), b = __ballot(gx1 >= v);
-            const uint64_t c = __ballot(gy0 <= v), d = __ballot(gy1 >= v);
-            if (lane == 0) {
-                if (v < G.ngx) { x_lo[v] = a; x_hi[v] = b; }
-                if (v < G.ngy) { y_lo[v] = c; y_hi[v] = d; }
-            }
-        }
-        __syncthreads();
-        const int gw = gx1 - gx0 + 1;
-        const int area = gw > 0 ? gw * (gy1 - gy0 + 1) : 0;
-        {
-            int gx = gx0, gy = gy0;
-            for (int k = 0; k < area; ++k) {
-                const uint64_t peers = x_lo[gx] & x_hi[gx] & y_lo[gy] & y_hi[gy];
-                const uint32_t pos = cursor[gy * G.ngx + gx] + rank_below(peers);
-                if (pos < cap) {
-                    // the rectangle clipped to this group's 8x8 tiles
-                    const uint32_t ox = (uint32_t)gx * kGroupW, oy = (uint32_t)gy * kGroupH;
-                    const uint32_t x0 = max(xlo, ox) - ox, x1 = min(xhi, ox + kGroupW - 1) - ox;
-                    const uint32_t y0 = max(ylo, oy) - oy, y1 = min(yhi, oy + kGroupH - 1) - oy;
-                    gval[pos] = item;
-                    gloc[pos] = (uint16_t)(x0 | (x1 << 3) | (y0 << 6) | (y1 << 9));
-                }
-                if (++gx > gx1) { gx = gx0; ++gy; }
-            }
-        }
-        __syncthreads();   // every lane has read the cursors of this round
-        {
-            int gx = gx0, gy = gy0;
-            for (int k = 0; k < area; ++k) {
-                const uint64_t peers = x_lo[gx] & x_hi[gx] & y_lo[gy] & y_hi[gy];
-                if (rank_below(peers) == 0) cursor[gy * G.ngx + gx] += (uint32_t)__popcll(peers);
-                if (++gx > gx1) { gx = gx0; ++gy; }
-            }
-        }
     }
 }
 
@@ -768,22 +688,16 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     if (chunks) {
         ProfScope _p("k_group_place", s);
-        const int ngx = (P.ntx + kGroupW - 1) / kGroupW, ngy = (P.nty + kGroupH - 1) / kGroupH;
-        if (g.C >= 1024 || chunks < 4096) {
-            // large batches (1024-item chunks) and small ones (fewer than 4096
-            // one-wave chunks, e.g. one 640 x 480 frame): one wave per (chunk,
-            // group row), runs of whole lines (1M x 16 frames: 622 -> 394 us;
-            // 100k x 1 frame: 13.8 -> 7.3 us); in between, one wave per chunk
-            // (200k x 8 frames: 27 against 30 us)
-            const int64_t items = (int64_t)P.F * g.QC * ngy;
-            const unsigned grid = (unsigned)((items < 16384 ? items : 16384) + 7) / 8 * 8;
-            hipLaunchKernelGGL(k_group_place_rows, dim3(grid), dim3(64), 4 * (size_t)ngx, s, P, g.C, g.QC,
-                               w.dval[dbuf], w.dkey[dbuf], w.drect[dbuf], w.cntA, w.granges, w.gval, w.gloc);
-        } else {
-            const size_t lds = 16 * (size_t)(ngx + ngy) + 4 * (size_t)g.ng;
-            hipLaunchKernelGGL(k_group_place, dim3(chunks), dim3(64), lds, s, P, g.C, g.QC, w.dval[dbuf],
-                               w.dkey[dbuf], w.drect[dbuf], w.cntA, w.granges, w.gval, w.gloc);
-        }
+        const int ngy = (P.nty + kGroupH - 1) / kGroupH, ngx = (P.ntx + kGroupW - 1) / kGroupW;
+        // runs of up to 512 items per wave while at least 8192 work items
+        // remain (200k x 8 frames: runs of 4 chunks of 128; one 640 x 480
+        // frame of 100k: 1 chunk; 1M x 16 frames: 1 chunk of 1024)
+        int RA = g.C >= 512 ? 1 : 512 / g.C;
+        while (RA > 1 && (int64_t)P.F * ((g.QC + RA - 1) / RA) * ngy < 8192) RA /= 2;
+        const int64_t items = (int64_t)P.F * ((g.QC + RA - 1) / RA) * ngy;
+        const unsigned grid = (unsigned)((items < 16384 ? items : 16384) + 7) / 8 * 8;
+        hipLaunchKernelGGL(k_group_place, dim3(grid), dim3(64), 4 * (size_t)ngx, s, P, g.C, g.QC, RA,
+                           w.dval[dbuf], w.dkey[dbuf], w.drect[dbuf], w.cntA, w.granges, w.gval, w.gloc);
     }
     // persistent level-B grids: every wave loops over segments (counting) or
     // over (chunk, tile row) work items (placing; a multiple of 8 workgroups,
