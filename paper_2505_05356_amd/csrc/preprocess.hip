@@ -152,11 +152,13 @@ __device__ Binned bin(const Gauss& G, const gftorf_frame& fr, const Params& P,
     if (ext > 0.0) {
         const double hx = ext * sqrt(b.S00);
         const double hy = ext * sqrt(b.S11);
-        const double tw = (double)P.tw, th = (double)P.th;
-        xlo = fmax(floor(((b.u - hx) + 0.5) / tw), 0.0);
-        xhi = fmin(floor(((b.u + hx) - 0.5) / tw), (double)(P.ntx - 1));
-        ylo = fmax(floor(((b.v - hy) + 0.5) / th), 0.0);
-        yhi = fmin(floor(((b.v + hy) - 0.5) / th), (double)(P.nty - 1));
+        // the tile sides are powers of two (8, 16, 32), so multiplying by
+        // their reciprocals is exact and equals the correctly rounded division
+        const double itw = 1.0 / (double)P.tw, ith = 1.0 / (double)P.th;
+        xlo = fmax(floor(((b.u - hx) + 0.5) * itw), 0.0);
+        xhi = fmin(floor(((b.u + hx) - 0.5) * itw), (double)(P.ntx - 1));
+        ylo = fmax(floor(((b.v - hy) + 0.5) * ith), 0.0);
+        yhi = fmin(floor(((b.v + hy) - 0.5) * ith), (double)(P.nty - 1));
     } else {
         xlo = 0.0; xhi = (double)(P.ntx - 1);
         ylo = 0.0; yhi = (double)(P.nty - 1);
