@@ -169,8 +169,11 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
             // Wave-synchronous LDS counter: every lane of the peer group reads
             // the counter, then its highest lane advances it.  LDS operations
             // of one wave complete in issue order and the volatile accesses
-            // keep the compiler from reordering them across iterations.
-            volatile uint32_t* wh = whist[wave];
+            // keep the compiler from reordering them across iterations; the
+            // pointer keeps its LDS address space, so they stay LDS
+            // instructions rather than generic (flat) ones.
+            volatile __attribute__((address_space(3))) uint32_t* wh =
+                (volatile __attribute__((address_space(3))) uint32_t*)whist[wave];
             uint32_t prev = 0;
             const bool valid = d < (uint32_t)kSortBuckets;
             if (valid) prev = wh[d];
