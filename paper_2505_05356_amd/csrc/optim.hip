@@ -1,6 +1,7 @@
 // Optimisation-step kernels around the rasterizer: L2 reconstruction loss,
 // fused Adam over several parameter groups, and device-side frame selection
 // so that a captured step graph can be replayed without host involvement.
+#include <cstdint>
 #include "block_scan.h"
 #include "common.h"
 
@@ -9,23 +10,40 @@ namespace gft {
 namespace {
 
 // L2 loss (paper Eq. 9, L2 part): grad = w * 2 (p - t) / count, loss += w * sum (p - t)^2 / count.
+// Grid (chunks, frames): a workgroup takes a strided share of one frame's
+// elements, so no element index is divided; VEC: 16-byte accesses (the
+// per-frame element count is a multiple of 4 and the arrays are aligned).
+template <bool VEC>
 __global__ void __launch_bounds__(256) k_l2_loss(const float* __restrict__ pred,
                                                  const float* __restrict__ targets,
                                                  const int32_t* __restrict__ frame_index,
                                                  int32_t n_frames, long long elems, float weight,
                                                  float* __restrict__ grad, float* __restrict__ loss) {
     __shared__ float red[4];
-    const long long total = (long long)n_frames * elems;
-    const float inv = 1.0f / (float)total;
+    const long long f = blockIdx.y;
+    const float inv = 1.0f / (float)((long long)n_frames * elems);
+    const float gs = weight * 2.0f * inv;
+    const long long sidx = frame_index ? (long long)frame_index[f] : f;
+    const float* pf = pred + f * elems;
+    const float* tf = targets + sidx * elems;
+    float* gf = grad + f * elems;
     float acc = 0.f;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const long long f = i / elems;
-        const long long e = i - f * elems;
-        const long long sidx = frame_index ? (long long)frame_index[f] : f;
-        const float r = pred[i] - targets[sidx * elems + e];
-        grad[i] = weight * 2.0f * r * inv;
-        acc += r * r;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    if constexpr (VEC) {
+        const long long n4 = elems >> 2;
+        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+            const float4 pv = reinterpret_cast<const float4*>(pf)[i];
+            const float4 tv = reinterpret_cast<const float4*>(tf)[i];
+            const float4 r = make_float4(pv.x - tv.x, pv.y - tv.y, pv.z - tv.z, pv.w - tv.w);
+            reinterpret_cast<float4*>(gf)[i] = make_float4(gs * r.x, gs * r.y, gs * r.z, gs * r.w);
+            acc += (r.x * r.x + r.y * r.y) + (r.z * r.z + r.w * r.w);
+        }
+    } else {
+        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < elems; i += stride) {
+            const float r = pf[i] - tf[i];
+            gf[i] = gs * r;
+            acc += r * r;
+        }
     }
     acc = wave_reduce_sum(acc);
     if (lane_id() == 0) red[threadIdx.x / 64] = acc;
@@ -34,12 +52,15 @@ __global__ void __launch_bounds__(256) k_l2_loss(const float* __restrict__ pred,
 }
 
 constexpr int kMaxGroups = 16;
+constexpr int kAdamChunk = 256 * 16;   // elements per workgroup: 4 float4 per thread
 struct AdamArgs {
     float* p[kMaxGroups];
     const float* g[kMaxGroups];
     float* m[kMaxGroups];
     float* v[kMaxGroups];
-    long long start[kMaxGroups + 1];
+    long long n[kMaxGroups];
+    int bstart[kMaxGroups + 1];   // first workgroup of each group
+    int vec[kMaxGroups];          // 1: the four arrays are 16-byte aligned
     float lr[kMaxGroups];
     float lr_final[kMaxGroups];
     int decay[kMaxGroups];
@@ -51,34 +72,59 @@ __global__ void k_step_increment(int32_t* step) {
     if (threadIdx.x == 0 && blockIdx.x == 0) step[0] += 1;
 }
 
+__device__ __forceinline__ float adam_one(float& p, float g, float& m, float& v, float b1, float b2, float ibc1,
+                                          float ibc2, float lr, float eps) {
+    m = b1 * m + (1.0f - b1) * g;
+    v = b2 * v + (1.0f - b2) * g * g;
+    p -= lr * (m * ibc1) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + eps);
+    return p;
+}
+
+// One workgroup per chunk of kAdamChunk consecutive elements of one group:
+// the group and its (possibly decayed) rate are uniform per workgroup, and
+// the bias corrections are multiplied in as reciprocals.
 __global__ void __launch_bounds__(256) k_adam(AdamArgs A, const int32_t* __restrict__ step) {
     const int t = *step;
-    const float bc1 = 1.0f - powf(A.b1, (float)t);
-    const float bc2 = 1.0f - powf(A.b2, (float)t);
-    const long long total = A.start[A.n_groups];
-    int lr_g = -1;   // group whose (possibly decayed) rate is in lr
-    float lr = 0.0f;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        int gi = 0;
-        while (i >= A.start[gi + 1]) ++gi;
-        if (gi != lr_g) {
-            lr_g = gi;
-            lr = A.lr[gi];
-            if (A.decay[gi] > 0) {
-                const float s = (float)min(t - 1, A.decay[gi]) / (float)A.decay[gi];
-                lr = A.lr[gi] * powf(A.lr_final[gi] / A.lr[gi], s);
-            }
+    const float ibc1 = 1.0f / (1.0f - powf(A.b1, (float)t));
+    const float ibc2 = 1.0f / (1.0f - powf(A.b2, (float)t));
+    int gi = 0;
+    while ((int)blockIdx.x >= A.bstart[gi + 1]) ++gi;
+    float lr = A.lr[gi];
+    if (A.decay[gi] > 0) {
+        const float s = (float)min(t - 1, A.decay[gi]) / (float)A.decay[gi];
+        lr = A.lr[gi] * powf(A.lr_final[gi] / A.lr[gi], s);
+    }
+    const long long n = A.n[gi];
+    const long long j0 = (long long)(blockIdx.x - A.bstart[gi]) * kAdamChunk;
+    float* P = A.p[gi];
+    const float* G = A.g[gi];
+    float* M = A.m[gi];
+    float* V = A.v[gi];
+    if (A.vec[gi] && j0 + kAdamChunk <= n) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long long j = j0 + 4 * ((long long)k * 256 + threadIdx.x);
+            float4 p = *reinterpret_cast<float4*>(P + j);
+            const float4 g = *reinterpret_cast<const float4*>(G + j);
+            float4 m = *reinterpret_cast<float4*>(M + j);
+            float4 v = *reinterpret_cast<float4*>(V + j);
+            adam_one(p.x, g.x, m.x, v.x, A.b1, A.b2, ibc1, ibc2, lr, A.eps);
+            adam_one(p.y, g.y, m.y, v.y, A.b1, A.b2, ibc1, ibc2, lr, A.eps);
+            adam_one(p.z, g.z, m.z, v.z, A.b1, A.b2, ibc1, ibc2, lr, A.eps);
+            adam_one(p.w, g.w, m.w, v.w, A.b1, A.b2, ibc1, ibc2, lr, A.eps);
+            *reinterpret_cast<float4*>(P + j) = p;
+            *reinterpret_cast<float4*>(M + j) = m;
+            *reinterpret_cast<float4*>(V + j) = v;
         }
-        const long long j = i - A.start[gi];
-        const float g = A.g[gi][j];
-        const float m = A.b1 * A.m[gi][j] + (1.0f - A.b1) * g;
-        const float v = A.b2 * A.v[gi][j] + (1.0f - A.b2) * g * g;
-        A.m[gi][j] = m;
-        A.v[gi][j] = v;
-        const float mh = m / bc1;
-        const float vh = v / bc2;
-        A.p[gi][j] -= lr * mh / (sqrtf(vh) + A.eps);
+    } else {
+        const long long j1 = min(j0 + (long long)kAdamChunk, n);
+        for (long long j = j0 + threadIdx.x; j < j1; j += 256) {
+            float p = P[j], m = M[j], v = V[j];
+            adam_one(p, G[j], m, v, A.b1, A.b2, ibc1, ibc2, lr, A.eps);
+            P[j] = p;
+            M[j] = m;
+            V[j] = v;
+        }
     }
 }
 
@@ -111,13 +157,20 @@ __global__ void k_select_frames(gftorf_frame* __restrict__ frames, int32_t n_bat
 void launch_l2_loss(const float* pred, const float* targets, const int32_t* frame_index,
                     int32_t n_frames, int64_t elems, float weight, float* grad, float* loss,
                     hipStream_t s) {
-    const long long total = (long long)n_frames * elems;
-    long long blocks = (total + 256 * 8 - 1) / (256 * 8);
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
+    if (n_frames <= 0 || elems <= 0) return;
+    const auto aligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+    const bool vec = (elems & 3) == 0 && aligned(pred) && aligned(targets) && aligned(grad);
+    long long per = vec ? elems / 4 : elems;
+    long long bx = (per + 256 * 4 - 1) / (256 * 4);   // about 4 accesses per thread
+    if (bx > 4096) bx = 4096;
+    const dim3 grid((unsigned)bx, (unsigned)n_frames);
     { ProfScope _p("k_l2_loss", s);
-    hipLaunchKernelGGL(k_l2_loss, dim3((unsigned)blocks), dim3(256), 0, s, pred, targets, frame_index,
-                       n_frames, (long long)elems, weight, grad, loss);
+    if (vec)
+        hipLaunchKernelGGL(k_l2_loss<true>, grid, dim3(256), 0, s, pred, targets, frame_index, n_frames,
+                           (long long)elems, weight, grad, loss);
+    else
+        hipLaunchKernelGGL(k_l2_loss<false>, grid, dim3(256), 0, s, pred, targets, frame_index, n_frames,
+                           (long long)elems, weight, grad, loss);
     }
 }
 
@@ -126,6 +179,7 @@ void launch_adam(const gftorf_adam_group* groups, int32_t n_groups, int32_t* ste
     { ProfScope _p("k_step_increment", s);
     hipLaunchKernelGGL(k_step_increment, dim3(1), dim3(64), 0, s, step);
     }
+    const auto aligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
     for (int base = 0; base < n_groups; base += kMaxGroups) {
         AdamArgs A{};
         const int ng = (n_groups - base) < kMaxGroups ? (n_groups - base) : kMaxGroups;
@@ -133,23 +187,24 @@ void launch_adam(const gftorf_adam_group* groups, int32_t n_groups, int32_t* ste
         A.b1 = b1;
         A.b2 = b2;
         A.eps = eps;
-        A.start[0] = 0;
+        A.bstart[0] = 0;
         for (int i = 0; i < ng; ++i) {
             const gftorf_adam_group& g = groups[base + i];
             A.p[i] = g.param;
             A.g[i] = g.grad;
             A.m[i] = g.m;
             A.v[i] = g.v;
+            A.n[i] = g.n;
+            A.vec[i] = aligned(g.param) && aligned(g.grad) && aligned(g.m) && aligned(g.v);
             A.lr[i] = g.lr;
             A.lr_final[i] = g.lr_final;
             A.decay[i] = g.decay_steps;
-            A.start[i + 1] = A.start[i] + g.n;
+            A.bstart[i + 1] = A.bstart[i] + (int)((g.n + kAdamChunk - 1) / kAdamChunk);
         }
-        long long blocks = (A.start[ng] + 256 * 4 - 1) / (256 * 4);
-        if (blocks > 8192) blocks = 8192;
-        if (blocks < 1) blocks = 1;
+        for (int i = ng; i < kMaxGroups; ++i) A.bstart[i + 1] = A.bstart[ng];
+        if (A.bstart[ng] == 0) continue;
         { ProfScope _p("k_adam", s);
-        hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, A, step);
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)A.bstart[ng]), dim3(256), 0, s, A, step);
         }
     }
 }
