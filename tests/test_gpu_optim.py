@@ -22,10 +22,11 @@ def _s():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def test_l2_loss_matches_oracle():
+@pytest.mark.parametrize("E", [4 * 33 * 29, 3 * 33 * 29 + 1])   # 16-byte path; one-float path
+def test_l2_loss_matches_oracle(E):
     lib = _lib.load()
     rng = np.random.default_rng(0)
-    F, S, E = 3, 7, 4 * 33 * 29
+    F, S = 3, 7
     pred = rng.normal(size=(F, E)).astype(np.float32)
     tgt = rng.normal(size=(S, E)).astype(np.float32)
     idx = np.array([5, 0, 3], np.int32)
@@ -42,32 +43,44 @@ def test_l2_loss_matches_oracle():
     np.testing.assert_allclose(grad.cpu().numpy(), ref_grad, rtol=1e-5, atol=1e-12)
 
 
+def _offset(n, misalign):
+    """A zeroed device vector of n floats, 4 bytes past a 16-byte boundary
+    when misalign is set (the kernel then takes its one-float path)."""
+    return torch.zeros(n + 1, device="cuda")[1:] if misalign else torch.zeros(n, device="cuda")
+
+
 def test_adam_matches_oracle():
     # Adam isolated from gradient noise: the GPU update equals FP64 Adam
-    # applied to the same gradients (two steps, two groups).
+    # applied to the same gradients (two steps, three groups: whole 4096-element
+    # chunks with a ragged tail, a group shorter than a chunk, and a group of
+    # several chunks whose arrays are not 16-byte aligned)
     lib = _lib.load()
     rng = np.random.default_rng(1)
-    sizes, lrs = (1000, 37), (1e-3, 1.6e-4)
+    sizes, lrs, misalign = (10003, 37, 9000), (1e-3, 1.6e-4, 5e-4), (False, False, True)
+    G = len(sizes)
     p = [rng.normal(size=n).astype(np.float32) for n in sizes]
     gs = [[rng.normal(size=n).astype(np.float32) * 1e-2 for n in sizes] for _ in range(2)]
-    dp = [torch.from_numpy(a.copy()).cuda() for a in p]
-    dm = [torch.zeros(n, device="cuda") for n in sizes]
-    dv = [torch.zeros(n, device="cuda") for n in sizes]
-    dg = [torch.empty(n, device="cuda") for n in sizes]
+    dp = [_offset(n, ma) for n, ma in zip(sizes, misalign)]
+    for i in range(G):
+        dp[i].copy_(torch.from_numpy(p[i]))
+    dm = [_offset(n, ma) for n, ma in zip(sizes, misalign)]
+    dv = [_offset(n, ma) for n, ma in zip(sizes, misalign)]
+    dg = [_offset(n, ma) for n, ma in zip(sizes, misalign)]
+    assert dp[2].data_ptr() % 16 != 0 and dp[0].data_ptr() % 16 == 0
     step = torch.zeros(1, dtype=torch.int32, device="cuda")
-    groups = (_lib.AdamGroupC * 2)()
-    for i in range(2):
+    groups = (_lib.AdamGroupC * G)()
+    for i in range(G):
         groups[i].param, groups[i].grad = dp[i].data_ptr(), dg[i].data_ptr()
         groups[i].m, groups[i].v = dm[i].data_ptr(), dv[i].data_ptr()
         groups[i].n, groups[i].lr = sizes[i], lrs[i]
     ref = [(a.astype(np.float64), np.zeros(len(a)), np.zeros(len(a))) for a in p]
     for t in range(2):
-        for i in range(2):
+        for i in range(G):
             dg[i].copy_(torch.from_numpy(gs[t][i]))
-        _lib.check(lib.gftorf_adam_step(groups, 2, _p(step), 0.9, 0.999, 1e-15, _s()))
+        _lib.check(lib.gftorf_adam_step(groups, G, _p(step), 0.9, 0.999, 1e-15, _s()))
         ref = [ooptim.adam_step(r[0], gs[t][i], r[1], r[2], t + 1, lrs[i]) for i, r in enumerate(ref)]
         torch.cuda.synchronize()
-        for i in range(2):
+        for i in range(G):
             # the parameters live in float32, so every step rounds them by up
             # to half a unit in the last place: the measured update carries
             # (t + 1) / 2 ulp(p) beyond the float32 arithmetic of the update
