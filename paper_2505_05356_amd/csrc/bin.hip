@@ -665,6 +665,15 @@ BinGeom bin_geometry(int64_t n, int32_t n_frames, int ntx, int nty, uint64_t cap
     return g;
 }
 
+// Grid caps of the one-wave placing and counting kernels.  Their waves wait
+// on loads most of the time, so a grid of several times the 8192 resident
+// waves (32 per CU) keeps the chip busier than a resident-sized one: level A
+// gets one wave per work item up to 128K items (1M x 16 frames: 94K); the
+// level-B grids are sized from an upper bound on the segments, so their cap
+// also bounds the waves that find no work.
+constexpr int64_t kPlaceGridA = 131072;
+constexpr int64_t kLevelBGrid = 32768;
+
 hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStream_t s) {
     const BinGeom g = bin_geometry(P.n, P.F, P.ntx, P.nty, P.cap);
     const int K = P.F * g.ng;
@@ -695,16 +704,16 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
         int RA = g.C >= 512 ? 1 : 512 / g.C;
         while (RA > 1 && (int64_t)P.F * ((g.QC + RA - 1) / RA) * ngy < 8192) RA /= 2;
         const int64_t items = (int64_t)P.F * ((g.QC + RA - 1) / RA) * ngy;
-        const unsigned grid = (unsigned)((items < 16384 ? items : 16384) + 7) / 8 * 8;
+        const unsigned grid = (unsigned)((items < kPlaceGridA ? items : kPlaceGridA) + 7) / 8 * 8;
         hipLaunchKernelGGL(k_group_place, dim3(grid), dim3(64), 4 * (size_t)ngx, s, P, g.C, g.QC, RA,
                            w.dval[dbuf], w.dkey[dbuf], w.drect[dbuf], w.cntA, w.granges, w.gval, w.gloc);
     }
     // persistent level-B grids: every wave loops over segments (counting) or
     // over (chunk, tile row) work items (placing; a multiple of 8 workgroups,
     // as its split of the work items over the XCDs needs)
-    const unsigned segs = (unsigned)(g.max_segments < 16384 ? g.max_segments : 16384);
+    const unsigned segs = (unsigned)(g.max_segments < kLevelBGrid ? g.max_segments : kLevelBGrid);
     const int64_t max_items = ((g.max_segments + g.R - 1) / g.R + K) * kGroupH;
-    const unsigned place_grid = (unsigned)((max_items < 16384 ? max_items : 16384) + 7) / 8 * 8;
+    const unsigned place_grid = (unsigned)((max_items < kLevelBGrid ? max_items : kLevelBGrid) + 7) / 8 * 8;
     {
         ProfScope _p("k_tile_count", s);
         hipLaunchKernelGGL(k_tile_count, dim3(segs), dim3(64), 0, s, P, g.S, w.seg_start, w.granges,
