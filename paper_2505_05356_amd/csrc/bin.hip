@@ -424,32 +424,38 @@ __device__ __forceinline__ void place_batch(uint32_t row, uint32_t item, uint32_
 }
 
 // The entries [beg, end) of a group list, 64 at a time, appended to the
-// lists of the group's tile row r; the next batch's entries are loaded while
-// this batch is placed.
+// lists of the group's tile row r.  The entries are loaded kRowBatches
+// batches at a time, all loads in flight before the first batch is placed
+// (a work item is at most R * S = kRowBatches * 64 entries), so a wave waits
+// for its loads once per work item rather than once per batch.
+constexpr int kRowBatches = 16;
+
 template <bool FAST>
 __device__ __forceinline__ void place_row(uint32_t beg, uint32_t end, uint32_t r, int lane, uint32_t (&cur)[kGroupW],
                                           uint32_t ncol, uint32_t cap, const uint32_t* __restrict__ gval,
                                           const uint16_t* __restrict__ gloc, uint32_t* __restrict__ tval) {
-    uint32_t nitem = 0, nloc = 0;
-    bool nvalid = beg + lane < end;
-    if (nvalid) {
-        nitem = gval[beg + lane];
-        nloc = gloc[beg + lane];
-    }
-    for (uint32_t j0 = beg; j0 < end; j0 += 64) {
-        const uint32_t item = nitem;
-        uint32_t row = 0;   // bit c: the entry covers tile (c, r) of the group
-        if (nvalid) {
-            const LocalRect lr = local_rect(nloc);
-            if (lr.y0 <= r && r <= lr.y1) row = ((2u << lr.x1) - (1u << lr.x0)) & 0xffu;
+    for (uint32_t j0 = beg; j0 < end; j0 += 64 * kRowBatches) {
+        uint32_t item[kRowBatches], loc[kRowBatches];
+#pragma unroll
+        for (int b = 0; b < kRowBatches; ++b) {
+            const uint32_t j = j0 + 64 * b + lane;
+            item[b] = 0;
+            loc[b] = 0;
+            if (j < end) {
+                item[b] = gval[j];
+                loc[b] = gloc[j];
+            }
         }
-        const uint32_t jn = j0 + 64 + lane;
-        nvalid = jn < end;
-        if (nvalid) {
-            nitem = gval[jn];
-            nloc = gloc[jn];
+#pragma unroll
+        for (int b = 0; b < kRowBatches; ++b) {
+            if (j0 + 64 * b >= end) break;   // wave-uniform
+            uint32_t row = 0;   // bit c: the entry covers tile (c, r) of the group
+            if (j0 + 64 * b + lane < end) {
+                const LocalRect lr = local_rect(loc[b]);
+                if (lr.y0 <= r && r <= lr.y1) row = ((2u << lr.x1) - (1u << lr.x0)) & 0xffu;
+            }
+            place_batch<FAST>(row, item[b], cur, ncol, cap, tval);
         }
-        place_batch<FAST>(row, item, cur, ncol, cap, tval);
     }
 }
 
