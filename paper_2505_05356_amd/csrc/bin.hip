@@ -151,8 +151,10 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t peers) {
 // ranges are clamped to it), so the stores need no check.  REG: the row has
 // at most kGroupW groups, whose cursors stay in scalar registers under an
 // unrolled, branch-free column loop (an empty ballot stores nothing);
-// otherwise they live in LDS.
-template <bool FAST, bool REG>
+// otherwise they live in LDS.  NB: runs of at least 16 batches load 8
+// batches at a time (fewer waits per run); shorter runs load each batch
+// while the previous one is placed (measured faster there).
+template <bool FAST, bool REG, int NB>
 __device__ __forceinline__ void place_group_row(const Groups& G, long long beg, long long end, uint32_t gy, int lane,
                                                 uint32_t* cursor, uint32_t (&cur)[kGroupW], uint32_t cap,
                                                 const uint32_t* __restrict__ dval,
@@ -160,32 +162,16 @@ __device__ __forceinline__ void place_group_row(const Groups& G, long long beg, 
                                                 const uint2* __restrict__ drect,
                                                 uint32_t* __restrict__ gval, uint16_t* __restrict__ gloc) {
     const uint32_t oy = gy * kGroupH;
-    // the next batch's key, item and rectangle are loaded while this batch
-    // is placed
-    uint32_t nkey = kCulledKey, nitem = 0;
-    uint2 nrect = make_uint2(0u, 0u);
-    if (beg + lane < end) {
-        nkey = dkey[beg + lane];
-        nitem = dval[beg + lane];
-        nrect = drect[beg + lane];
-    }
-    for (long long j0 = beg; j0 < end; j0 += 64) {
+    // one batch: lane = item, covering the groups gx0 .. gx1 of the row
+    auto place_batch_a = [&](uint32_t key, uint32_t item, uint2 rect) {
         int gx0 = 1, gx1 = 0;   // empty: never in a ballot
         uint32_t xlo = 0, xhi = 0, ylo = 0, yhi = 0;
-        const uint32_t item = nitem;
-        if (nkey != kCulledKey) {
-            unpack_rect(nrect, xlo, xhi, ylo, yhi);
+        if (key != kCulledKey) {
+            unpack_rect(rect, xlo, xhi, ylo, yhi);
             if (ylo / kGroupH <= gy && gy <= yhi / kGroupH) {
                 gx0 = (int)(xlo / kGroupW);
                 gx1 = (int)(xhi / kGroupW);
             }
-        }
-        const long long jn = j0 + 64 + lane;
-        nkey = kCulledKey;
-        if (jn < end) {
-            nkey = dkey[jn];
-            nitem = dval[jn];
-            nrect = drect[jn];
         }
         // the rows of the rectangle clipped to this group row
         const uint32_t y0 = max(ylo, oy) - oy, y1 = min(yhi, oy + kGroupH - 1) - oy;
@@ -222,9 +208,57 @@ __device__ __forceinline__ void place_group_row(const Groups& G, long long beg, 
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
+    };
+    if constexpr (NB == 1) {
+        // the next batch's key, item and rectangle are loaded while this
+        // batch is placed
+        uint32_t nkey = kCulledKey, nitem = 0;
+        uint2 nrect = make_uint2(0u, 0u);
+        if (beg + lane < end) {
+            nkey = dkey[beg + lane];
+            nitem = dval[beg + lane];
+            nrect = drect[beg + lane];
+        }
+        for (long long j0 = beg; j0 < end; j0 += 64) {
+            const uint32_t key = nkey, item = nitem;
+            const uint2 rect = nrect;
+            const long long jn = j0 + 64 + lane;
+            nkey = kCulledKey;
+            if (jn < end) {
+                nkey = dkey[jn];
+                nitem = dval[jn];
+                nrect = drect[jn];
+            }
+            place_batch_a(key, item, rect);
+        }
+    } else {
+        // NB batches at a time, all their loads in flight before the first
+        // of them is placed
+        for (long long r0 = beg; r0 < end; r0 += 64 * NB) {
+            uint32_t bkey[NB], bitem[NB];
+            uint2 brect[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const long long j = r0 + 64 * b + lane;
+                bkey[b] = kCulledKey;
+                bitem[b] = 0;
+                brect[b] = make_uint2(0u, 0u);
+                if (j < end) {
+                    bkey[b] = dkey[j];
+                    bitem[b] = dval[j];
+                    brect[b] = drect[j];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (r0 + 64 * b >= end) break;   // wave-uniform
+                place_batch_a(bkey[b], bitem[b], brect[b]);
+            }
+        }
     }
 }
 
+template <int NB>
 __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC, int RA,
                                                          const uint32_t* __restrict__ dval,
                                                          const uint32_t* __restrict__ dkey,
@@ -268,9 +302,9 @@ __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC, int
 #pragma unroll
             for (int c = 0; c < kGroupW; ++c) cur[c] = (uint32_t)__builtin_amdgcn_readlane((int)cl, c);
             if (__ballot(el >= cap) == 0ull)
-                place_group_row<true, true>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
+                place_group_row<true, true, NB>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
             else
-                place_group_row<false, true>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
+                place_group_row<false, true, NB>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
             continue;
         }
         __syncthreads();   // the previous work item's cursor reads are done
@@ -281,9 +315,9 @@ __global__ void __launch_bounds__(64) k_group_place(Params P, int C, int QC, int
         }
         __syncthreads();
         if (__ballot(el >= cap) == 0ull)
-            place_group_row<true, false>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
+            place_group_row<true, false, NB>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
         else
-            place_group_row<false, false>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
+            place_group_row<false, false, NB>(G, beg, end, gy, lane, cursor, cur, cap, dval, dkey, drect, gval, gloc);
     }
 }
 
@@ -711,8 +745,12 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
         while (RA > 1 && (int64_t)P.F * ((g.QC + RA - 1) / RA) * ngy < 8192) RA /= 2;
         const int64_t items = (int64_t)P.F * ((g.QC + RA - 1) / RA) * ngy;
         const unsigned grid = (unsigned)((items < kPlaceGridA ? items : kPlaceGridA) + 7) / 8 * 8;
-        hipLaunchKernelGGL(k_group_place, dim3(grid), dim3(64), 4 * (size_t)ngx, s, P, g.C, g.QC, RA,
-                           w.dval[dbuf], w.dkey[dbuf], w.drect[dbuf], w.cntA, w.granges, w.gval, w.gloc);
+        if ((int64_t)RA * g.C >= 1024)
+            hipLaunchKernelGGL(k_group_place<8>, dim3(grid), dim3(64), 4 * (size_t)ngx, s, P, g.C, g.QC, RA,
+                               w.dval[dbuf], w.dkey[dbuf], w.drect[dbuf], w.cntA, w.granges, w.gval, w.gloc);
+        else
+            hipLaunchKernelGGL(k_group_place<1>, dim3(grid), dim3(64), 4 * (size_t)ngx, s, P, g.C, g.QC, RA,
+                               w.dval[dbuf], w.dkey[dbuf], w.drect[dbuf], w.cntA, w.granges, w.gval, w.gloc);
     }
     // persistent level-B grids: every wave loops over segments (counting) or
     // over (chunk, tile row) work items (placing; a multiple of 8 workgroups,
