@@ -116,6 +116,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
     __shared__ uint32_t digit_base[kSortBuckets];
     __shared__ uint32_t whist[4][kSortBuckets];
     __shared__ uint32_t tile_start[kSortBuckets];
+    __shared__ uint32_t out_base[kSortBuckets];
     __shared__ uint32_t skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
     __shared__ uint2 srect[kSortTile];
@@ -140,6 +141,9 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
             cur_f = st.f;
         }
         for (int i = lane; i < kSortBuckets; i += 64) whist[wave][i] = 0;
+        // this tile's offset of digit `tid` among the frame's keys of that
+        // digit, loaded now so the load overlaps the ranking
+        const uint32_t tile_off = counts[(st.f * kSortBuckets + tid) * tpf + st.t];
         uint32_t k[kSortItems], v[kSortItems], rank[kSortItems];
         uint2 rc[kSortItems];
         const long long wbase = st.beg + (long long)wave * (kSortItems * 64);
@@ -192,6 +196,9 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
             uint32_t tot;
             uint32_t ex = block_exclusive_scan<uint32_t, kSortThreads>(s, scratch, &tot);
             tile_start[d] = ex;
+            // output position of the tile's element j of digit d, minus j
+            // (mod 2^32: the true position is below n)
+            out_base[d] = digit_base[d] + tile_off - ex;
         }
         __syncthreads();
 #pragma unroll
@@ -205,17 +212,21 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_downsweep(
             }
         }
         __syncthreads();
+        // scatter: no global loads here, so the stores of all kSortItems
+        // rounds issue back to back
         const int valid_n = (int)(st.end - st.beg);
         const long long fbase = st.f * n;
-        for (int j = tid; j < valid_n; j += kSortThreads) {
-            const uint32_t key = skey[j];
-            const uint32_t val = sval[j];
-            const uint32_t d = (key >> shift) & 0xffu;
-            const long long gpos = fbase + (long long)digit_base[d] +
-                                   counts[(st.f * kSortBuckets + d) * tpf + st.t] + (j - tile_start[d]);
-            kout[gpos] = key;
-            vout[gpos] = val;
-            rout[gpos] = srect[j];
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            const int j = tid + it * kSortThreads;
+            if (j < valid_n) {
+                const uint32_t key = skey[j];
+                const uint32_t d = (key >> shift) & 0xffu;
+                const long long gpos = fbase + (long long)(uint32_t)(out_base[d] + (uint32_t)j);
+                kout[gpos] = key;
+                vout[gpos] = sval[j];
+                rout[gpos] = srect[j];
+            }
         }
         __syncthreads();
     }
