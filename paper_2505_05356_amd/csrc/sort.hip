@@ -256,7 +256,10 @@ unsigned grid_for(long long items, long long per_block, unsigned cap_blocks) {
 void radix_pass(const uint32_t* kin, const uint32_t* vin, const uint2* rin, uint32_t* kout, uint32_t* vout,
                 uint2* rout, long long n, int F, int shift, const Workspace& w, hipStream_t s) {
     const long long tpf = w.max_sort_tiles;
-    const unsigned g = grid_for((long long)F * tpf, 1, 4096);
+    // one workgroup per sort tile up to 16K tiles (33.5M keys): the
+    // downsweep measured 5% faster so than with half as many workgroups
+    // looping over two tiles each (16M keys)
+    const unsigned g = grid_for((long long)F * tpf, 1, 16384);
     {
         ProfScope _p("k_sort_upsweep", s);
         hipLaunchKernelGGL(k_sort_upsweep, dim3(g), dim3(kSortThreads), 0, s, kin, n, F, tpf, shift,
