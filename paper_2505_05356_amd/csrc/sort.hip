@@ -257,7 +257,7 @@ void radix_pass(const uint32_t* kin, const uint32_t* vin, const uint2* rin, uint
                 uint2* rout, long long n, int F, int shift, const Workspace& w, hipStream_t s) {
     const long long tpf = w.max_sort_tiles;
     // one workgroup per sort tile up to 16K tiles (33.5M keys): the
-    // downsweep measured 5% faster so than with half as many workgroups
+    // downsweep measured 5% faster than with half as many workgroups
     // looping over two tiles each (16M keys)
     const unsigned g = grid_for((long long)F * tpf, 1, 16384);
     {
