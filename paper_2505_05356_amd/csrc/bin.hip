@@ -85,14 +85,27 @@ __global__ void __launch_bounds__(256) k_group_colscan(Params P, int QC, uint32_
     const int per = (QC + 255) / 256;
     const int q0 = min((int)threadIdx.x * per, QC), q1 = min(q0 + per, QC);
     uint32_t* col = cntA + (size_t)f * QC * G.ng + gi;
+    // 8 loads in flight per round (a thread's run is 4-8 chunks at 1.6M-16M
+    // items)
     uint32_t s = 0;
-    for (int q = q0; q < q1; ++q) s += col[(size_t)q * G.ng];
+    for (int q = q0; q < q1; q += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = q + i < q1 ? col[(size_t)(q + i) * G.ng] : 0u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += v[i];
+    }
     uint32_t total;
     uint32_t run = block_exclusive_scan<uint32_t, 256>(s, scratch, &total);
-    for (int q = q0; q < q1; ++q) {
-        const uint32_t v = col[(size_t)q * G.ng];
-        col[(size_t)q * G.ng] = run;
-        run += v;
+    for (int q = q0; q < q1; q += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = q + i < q1 ? col[(size_t)(q + i) * G.ng] : 0u;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (q + i < q1) col[(size_t)(q + i) * G.ng] = run;
+            run += v[i];
+        }
     }
     if (threadIdx.x == 0) lenA[(size_t)f * G.ng + gi] = total;
 }
@@ -554,13 +567,15 @@ __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, int R,
     }
 }
 
-// One workgroup of 4 waves per (frame, group): exclusive scan of each lane's
-// tile column over the group's segments (each wave a quarter of them, then a
-// prefix over the waves); per-tile totals.
-__global__ void __launch_bounds__(256) k_tile_colscan(Params P, const uint32_t* __restrict__ seg_start,
+// One workgroup of kColWaves waves per (frame, group): exclusive scan of each
+// lane's tile column over the group's segments (each wave a share of them,
+// then a prefix over the waves); per-tile totals.
+constexpr int kColWaves = 8;
+
+__global__ void __launch_bounds__(64 * kColWaves) k_tile_colscan(Params P, const uint32_t* __restrict__ seg_start,
                                                       uint32_t* __restrict__ cntB,
                                                       uint32_t* __restrict__ tcount) {
-    __shared__ uint32_t part[4][64];
+    __shared__ uint32_t part[kColWaves][64];
     const Groups G = groups_of(P);
     const int fg = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -568,7 +583,7 @@ __global__ void __launch_bounds__(256) k_tile_colscan(Params P, const uint32_t* 
     const uint32_t gy = gi / G.ngx, gx = gi - gy * G.ngx;
     const uint32_t tx = gx * kGroupW + lane % kGroupW, ty = gy * kGroupH + lane / kGroupW;
     const uint32_t s0 = seg_start[fg], s1 = seg_start[fg + 1];
-    const uint32_t per = (s1 - s0 + 3) / 4;
+    const uint32_t per = (s1 - s0 + kColWaves - 1) / kColWaves;
     const uint32_t b0 = min(s0 + wave * per, s1), b1 = min(b0 + per, s1);
     uint32_t sum = 0;
     uint32_t b = b0;
@@ -584,7 +599,7 @@ __global__ void __launch_bounds__(256) k_tile_colscan(Params P, const uint32_t* 
     __syncthreads();
     uint32_t run = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
+    for (int w = 0; w < kColWaves; ++w) {
         run += w < wave ? part[w][lane] : 0u;
         total += part[w][lane];
     }
@@ -768,7 +783,7 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     {
         ProfScope _p("k_tile_colscan", s);
-        hipLaunchKernelGGL(k_tile_colscan, dim3(K), dim3(256), 0, s, P, w.seg_start, w.cntB, w.tcount);
+        hipLaunchKernelGGL(k_tile_colscan, dim3(K), dim3(64 * kColWaves), 0, s, P, w.seg_start, w.cntB, w.tcount);
     }
     {
         ProfScope _p("k_tile_keyscan", s);
