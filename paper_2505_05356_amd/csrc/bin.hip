@@ -49,29 +49,42 @@ __device__ __forceinline__ Groups groups_of(const Params& P) {
 
 // ---- level A: items -> groups ----------------------------------------------
 
-__global__ void __launch_bounds__(256) k_group_count(Params P, int C, int QC,
+// Group counts of each chunk of C items: one workgroup of 256 threads per CPW
+// chunks (CPW = 512 / C, between 1 and 4, so that every thread counts two or
+// more items and short chunks do not each pay a workgroup launch).
+constexpr int kMaxChunksPerBlock = 4;
+
+__global__ void __launch_bounds__(256) k_group_count(Params P, int C, int QC, int CPW,
                                                      const uint32_t* __restrict__ dkey,
                                                      const uint2* __restrict__ drect,
                                                      uint32_t* __restrict__ cntA) {
-    __shared__ uint32_t lcnt[kMaxGroupsPerFrame];
+    __shared__ uint32_t lcnt[kMaxChunksPerBlock][kMaxGroupsPerFrame];
     const Groups G = groups_of(P);
-    const int chunk = blockIdx.x;
-    const int f = chunk / QC, q = chunk - f * QC;
-    for (int t = threadIdx.x; t < G.ng; t += 256) lcnt[t] = 0;
+    const int TPC = 256 / CPW;   // threads per chunk
+    const int sub = (int)threadIdx.x / TPC, lt = (int)threadIdx.x - sub * TPC;
+    const int chunk = blockIdx.x * CPW + sub;
+    const bool have = chunk < P.F * QC;
+    uint32_t* cnt = lcnt[sub];
+    for (int t = lt; t < G.ng; t += TPC) cnt[t] = 0;
     __syncthreads();
-    const long long beg = (long long)f * P.n + (long long)q * C;
-    const long long end = min(beg + C, (long long)(f + 1) * P.n);
-    for (long long j = beg + threadIdx.x; j < end; j += 256) {
-        if (dkey[j] == kCulledKey) continue;
-        uint32_t xlo, xhi, ylo, yhi;
-        unpack_rect(drect[j], xlo, xhi, ylo, yhi);
-        for (uint32_t gy = ylo / kGroupH; gy <= yhi / kGroupH; ++gy)
-            for (uint32_t gx = xlo / kGroupW; gx <= xhi / kGroupW; ++gx)
-                atomicAdd(&lcnt[gy * G.ngx + gx], 1u);
+    if (have) {
+        const int f = chunk / QC, q = chunk - f * QC;
+        const long long beg = (long long)f * P.n + (long long)q * C;
+        const long long end = min(beg + C, (long long)(f + 1) * P.n);
+        for (long long j = beg + lt; j < end; j += TPC) {
+            if (dkey[j] == kCulledKey) continue;
+            uint32_t xlo, xhi, ylo, yhi;
+            unpack_rect(drect[j], xlo, xhi, ylo, yhi);
+            for (uint32_t gy = ylo / kGroupH; gy <= yhi / kGroupH; ++gy)
+                for (uint32_t gx = xlo / kGroupW; gx <= xhi / kGroupW; ++gx)
+                    atomicAdd(&cnt[gy * G.ngx + gx], 1u);
+        }
     }
     __syncthreads();
-    uint32_t* out = cntA + (size_t)chunk * G.ng;
-    for (int t = threadIdx.x; t < G.ng; t += 256) out[t] = lcnt[t];
+    if (have) {
+        uint32_t* out = cntA + (size_t)chunk * G.ng;
+        for (int t = lt; t < G.ng; t += TPC) out[t] = cnt[t];
+    }
 }
 
 // grid (ng, F), 256 threads: one workgroup per (frame, group) column.
@@ -738,8 +751,9 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     const unsigned chunks = (unsigned)(P.F * g.QC);
     if (chunks) {
         ProfScope _p("k_group_count", s);
-        hipLaunchKernelGGL(k_group_count, dim3(chunks), dim3(256), 0, s, P, g.C, g.QC, w.dkey[dbuf],
-                           w.drect[dbuf], w.cntA);
+        const int cpw = g.C >= 512 ? 1 : (g.C >= 256 ? 2 : 4);   // 512 / C in [1, 4]
+        hipLaunchKernelGGL(k_group_count, dim3((chunks + cpw - 1) / cpw), dim3(256), 0, s, P, g.C, g.QC, cpw,
+                           w.dkey[dbuf], w.drect[dbuf], w.cntA);
     }
     if (chunks) {
         ProfScope _p("k_group_colscan", s);

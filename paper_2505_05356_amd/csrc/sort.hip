@@ -43,7 +43,9 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_upsweep(const uint32_t* _
     __shared__ uint32_t hist[4][kSortBuckets];
     const long long ntiles = (long long)F * tpf;
     const int wave = threadIdx.x / 64;
-    for (long long g = blockIdx.x; g < ntiles; g += gridDim.x) {
+    // consecutive tiles write neighbouring counts of every digit row: one XCD
+    const long long g0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    for (long long g = g0; g < ntiles; g += gridDim.x) {
         const SortTile st = sort_tile(g, n, tpf);
         for (int i = threadIdx.x; i < 4 * kSortBuckets; i += kSortThreads) (&hist[0][0])[i] = 0;
         // a histogram needs no element order: each thread loads its 8 keys
