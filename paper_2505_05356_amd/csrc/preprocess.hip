@@ -329,11 +329,21 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
 #pragma unroll
     for (int i = 0; i < kNG; ++i) acc[i] = 0.f;
     // spherical-harmonic coefficient gradients: colour [l][c] at 3 l + c,
-    // reflectivity [l] at 3 kMaxSH + l
-    constexpr int NSH = SH ? 4 * kMaxSH : 1;
+    // reflectivity [l] at 3 kMaxSH + l.  With fewer than 64 lanes per
+    // Gaussian every lane has at most one frame (GS is the smallest power of
+    // two >= F), so a lane keeps only that frame's basis values and upstream
+    // factors, and the products are formed and summed over the group one at
+    // a time after the frame loop; otherwise each lane accumulates them over
+    // its frames.
+    constexpr bool kOneFrame = GS < 64;
+    constexpr int NSH = SH && !kOneFrame ? 4 * kMaxSH : 1;
     float ash[NSH];
 #pragma unroll
     for (int i = 0; i < NSH; ++i) ash[i] = 0.f;
+    constexpr int NY = SH && kOneFrame ? kMaxSH : 1;
+    float ysv[NY], tcv[3] = {0.f, 0.f, 0.f}, trv = 0.f;
+#pragma unroll
+    for (int l = 0; l < NY; ++l) ysv[l] = 0.f;
     const int K = sh_count(g.sh_degree);
     if (have) {
         auto ld = [&](const float* p, int64_t i) { return p ? p[i] : 0.0f; };
@@ -483,14 +493,21 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             const float tc = gr[6 + c] * act_c[c];
-                            ash[3 * l + c] += Y[l] * tc;
+                            if constexpr (!kOneFrame) ash[3 * l + c] += Y[l] * tc;
                             w[l] += kr(l, c) * tc;
                         }
                     if (g.sh_albedo) {
                         const float tr = galb * act_r;
-                        ash[3 * kMaxSH + l] += Y[l] * tr;
+                        if constexpr (!kOneFrame) ash[3 * kMaxSH + l] += Y[l] * tr;
                         w[l] += ka(l) * tr;
                     }
+                }
+                if constexpr (kOneFrame) {
+#pragma unroll
+                    for (int l = 0; l < kMaxSH; ++l) ysv[l] = Y[l];
+                    if (g.sh_rgb)
+                        for (int c = 0; c < 3; ++c) tcv[c] = gr[6 + c] * act_c[c];
+                    if (g.sh_albedo) trv = galb * act_r;
                 }
                 // direction = e / d: dL/de = (I - dir dir^T) dL/ddir / d
                 float gdir[3];
@@ -598,12 +615,26 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(Params P, gftorf_gaussia
     }
 #pragma unroll
     for (int i = 0; i < kNG - 1; ++i) acc[i] = group_sum<GS>(acc[i]);
-    if constexpr (SH) {
+    if constexpr (SH && kOneFrame) {
+        // the group's sum of each product, stored by the group's first lane
+        const bool store = have && f0 == 0;
+#pragma unroll
+        for (int l = 0; l < kMaxSH; ++l) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float v = group_sum<GS>(ysv[l] * tcv[c]);
+                if (store && l < K && out.sh_rgb) out.sh_rgb[((int64_t)l * 3 + c) * n + k] = v;
+            }
+            const float v = group_sum<GS>(ysv[l] * trv);
+            if (store && l < K && out.sh_albedo) out.sh_albedo[(int64_t)l * n + k] = v;
+        }
+    }
+    if constexpr (SH && !kOneFrame) {
 #pragma unroll
         for (int i = 0; i < NSH; ++i) ash[i] = group_sum<GS>(ash[i]);
     }
     if (!have || f0 != 0) return;
-    if constexpr (SH) {
+    if constexpr (SH && !kOneFrame) {
 #pragma unroll
         for (int l = 0; l < kMaxSH; ++l) {
             if (l >= K) continue;
