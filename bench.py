@@ -55,20 +55,20 @@ COMPOSITE_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_
 BIN_FILES = ("paper_2505_05356_amd/csrc/bin.hip", "paper_2505_05356_amd/csrc/common.h")
 MLP_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
 _COMPOSITE_SHA = "00c0986837c56de4efd0f3e9aec1d2328c9cce34094f5deb57a74fd8f8b13688"
-_BIN_SHA = "a2a972e7d73d39620bc25b9d0a9ef47eaab2d305858ca1e1c0651e9ad2c3c5bd"
+_BIN_SHA = "de418f93f524f0c79575f4fd18061db74e9ff742c4ede0ee9ee7582038dca0bb"
 # {workload: {kernel: (source files, sha256, (FETCH KiB, WRITE KiB) per launch)}};
 # k_mlp_dw counts its three launches together
 TRAFFIC = {
     "dynamic-200k-gaussians-8f-640x480": {
         "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (52202, 50919)),
-        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (5291, 96150)),
-        "k_tile_place": (BIN_FILES, _BIN_SHA, (9696, 159184)),
-        "k_group_place": (BIN_FILES, _BIN_SHA, (12840, 18555))},
+        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (5288, 96164)),
+        "k_tile_place": (BIN_FILES, _BIN_SHA, (9249, 154070)),
+        "k_group_place": (BIN_FILES, _BIN_SHA, (12841, 18420))},
     "dynamic-1000k-1024x768-16f-2freq": {
-        "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (361223, 247936)),
-        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (19684, 690600)),
-        "k_tile_place": (BIN_FILES, _BIN_SHA, (95763, 2171993)),
-        "k_group_place": (BIN_FILES, _BIN_SHA, (131363, 381802))},
+        "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (361224, 247936)),
+        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (19680, 690602)),
+        "k_tile_place": (BIN_FILES, _BIN_SHA, (84788, 1986773)),
+        "k_group_place": (BIN_FILES, _BIN_SHA, (126579, 200512))},
     "deform-mlp-200k-x8-8x256-pe10": {
         k: (MLP_FILES, "758fb7db4681d89e83ed8c3e0ed2175bdec48243246efba660bfe0392d4a448f", kib)
         for k, kib in (("k_mlp_fwd", (219623, 7156258)), ("k_mlp_bwd", (375813, 6468750)),
