@@ -184,7 +184,8 @@ typedef struct gftorf_status {
      * cleared (by the caller, or gftorf_clear_status): e.g. across replays
      * of a captured optimisation step, whose parameters move between forwards */
     int32_t overflow_seen;   /* 1 if any of those forwards overflowed                      */
-    int32_t reserved;
+    int32_t sort_fault;      /* 1 if the last forward's depth sort gave up waiting on an
+                                earlier sort tile (its outputs are then invalid)           */
     int64_t n_pairs_seen;    /* largest pair count among them                              */
 } gftorf_status;
 
@@ -223,7 +224,10 @@ int gftorf_render_bwd(const gftorf_gaussians* g, const gftorf_frame* frames, int
                       void* ws, size_t ws_bytes, void* stream);
 
 /* Synchronises `stream`, then copies the status of the last forward that
- * used `ws` into *out (host).  Returns GFTORF_EOVERFLOW if it overflowed.
+ * used `ws` into *out (host).  Returns GFTORF_EOVERFLOW if it overflowed,
+ * GFTORF_EHIP if its depth sort gave up a wait (sort_fault; small batches
+ * sort each pass in one launch whose workgroups wait, boundedly, for the
+ * digit counts of the frame's earlier sort tiles).
  * n_evaluated / n_composited are summed here from the forward's per-tile
  * counts (zero if no forward has filled this workspace since its first 64
  * bytes were cleared). */

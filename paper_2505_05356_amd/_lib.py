@@ -66,7 +66,7 @@ class OutputsC(ctypes.Structure):
 class StatusC(ctypes.Structure):
     _fields_ = [("n_pairs", c_int64), ("max_pairs", c_int64), ("overflow", c_int32),
                 ("nonfinite", c_int32), ("n_evaluated", c_int64), ("n_composited", c_int64),
-                ("overflow_seen", c_int32), ("reserved", c_int32), ("n_pairs_seen", c_int64)]
+                ("overflow_seen", c_int32), ("sort_fault", c_int32), ("n_pairs_seen", c_int64)]
 
 
 class AdamGroupC(ctypes.Structure):

@@ -641,7 +641,8 @@ __global__ void __launch_bounds__(64 * kColWaves) k_tile_colscan(Params P, const
 __global__ void __launch_bounds__(1024) k_tile_keyscan(const uint32_t* __restrict__ tcount, long long K,
                                                        unsigned long long cap, uint2* __restrict__ ranges,
                                                        const uint32_t* __restrict__ nf_block, int n_blocks,
-                                                       unsigned long long wcount_off, Status* status) {
+                                                       unsigned long long wcount_off, const uint32_t* sort_fault,
+                                                       Status* status) {
     __shared__ unsigned long long scratch[17];
     unsigned long long carry = 0;
     // 4 consecutive tiles per thread, 4096 per round; the next round's counts
@@ -687,6 +688,7 @@ __global__ void __launch_bounds__(1024) k_tile_keyscan(const uint32_t* __restric
         status->overflow_seen |= carry > cap ? 1u : 0u;
         if (carry > status->n_pairs_seen) status->n_pairs_seen = carry;
         status->nonfinite = nf_sum;
+        status->sort_fault = sort_fault ? *sort_fault : 0u;
         status->wcount_off = wcount_off;
         status->n_items = (unsigned long long)K;
         status->magic = kStatusMagic;
@@ -805,7 +807,7 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
                            (long long)P.F * P.n_tiles, (unsigned long long)P.cap, w.ranges, w.nf_block,
                            (int)((P.n + 255) / 256),
                            (unsigned long long)(reinterpret_cast<char*>(w.wcount) - reinterpret_cast<char*>(w.status)),
-                           w.status);
+                           one_sweep_sort(P, w) ? w.sctl + kSortFault : nullptr, w.status);
     }
     {
         ProfScope _p("k_tile_place", s);

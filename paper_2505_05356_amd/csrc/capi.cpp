@@ -269,7 +269,7 @@ int gftorf_read_status(const void* ws, gftorf_status* out, void* stream) {
     out->overflow = (int32_t)st.overflow;
     out->nonfinite = (int32_t)st.nonfinite;
     out->overflow_seen = (int32_t)st.overflow_seen;
-    out->reserved = 0;
+    out->sort_fault = st.magic == gft::kStatusMagic ? (int32_t)(st.sort_fault != 0u) : 0;
     out->n_pairs_seen = (int64_t)st.n_pairs_seen;
     out->n_evaluated = out->n_composited = 0;
     // the forward's per-work-item counts, summed here (the stream is idle)
@@ -288,6 +288,7 @@ int gftorf_read_status(const void* ws, gftorf_status* out, void* stream) {
         out->n_composited = (int64_t)co;
     }
     if (st.overflow) return fail(GFTORF_EOVERFLOW, "pairs exceeded max_pairs: " + std::to_string(st.n_pairs));
+    if (out->sort_fault) return fail(GFTORF_EHIP, "depth sort: a look-back wait gave up; the forward is invalid");
     return GFTORF_OK;
 }
 

@@ -11,12 +11,21 @@ namespace gft {
 constexpr double kSpeedOfLight = 299792458.0;   // m/s
 constexpr float kLog2e = 1.4426950408889634f;
 
-// Radix sort geometry: 256 threads (4 wave64), 16 keys per thread.
+// Radix sort geometry: 256 threads (4 wave64), 8 keys per thread.
 constexpr uint32_t kCulledKey = 0xffffffffu;   // depth key of a culled item
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per tile
 constexpr int kSortBuckets = 256;                       // <= 8 digit bits per pass
+constexpr int kSortPasses = 4;                          // 32-bit keys
+// Batches of at most this many sort tiles (all frames) sort with one launch
+// per pass (decoupled look-back over the frame's earlier tiles) after one
+// histogram launch; larger batches use three launches per pass.
+constexpr int64_t kOneSweepMaxTiles = 256;
+// Words of the one-sweep control block: the next tile of each pass, then the
+// flag set when a look-back wait gave up.
+constexpr int kSortCtlWords = 8;
+constexpr int kSortFault = kSortPasses;
 
 // Tile binning works on chunks of depth-sorted items of one frame, first into
 // groups of 8x8 tiles (one LDS counter per group of a frame), then into tiles.
@@ -59,7 +68,8 @@ struct Status {
     // overflow flags and the largest pair count
     unsigned int overflow_seen;
     unsigned long long n_pairs_seen;
-    unsigned int pad[2];
+    unsigned int sort_fault;         // the last forward's depth sort gave up a look-back wait
+    unsigned int pad;
 };
 static_assert(sizeof(Status) == 64, "the status header is the workspace's first 64 bytes");
 constexpr unsigned int kStatusMagic = 0x47465352u;
@@ -93,6 +103,10 @@ struct Workspace {
     uint2* drect[2];        // [M] tile rectangles (x_lo | x_hi << 16, y_lo | y_hi << 16), sort payload
     uint32_t* counts;       // [F][256][max_sort_tiles] per-tile digit counts of the depth sort
     uint32_t* totals;       // [F][256] digit totals per frame
+    uint32_t* sctl;         // [kSortCtlWords + F * kSortPasses * 256] one-sweep control words,
+                            // then the digit counts of every frame and pass (shist)
+    uint32_t* shist;        // = sctl + kSortCtlWords
+    uint32_t* slook[2];     // [F * max_sort_tiles][256] look-back words (one-sweep batches only)
     uint32_t* cntA;         // [F][QC][ng] per-chunk group counts, then column prefixes
     uint32_t* lenA;         // [F * ng] group-list lengths
     uint2* granges;         // [F * ng] group-list ranges in gval
@@ -138,6 +152,11 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nt
     for (int i = 0; i < 2; ++i) w.drect[i] = reinterpret_cast<uint2*>(take(sizeof(uint2) * M));
     w.counts = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * kSortBuckets * w.max_sort_tiles));
     w.totals = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * kSortBuckets));
+    w.sctl = reinterpret_cast<uint32_t*>(take(4 * ((size_t)kSortCtlWords + (size_t)F * kSortPasses * kSortBuckets)));
+    w.shist = w.sctl ? w.sctl + kSortCtlWords : nullptr;
+    const int64_t sort_tiles = (int64_t)F * w.max_sort_tiles;
+    const size_t look_words = sort_tiles <= kOneSweepMaxTiles ? (size_t)sort_tiles * kSortBuckets : 0;
+    for (int i = 0; i < 2; ++i) w.slook[i] = reinterpret_cast<uint32_t*>(take(4 * look_words));
     const int64_t KG = (int64_t)F * g.ng;
     w.cntA = reinterpret_cast<uint32_t*>(take(4 * (size_t)F * g.QC * g.ng));
     w.lenA = reinterpret_cast<uint32_t*>(take(4 * KG));
@@ -184,6 +203,12 @@ void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_
                        const Workspace& w, hipStream_t s);
 int depth_sort_passes(int n_frames);
 int launch_depth_sort(const Params& P, const Workspace& w, hipStream_t s);
+// True when this batch sorts with one launch per pass (its few sort tiles
+// make the look-back chains short); the preprocess then clears the sort's
+// control words and digit counts.
+inline bool one_sweep_sort(const Params& P, const Workspace& w) {
+    return w.M > 0 && (int64_t)P.F * w.max_sort_tiles <= kOneSweepMaxTiles;
+}
 hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStream_t s);
 void launch_item_rects(const Workspace& w, int dbuf, uint2* out, hipStream_t s);
 void launch_keys_from_ranges(const Params& P, const Workspace& w, uint32_t* keys,

@@ -183,12 +183,16 @@ __global__ void __launch_bounds__(256) k_preprocess(Params P, gftorf_gaussians g
                                                     float4* __restrict__ rec, float4* __restrict__ conic,
                                                     uint2* __restrict__ rect,
                                                     uint32_t* __restrict__ cnt, uint32_t* __restrict__ dkey,
-                                                    uint32_t* __restrict__ dval, uint32_t* __restrict__ nf_block) {
+                                                    uint32_t* __restrict__ dval, uint32_t* __restrict__ nf_block,
+                                                    uint32_t* __restrict__ sclear, int64_t nclear) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const Gauss G = load_gauss(g, k < P.n ? k : 0);
     // non-finite Gaussians per block (summed by the tile-range scan)
     const int bad = __syncthreads_count(k < P.n && !G.finite);
     if (threadIdx.x == 0) nf_block[blockIdx.x] = (uint32_t)bad;
+    // the one-sweep depth sort's control words and digit counts start at 0
+    if (sclear)
+        for (int64_t i = k; i < nclear; i += (int64_t)gridDim.x * blockDim.x) sclear[i] = 0u;
     if (k >= P.n) return;
     const int RS4 = record_float4s(P.nf);
     const double o = 1.0 / (1.0 + exp(-G.logit));
@@ -664,13 +668,15 @@ void launch_preprocess(const Params& P, const gftorf_gaussians& g, const gftorf_
     const int threads = 256;
     const unsigned blocks = (unsigned)((P.n + threads - 1) / threads);
     if (blocks == 0) return;
+    uint32_t* sclear = one_sweep_sort(P, w) ? w.sctl : nullptr;
+    const int64_t nclear = kSortCtlWords + (int64_t)P.F * kSortPasses * kSortBuckets;
     { ProfScope _p("k_preprocess", s);
     if (g.sh_rgb || g.sh_albedo)
         hipLaunchKernelGGL(k_preprocess<true>, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec,
-                           w.conic, w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.nf_block);
+                           w.conic, w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.nf_block, sclear, nclear);
     else
         hipLaunchKernelGGL(k_preprocess<false>, dim3(blocks), dim3(threads), 0, s, P, g, frames, w.rec,
-                           w.conic, w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.nf_block);
+                           w.conic, w.drect[0], w.cnt, w.dkey[0], w.dval[0], w.nf_block, sclear, nclear);
     }
 }
 

@@ -194,7 +194,7 @@ class Workspace:
         return dict(n_pairs=st.n_pairs, max_pairs=st.max_pairs, overflow=bool(st.overflow),
                     nonfinite=st.nonfinite, n_evaluated=st.n_evaluated,
                     n_composited=st.n_composited, overflow_seen=bool(st.overflow_seen),
-                    n_pairs_seen=st.n_pairs_seen)
+                    n_pairs_seen=st.n_pairs_seen, sort_fault=bool(st.sort_fault))
 
     def clear_status(self, stream=None):
         """Clears the status header, including the sticky overflow_seen and

@@ -340,6 +340,44 @@ def test_depth_key_ties_bit_exact():
     np.testing.assert_array_equal(res["n_contrib"][ok], ref_img["n_contrib"][ok])
 
 
+@pytest.mark.parametrize("n,F", [(100_000, 1), (30_000, 3), (2048 * 128, 2), (2048 * 128 + 5, 2)])
+def test_depth_sort_order(n, F):
+    # Batches of at most 256 sort tiles (2048 items each) sort each pass in
+    # one launch whose tiles add the digit counts of the frame's earlier tiles
+    # by look-back; larger batches use three launches per pass.  Both sides of
+    # that line: every frame's items in ascending (depth key, index) order,
+    # keys equal to the oracle's, and a third of the Gaussians moved to one of
+    # three depths, so that runs of equal keys span several sort tiles.
+    W, H = 96, 72
+    g = scenes.draw_gaussians(n, W, H, 80.0, 80.0, seed=31)
+    rng = np.random.default_rng(32)
+    tie = rng.random(n) < 0.33
+    z_new = np.array([1.5, 2.5, 4.0], np.float32)[rng.integers(0, 3, n)]
+    s = np.where(tie, z_new.astype(np.float64) / g.mean[2].astype(np.float64), 1.0)
+    g.mean[0] = (g.mean[0] * s).astype(np.float32)
+    g.mean[1] = (g.mean[1] * s).astype(np.float32)
+    g.mean[2] = np.where(tie, z_new, g.mean[2]).astype(np.float32)
+    frames = scenes.identity_frames([0.1 * f for f in range(F)], W, H, 80.0, 80.0, 4)
+    cfg = scenes.RenderConfig(width=W, height=H)
+    res = run_gpu(g, frames, cfg, channels=("rgb",))
+    assert not res["status"]["sort_fault"] and not res["status"]["overflow"]
+    lists = gpu_lists(res, g, frames, cfg, pairs_to_host=False)
+    key = lists["depth_key"].astype(np.int64)
+    item = lists["depth_item"].astype(np.int64)
+    np.testing.assert_array_equal(np.sort(item), np.arange(n * F))
+    key_ref = np.concatenate([binning.project(g, fr, cfg, f)["key"].astype(np.int64)
+                              for f, fr in enumerate(frames)])
+    np.testing.assert_array_equal(key, key_ref[item])
+    frame_of = item // n
+    assert np.all(np.diff(frame_of) >= 0)
+    same_frame = np.diff(frame_of) == 0
+    dk, di = np.diff(key), np.diff(item)
+    assert np.all(((dk > 0) | ((dk == 0) & (di > 0)))[same_frame])
+    # runs of equal keys longer than a sort tile
+    starts = np.flatnonzero(np.concatenate([[True], (dk != 0) | ~same_frame, [True]]))
+    assert np.max(np.diff(starts)) > 2048
+
+
 @pytest.mark.parametrize("n_freq,phases", [
     (3, scenes.QUAD_PHASES), (4, scenes.QUAD_PHASES),
     (1, (0.3,)), (2, (0.0, 2 * np.pi / 3, 4 * np.pi / 3)), (4, (0.1, 2.0, 4.0))])
