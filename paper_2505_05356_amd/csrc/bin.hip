@@ -137,16 +137,20 @@ __global__ void __launch_bounds__(1024) k_group_scan(const uint32_t* __restrict_
     for (int base = 0; base < K; base += 1024) {
         const int i = base + threadIdx.x;
         const unsigned long long v = i < K ? lenA[i] : 0ull;
-        const uint32_t nsg = (uint32_t)((v + S - 1) / S);
-        const uint32_t nch = (nsg + R - 1) / R;
         unsigned long long tot;
         uint32_t stot, ctot;
         const unsigned long long ex = block_exclusive_scan<unsigned long long, 1024>(v, scratch, &tot);
+        const unsigned long long a = carry + ex, b = a + v;
+        const unsigned long long ac = a < cap ? a : cap, bc = b < cap ? b : cap;
+        // segments and chunks of the stored part of the list only (the lists
+        // are cut at the capacity), so their counts stay within the
+        // workspace's bound even when an overflowed batch has more entries
+        const uint32_t nsg = (uint32_t)((bc - ac + S - 1) / S);
+        const uint32_t nch = (nsg + R - 1) / R;
         const uint32_t sex = block_exclusive_scan<uint32_t, 1024>(nsg, scratch32, &stot);
         const uint32_t cex = block_exclusive_scan<uint32_t, 1024>(nch, scratch32, &ctot);
         if (i < K) {
-            const unsigned long long a = carry + ex, b = a + v;
-            granges[i] = make_uint2((uint32_t)(a < cap ? a : cap), (uint32_t)(b < cap ? b : cap));
+            granges[i] = make_uint2((uint32_t)ac, (uint32_t)bc);
             seg_start[i] = scarry + sex;
             chunk_start[i] = ccarry + cex;
         }
@@ -523,10 +527,9 @@ __device__ __forceinline__ void place_row(uint32_t beg, uint32_t end, uint32_t r
 // tile's list.  The 8 cursors are wave-uniform (scalar registers, the tile
 // loop unrolled), and one wave appends each tile's run over R * S entries, so
 // the runs span whole cache lines except at their two ends.
-__global__ void __launch_bounds__(64) k_tile_place(Params P, int S, int R,
-                                                   const uint32_t* __restrict__ seg_start,
+__global__ void __launch_bounds__(64) k_tile_place(Params P,
                                                    const uint32_t* __restrict__ chunk_start,
-                                                   const uint2* __restrict__ granges,
+                                                   const uint4* __restrict__ chunk_info,
                                                    const uint32_t* __restrict__ gval,
                                                    const uint16_t* __restrict__ gloc,
                                                    const uint32_t* __restrict__ cntB,
@@ -550,15 +553,13 @@ __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, int R,
     for (uint32_t wi = (uint32_t)((uint64_t)nitems * xcd / kXcds) + blockIdx.x / kXcds; wi < hi; wi += per_xcd) {
         const uint32_t ch = wi / kGroupH;
         const uint32_t r = wi - ch * kGroupH;   // tile row of the group
-        const int fg = last_le(chunk_start, K, ch);
+        const uint4 ci = chunk_info[ch];   // group, first and end entry, first segment
+        const int fg = (int)ci.x;
         const int f = fg / G.ng, gi = fg - f * G.ng;
         const uint32_t gy = gi / G.ngx, gx = gi - gy * G.ngx;
         const uint32_t ty = gy * kGroupH + r;
         if (ty >= (uint32_t)P.nty) continue;   // the row lies below the frame
-        const uint32_t b0 = seg_start[fg] + (ch - chunk_start[fg]) * (uint32_t)R;   // first segment
-        const uint2 gr = granges[fg];
-        const uint32_t beg = gr.x + (b0 - seg_start[fg]) * (uint32_t)S;
-        const uint32_t end = min(beg + (uint32_t)(R * S), gr.y);
+        const uint32_t beg = ci.y, end = ci.z, b0 = ci.w;
         // cursors of the row's tiles (lane c < 8 loads tile c's), then wave-uniform
         uint32_t cl = 0, el = 0;
         const uint32_t txl = gx * kGroupW + (uint32_t)lane;
@@ -585,9 +586,13 @@ __global__ void __launch_bounds__(64) k_tile_place(Params P, int S, int R,
 // then a prefix over the waves); per-tile totals.
 constexpr int kColWaves = 8;
 
-__global__ void __launch_bounds__(64 * kColWaves) k_tile_colscan(Params P, const uint32_t* __restrict__ seg_start,
+__global__ void __launch_bounds__(64 * kColWaves) k_tile_colscan(Params P, int S, int R,
+                                                      const uint32_t* __restrict__ seg_start,
+                                                      const uint32_t* __restrict__ chunk_start,
+                                                      const uint2* __restrict__ granges,
                                                       uint32_t* __restrict__ cntB,
-                                                      uint32_t* __restrict__ tcount) {
+                                                      uint32_t* __restrict__ tcount,
+                                                      uint4* __restrict__ chunk_info) {
     __shared__ uint32_t part[kColWaves][64];
     const Groups G = groups_of(P);
     const int fg = blockIdx.x;
@@ -596,6 +601,16 @@ __global__ void __launch_bounds__(64 * kColWaves) k_tile_colscan(Params P, const
     const uint32_t gy = gi / G.ngx, gx = gi - gy * G.ngx;
     const uint32_t tx = gx * kGroupW + lane % kGroupW, ty = gy * kGroupH + lane / kGroupW;
     const uint32_t s0 = seg_start[fg], s1 = seg_start[fg + 1];
+    {   // the group's placement chunks, so that a placing wave finds its
+        // chunk's group and entries with one load
+        const uint32_t c0 = chunk_start[fg], c1 = chunk_start[fg + 1];
+        const uint2 gr = granges[fg];
+        for (uint32_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+            const uint32_t i = c - c0;
+            const uint32_t beg = gr.x + i * (uint32_t)(R * S);
+            chunk_info[c] = make_uint4((uint32_t)fg, beg, min(beg + (uint32_t)(R * S), gr.y), s0 + i * (uint32_t)R);
+        }
+    }
     const uint32_t per = (s1 - s0 + kColWaves - 1) / kColWaves;
     const uint32_t b0 = min(s0 + wave * per, s1), b1 = min(b0 + per, s1);
     uint32_t sum = 0;
@@ -799,7 +814,8 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     {
         ProfScope _p("k_tile_colscan", s);
-        hipLaunchKernelGGL(k_tile_colscan, dim3(K), dim3(64 * kColWaves), 0, s, P, w.seg_start, w.cntB, w.tcount);
+        hipLaunchKernelGGL(k_tile_colscan, dim3(K), dim3(64 * kColWaves), 0, s, P, g.S, g.R, w.seg_start,
+                           w.chunk_start, w.granges, w.cntB, w.tcount, w.chunk_info);
     }
     {
         ProfScope _p("k_tile_keyscan", s);
@@ -811,8 +827,8 @@ hipError_t launch_binning(const Params& P, const Workspace& w, int dbuf, hipStre
     }
     {
         ProfScope _p("k_tile_place", s);
-        hipLaunchKernelGGL(k_tile_place, dim3(place_grid), dim3(64), 0, s, P, g.S, g.R, w.seg_start,
-                           w.chunk_start, w.granges, w.gval, w.gloc, w.cntB, w.ranges, w.tval);
+        hipLaunchKernelGGL(k_tile_place, dim3(place_grid), dim3(64), 0, s, P, w.chunk_start, w.chunk_info,
+                           w.gval, w.gloc, w.cntB, w.ranges, w.tval);
     }
     return hipGetLastError();
 }

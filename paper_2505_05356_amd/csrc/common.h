@@ -112,6 +112,7 @@ struct Workspace {
     uint2* granges;         // [F * ng] group-list ranges in gval
     uint32_t* seg_start;    // [F * ng + 1] first level-B segment of each group
     uint32_t* chunk_start;  // [F * ng + 1] first placement chunk (R segments) of each group
+    uint4* chunk_info;      // [max chunks] per placement chunk: group, first and end entry, first segment
     uint32_t* gval;         // [cap] item ids of the group lists
     uint16_t* gloc;         // [cap] their rectangles clipped to the group, 3 bits per bound
     uint32_t* cntB;         // [max_segments][64] per-segment tile counts, then prefixes
@@ -163,6 +164,7 @@ inline Workspace carve(void* base, int64_t n, int32_t F, int nf, int ntx, int nt
     w.granges = reinterpret_cast<uint2*>(take(sizeof(uint2) * KG));
     w.seg_start = reinterpret_cast<uint32_t*>(take(4 * (KG + 1)));
     w.chunk_start = reinterpret_cast<uint32_t*>(take(4 * (KG + 1)));
+    w.chunk_info = reinterpret_cast<uint4*>(take(sizeof(uint4) * (size_t)((g.max_segments + g.R - 1) / g.R + KG)));
     w.gval = reinterpret_cast<uint32_t*>(take(4 * cap));
     w.gloc = reinterpret_cast<uint16_t*>(take(2 * cap));
     w.cntB = reinterpret_cast<uint32_t*>(take(4 * 64 * (size_t)g.max_segments));
