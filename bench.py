@@ -54,21 +54,21 @@ FETCH_SCALE, WRITE_SCALE = 1048576 / 524318, 1048576 / 1048576   # 1 GiB copy: F
 COMPOSITE_FILES = ("paper_2505_05356_amd/csrc/composite.hip", "paper_2505_05356_amd/csrc/common.h")
 BIN_FILES = ("paper_2505_05356_amd/csrc/bin.hip", "paper_2505_05356_amd/csrc/common.h")
 MLP_FILES = ("paper_2505_05356_amd/csrc/mlp.hip", "paper_2505_05356_amd/csrc/mlp.h")
-_COMPOSITE_SHA = "00c0986837c56de4efd0f3e9aec1d2328c9cce34094f5deb57a74fd8f8b13688"
-_BIN_SHA = "de418f93f524f0c79575f4fd18061db74e9ff742c4ede0ee9ee7582038dca0bb"
+_COMPOSITE_SHA = "cd6b927c33cc7ddfef92101e8b2c3ebed96655616a2d324514a6c5f5a1bcdb0f"
+_BIN_SHA = "30381ced515e4468a2d60342f3df0e581007aa0fb0ac54ed325fcfd08fc4f716"
 # {workload: {kernel: (source files, sha256, (FETCH KiB, WRITE KiB) per launch)}};
 # k_mlp_dw counts its three launches together
 TRAFFIC = {
     "dynamic-200k-gaussians-8f-640x480": {
         "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (52202, 50919)),
-        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (5288, 96164)),
-        "k_tile_place": (BIN_FILES, _BIN_SHA, (9249, 154070)),
-        "k_group_place": (BIN_FILES, _BIN_SHA, (12841, 18420))},
+        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (5290, 96157)),
+        "k_tile_place": (BIN_FILES, _BIN_SHA, (9291, 154473)),
+        "k_group_place": (BIN_FILES, _BIN_SHA, (12834, 18412))},
     "dynamic-1000k-1024x768-16f-2freq": {
-        "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (361224, 247936)),
-        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (19680, 690602)),
-        "k_tile_place": (BIN_FILES, _BIN_SHA, (84788, 1986773)),
-        "k_group_place": (BIN_FILES, _BIN_SHA, (126579, 200512))},
+        "k_composite_bwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (361242, 247936)),
+        "k_composite_fwd": (COMPOSITE_FILES, _COMPOSITE_SHA, (19686, 691885)),
+        "k_tile_place": (BIN_FILES, _BIN_SHA, (85160, 2046582)),
+        "k_group_place": (BIN_FILES, _BIN_SHA, (126590, 198364))},
     "deform-mlp-200k-x8-8x256-pe10": {
         k: (MLP_FILES, "758fb7db4681d89e83ed8c3e0ed2175bdec48243246efba660bfe0392d4a448f", kib)
         for k, kib in (("k_mlp_fwd", (219623, 7156258)), ("k_mlp_bwd", (375813, 6468750)),
