@@ -70,9 +70,9 @@ TRAFFIC = {
         "k_tile_place": (BIN_FILES, _BIN_SHA, (85160, 2046582)),
         "k_group_place": (BIN_FILES, _BIN_SHA, (126590, 198364))},
     "deform-mlp-200k-x8-8x256-pe10": {
-        k: (MLP_FILES, "758fb7db4681d89e83ed8c3e0ed2175bdec48243246efba660bfe0392d4a448f", kib)
-        for k, kib in (("k_mlp_fwd", (219623, 7156258)), ("k_mlp_bwd", (375813, 6468750)),
-                       ("k_mlp_dw", (6575106, 275395)))},
+        k: (MLP_FILES, "38e594eb67121042452a36773f57beafc9891fcba0d2e72955acb9977e09c681", kib)
+        for k, kib in (("k_mlp_fwd", (214120, 7156260)), ("k_mlp_bwd", (368285, 6468750)),
+                       ("k_mlp_dw", (6575120, 275395)))},
 }
 
 

@@ -571,8 +571,17 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(RedArgs r, const float* __re
     } else {
         src = r.part_off[l] + (int64_t)pad_out(l) * pad_in(l) + (p - r.off_b[l]);
     }
+    // eight partials loaded at a time, added in chunk order
     float s = 0.f;
-    for (int c = 0; c < r.n_chunks; ++c) s += part[(int64_t)c * r.part_stride + src];
+    int c = 0;
+    for (; c + 8 <= r.n_chunks; c += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(c + j) * r.part_stride + src];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; c < r.n_chunks; ++c) s += part[(int64_t)c * r.part_stride + src];
     d_params[p] = s;
 }
 
