@@ -115,8 +115,8 @@ def test_select_frames_from_step_counter():
             np.testing.assert_array_equal(f[b, 17:24], table[s % n_bg, b].cpu().numpy())
 
 
-def _train_setup(seed=3, sh_degree=None):
-    wl = scenes.tiny_scene(30, 40, 32, seed=seed, dynamic=True)
+def _train_setup(seed=3, sh_degree=None, n=30):
+    wl = scenes.tiny_scene(n, 40, 32, seed=seed, dynamic=True)
     g = wl.gaussians
     g.opacity_logit[:] = np.clip(g.opacity_logit, -2.0, 1.5)
     if sh_degree is not None:
@@ -165,8 +165,11 @@ def test_train_step_matches_oracle(sh_degree):
         np.testing.assert_allclose(ts.params[k].cpu().numpy(), exp, rtol=1e-6, atol=lr * 1e-4)
 
 
-def test_graph_replay_equals_eager():
-    g, cfg, seq, tr, tq, bg = _train_setup(seed=5)
+@pytest.mark.parametrize("n", [30, 5000])
+def test_graph_replay_equals_eager(n):
+    # n = 5000: three sort tiles per frame, so the replayed one-launch sort
+    # passes wait on earlier tiles (their counters cleared inside the graph)
+    g, cfg, seq, tr, tq, bg = _train_setup(seed=5, n=n)
     eager = _make_step(g, cfg, seq, tr, tq, bg)
     graph = _make_step(g, cfg, seq, tr, tq, bg)
     graph.capture()
