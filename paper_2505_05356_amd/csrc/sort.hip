@@ -43,17 +43,21 @@ __device__ __forceinline__ SortTile sort_tile(long long g, long long n, long lon
 }
 
 // counts[(f * 256 + d) * tpf + t] = keys of digit d in tile t of frame f.
+// CP copies of each wave's histogram, lane l counting into copy l % CP: the
+// top byte of positive float depths takes few values, so its counts would
+// otherwise serialise on a few LDS addresses.
+template <int CP>
 __global__ void __launch_bounds__(kSortThreads) k_sort_upsweep(const uint32_t* __restrict__ keys, long long n,
                                                                int F, long long tpf, int shift,
                                                                uint32_t* __restrict__ counts) {
-    __shared__ uint32_t hist[4][kSortBuckets];
+    __shared__ uint32_t hist[4 * CP][kSortBuckets];
+    const int copy = (threadIdx.x / 64) * CP + (int)(threadIdx.x % CP);
     const long long ntiles = (long long)F * tpf;
-    const int wave = threadIdx.x / 64;
     // consecutive tiles write neighbouring counts of every digit row: one XCD
     const long long g0 = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     for (long long g = g0; g < ntiles; g += gridDim.x) {
         const SortTile st = sort_tile(g, n, tpf);
-        for (int i = threadIdx.x; i < 4 * kSortBuckets; i += kSortThreads) (&hist[0][0])[i] = 0;
+        for (int i = threadIdx.x; i < 4 * CP * kSortBuckets; i += kSortThreads) (&hist[0][0])[i] = 0;
         // a histogram needs no element order: each thread loads its 8 keys
         // as two 16-byte vectors where the tile is whole and 16-byte aligned,
         // all loads in flight before the first count
@@ -76,11 +80,14 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_upsweep(const uint32_t* _
 #pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
             const bool ok = vec || st.beg + it * kSortThreads + threadIdx.x < st.end;
-            if (ok) atomicAdd(&hist[wave][(kv[it] >> shift) & 0xffu], 1u);
+            if (ok) atomicAdd(&hist[copy][(kv[it] >> shift) & 0xffu], 1u);
         }
         __syncthreads();
         const int d = threadIdx.x;
-        counts[(st.f * kSortBuckets + d) * tpf + st.t] = hist[0][d] + hist[1][d] + hist[2][d] + hist[3][d];
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < 4 * CP; ++q) c += hist[q][d];
+        counts[(st.f * kSortBuckets + d) * tpf + st.t] = c;
         __syncthreads();
     }
 }
@@ -456,7 +463,11 @@ void radix_pass(const uint32_t* kin, const uint32_t* vin, const uint2* rin, uint
     const unsigned g = grid_for((long long)F * tpf, 1, 16384);
     {
         ProfScope _p("k_sort_upsweep", s);
-        hipLaunchKernelGGL(k_sort_upsweep, dim3(g), dim3(kSortThreads), 0, s, kin, n, F, tpf, shift,
+        if (shift == 24)
+            hipLaunchKernelGGL(k_sort_upsweep<4>, dim3(g), dim3(kSortThreads), 0, s, kin, n, F, tpf, shift,
+                               w.counts);
+        else
+            hipLaunchKernelGGL(k_sort_upsweep<1>, dim3(g), dim3(kSortThreads), 0, s, kin, n, F, tpf, shift,
                            w.counts);
     }
     {
