@@ -9,6 +9,8 @@ namespace gft {
 
 namespace {
 
+constexpr int kLossUnroll = 4;   // float4 loads in flight per thread and array
+
 // L2 loss (paper Eq. 9, L2 part): grad = w * 2 (p - t) / count, loss += w * sum (p - t)^2 / count.
 // Grid (chunks, frames): a workgroup takes a strided share of one frame's
 // elements, so no element index is divided; VEC: 16-byte accesses (the
@@ -31,13 +33,27 @@ __global__ void __launch_bounds__(256) k_l2_loss(const float* __restrict__ pred,
     const long long stride = (long long)gridDim.x * blockDim.x;
     if constexpr (VEC) {
         const long long n4 = elems >> 2;
-        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-            const float4 pv = reinterpret_cast<const float4*>(pf)[i];
-            const float4 tv = reinterpret_cast<const float4*>(tf)[i];
+        const float4* p4 = reinterpret_cast<const float4*>(pf);
+        const float4* t4 = reinterpret_cast<const float4*>(tf);
+        float4* g4 = reinterpret_cast<float4*>(gf);
+        const auto step = [&](const float4 pv, const float4 tv, long long i) {
             const float4 r = make_float4(pv.x - tv.x, pv.y - tv.y, pv.z - tv.z, pv.w - tv.w);
-            reinterpret_cast<float4*>(gf)[i] = make_float4(gs * r.x, gs * r.y, gs * r.z, gs * r.w);
+            g4[i] = make_float4(gs * r.x, gs * r.y, gs * r.z, gs * r.w);
             acc += (r.x * r.x + r.y * r.y) + (r.z * r.z + r.w * r.w);
+        };
+        long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        // kLossUnroll strided float4 pairs loaded before any is used.
+        for (; i + (kLossUnroll - 1) * stride < n4; i += kLossUnroll * stride) {
+            float4 pv[kLossUnroll], tv[kLossUnroll];
+#pragma unroll
+            for (int u = 0; u < kLossUnroll; ++u) {
+                pv[u] = p4[i + u * stride];
+                tv[u] = t4[i + u * stride];
+            }
+#pragma unroll
+            for (int u = 0; u < kLossUnroll; ++u) step(pv[u], tv[u], i + u * stride);
         }
+        for (; i < n4; i += stride) step(p4[i], t4[i], i);
     } else {
         for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < elems; i += stride) {
             const float r = pf[i] - tf[i];
@@ -161,7 +177,11 @@ void launch_l2_loss(const float* pred, const float* targets, const int32_t* fram
     const auto aligned = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
     const bool vec = (elems & 3) == 0 && aligned(pred) && aligned(targets) && aligned(grad);
     long long per = vec ? elems / 4 : elems;
-    long long bx = (per + 256 * 4 - 1) / (256 * 4);   // about 4 accesses per thread
+    // Vector path: about 16 accesses per thread, kLossUnroll at a time (a
+    // quarter of the workgroups, hence of the loss atomics on one word, of 4
+    // per thread); scalar path: about 4 per thread.
+    const long long per_thread = vec ? 4 * kLossUnroll : 4;
+    long long bx = (per + 256 * per_thread - 1) / (256 * per_thread);
     if (bx > 4096) bx = 4096;
     const dim3 grid((unsigned)bx, (unsigned)n_frames);
     { ProfScope _p("k_l2_loss", s);

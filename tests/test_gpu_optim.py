@@ -22,7 +22,8 @@ def _s():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-@pytest.mark.parametrize("E", [4 * 33 * 29, 3 * 33 * 29 + 1])   # 16-byte path; one-float path
+# 16-byte path; one-float path; 16-byte path over several unrolled rounds and a ragged tail
+@pytest.mark.parametrize("E", [4 * 33 * 29, 3 * 33 * 29 + 1, 4 * 300_007])
 def test_l2_loss_matches_oracle(E):
     lib = _lib.load()
     rng = np.random.default_rng(0)
